@@ -1,0 +1,128 @@
+/*
+ * CPU FP64 oracle for global registration of two surface fragments
+ * (LoopSmart, Sec. III "Fast global point cloud registration on GPU",
+ * Algorithm 1, and the robust line-process energy of Sec. IV, eqs. 2-5).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct definition that the GPU path is checked against.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  The product path never calls it and shares no code with it.
+ *
+ * Conventions
+ *  - Clouds are float32 structure-of-arrays (x, y, z, nx, ny, nz); every
+ *    computation upcasts to double first.
+ *  - Float parameters are upcast to double once: r2 = (double)r * (double)r.
+ *  - Squared distances use one pinned operation order,
+ *      dx = (double)xj - (double)xi, ...,
+ *      d2 = fma(dz, dz, fma(dy, dy, dx * dx)),
+ *    so that every radius, quadruple and inlier decision is a function of the
+ *    inputs alone.  The library is built with -ffp-contract=off.
+ *  - Index ties are broken towards the lowest index.
+ *  - Status codes: 1 accepted, 2 rejected, 3 degenerate.
+ *
+ * Parity pins (see tests/test_oracle_*.py): brute force on small inputs,
+ * closed forms (planes, spheres, scaled copies), rigid-motion invariance,
+ * recovery of a known transform, Horn/Umeyama least squares in the l == 1
+ * limit, finite differences of the alignment energy.
+ */
+#ifndef LSR_ORACLE_H
+#define LSR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_ACCEPTED = 1, ORC_REJECTED = 2, ORC_DEGENERATE = 3 };
+
+typedef struct {
+    float r_normal;          /* normal-estimation radius (m) */
+    float r_feature;         /* FPFH radius (m) */
+    float max_corr;          /* inlier / final-kernel distance delta (m) */
+    float tau;               /* polygon similarity threshold (0.9) */
+    int64_t n_trials;        /* consistency trials; <= 0 -> min(4e6, 100 N_P) */
+    double gnc_div;          /* mu divisor (1.4) */
+    int32_t gnc_every;       /* divide mu every this many iterations (4) */
+    int32_t gnc_max_iter;    /* cap on annealing iterations (256) */
+    int32_t polish_iter;     /* iterations at mu = delta^2 (32) */
+    float min_inlier_ratio;  /* accept threshold on the inlier ratio */
+    int64_t min_consistent;  /* accept threshold on |K| */
+    int32_t normal_check;    /* 1: inliers also need normal agreement */
+    float normal_cos;        /* cosine threshold of the normal check */
+    uint64_t seed;           /* consistency-filter RNG seed */
+} orc_params;
+
+typedef struct {
+    double T[16];            /* row-major 4x4, maps P into Q's frame */
+    double energy, mu_final, inlier_ratio, fitness;
+    int64_t n_valid_P, n_valid_Q, n_recip, n_consistent, n_inliers;
+    int32_t status, iters;
+} orc_result;
+
+/* ---- O1: radius neighbourhoods N_r(i) = { j : 0 < d2(i,j) <= r^2 } ---- */
+/* CSR lists sorted by index; offsets has n+1 entries.  Returns total size or
+ * -1 if cap is too small (offsets are still filled). */
+int64_t orc_neighbors_grid(const float *x, const float *y, const float *z, int64_t n,
+                           float r, int64_t *offsets, int64_t *idx, int64_t cap);
+int64_t orc_neighbors_brute(const float *x, const float *y, const float *z, int64_t n,
+                            float r, int64_t *offsets, int64_t *idx, int64_t cap);
+
+/* ---- O0: voxel downsample (optional step) ---- */
+/* Returns the number of voxels; out arrays need n entries each. */
+int64_t orc_voxel(const float *x, const float *y, const float *z,
+                  const float *nx, const float *ny, const float *nz, int64_t n, float v,
+                  float *ox, float *oy, float *oz, float *onx, float *ony, float *onz);
+
+/* ---- O2: normals (3n interleaved doubles), eigen gap and orientation ---- */
+void orc_normals(const float *x, const float *y, const float *z,
+                 const float *nx, const float *ny, const float *nz, int64_t n, float r_n,
+                 double *nrm, double *gap, double *orient, int32_t *count);
+
+/* ---- O3/O4: SPFH and FPFH (33 doubles per point) ---- */
+void orc_spfh(const float *x, const float *y, const float *z, const double *nrm, int64_t n,
+              float r_f, double *spfh, int32_t *k, int32_t *kprime, double *margin);
+void orc_fpfh(const float *x, const float *y, const float *z, const double *nrm, int64_t n,
+              float r_f, double *F, int32_t *valid, double *spfh_margin, double *desc_margin);
+
+/* ---- O5: reciprocal nearest neighbours in descriptor space ---- */
+void orc_match(const double *F, const int32_t *vF, int64_t nP,
+               const double *G, const int32_t *vG, int64_t nQ,
+               int32_t *nnQ, double *d1Q, int32_t *nn2Q, double *d2Q,
+               int32_t *nnP, double *d1P, int32_t *nn2P, double *d2P);
+/* near-tie flags of rows (P) and columns (Q) for descriptor tolerance eps */
+void orc_tie_flags(const double *F, int64_t nP, const double *G, int64_t nQ,
+                   const int32_t *nnQ, const double *d1Q, const int32_t *nn2Q, const double *d2Q,
+                   const int32_t *nnP, const double *d1P, const int32_t *nn2P, const double *d2P,
+                   double eps, uint8_t *tieP, uint8_t *tieQ);
+
+/* ---- O6: quadruple consistency filter ---- */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t n);
+int64_t orc_consistency(const float *px, const float *py, const float *pz, int64_t nP,
+                        const float *qx, const float *qy, const float *qz,
+                        const int32_t *nnQ, const uint8_t *mutual, int64_t n_trials,
+                        float tau, uint64_t seed, uint8_t *flag);
+
+/* ---- O7: graduated non-convexity robust pose ---- */
+int32_t orc_gnc(const double *p, const double *q, int64_t m, const orc_params *prm,
+                double *T, double *mu_final, double *energy, int32_t *iters);
+
+/* ---- O8: verification ---- */
+void orc_verify(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
+                const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
+                const double *T, float delta, int32_t normal_check, float normal_cos,
+                int64_t *n_inliers, double *ratio, double *fitness);
+
+/* ---- O9: robust alignment energy and its adjoint ---- */
+double orc_align_loss(const double *p, const double *q, int64_t m, const double *T, double mu,
+                      double *dp, double *dq, double *dxi);
+
+/* ---- whole pipeline ---- */
+void orc_default_params(orc_params *p);
+int32_t orc_register_pair(const float *const *P, int64_t nP, const float *const *Q, int64_t nQ,
+                          const orc_params *prm, orc_result *out,
+                          int32_t *nnQ_out, uint8_t *consistent_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
