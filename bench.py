@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of batched fragment-pair registration on one MI355X.
+
+One step = one register_batch call (HIP-graph replay) over a batch of
+fragment pairs of the indoor-room recipe at 50,000 points per fragment, every
+stage of the path (grid, normals, FPFH, reciprocal matching with the bf16
+screen, consistency filter, robust pose solve, verification) with the inputs
+already resident in HBM.  Also reported: the plain float32 per-pair path
+(register_pair in a host loop, no graph) on the same pairs, the roofline of
+the dominant kernel (the bf16 matrix-core screen) from HIP events, and the
+CPU oracle on a bounded sample.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pairs", type=int, default=256)
+    ap.add_argument("--distinct", type=int, default=64, help="distinct generated pairs, tiled to --pairs")
+    ap.add_argument("--points", type=int, default=50000)
+    ap.add_argument("--baseline-pairs", type=int, default=16)
+    ap.add_argument("--cpu-pairs", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--profile-reps", type=int, default=2)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is described, "
+              f"not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1801_01572_amd as lsr
+    import synth
+
+    lsr.lib()
+    t0 = time.time()
+    distinct = max(1, min(args.distinct, args.pairs))
+    prs = synth.make_batch(1, distinct, n_points=args.points)
+    log(f"generated {distinct} distinct pairs in {time.time() - t0:.1f}s")
+    order = [k % distinct for k in range(args.pairs)]
+    P_all = np.concatenate([prs[k].P for k in order], 1)
+    Q_all = np.concatenate([prs[k].Q for k in order], 1)
+    offP = np.concatenate([[0], np.cumsum([prs[k].P.shape[1] for k in order])]).astype(np.int64)
+    offQ = np.concatenate([[0], np.cumsum([prs[k].Q.shape[1] for k in order])]).astype(np.int64)
+    Pd = torch.from_numpy(P_all).cuda()
+    Qd = torch.from_numpy(Q_all).cuda()
+    npairs = args.pairs
+
+    prm = lsr.default_params(precision=lsr.BF16_SCREEN)
+    out = torch.empty(npairs * lsr._lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        lsr.register_batch(Pd, Qd, offP, offQ, prm, out=out, sync=False)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        lsr.register_batch(Pd, Qd, offP, offQ, prm, out=out, sync=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms_step = (t2 - t1) * 1e3 / args.steps
+    value = npairs * args.steps / (t2 - t1)
+    res = lsr._lib._parse_results(out, npairs)
+    log(f"batched bf16: {value:.1f} pairs/s ({ms_step:.2f} ms/step)")
+
+    # per-step timing of one eager run (same kernels as the graph)
+    lsr.set_timing(True)
+    lsr.get_timing()
+    stage_ms = {}
+    screen_ms = []
+    for _ in range(args.profile_reps):
+        lsr.register_batch(Pd, Qd, offP, offQ, prm, out=out, sync=False)
+        steps = lsr.get_timing()
+        for name, ms in steps:
+            stage_ms[name] = stage_ms.get(name, 0.0) + ms / args.profile_reps
+        screen_ms.append(sum(ms for name, ms in steps if name == "screen"))
+    lsr.set_timing(False)
+    scr = float(np.mean(screen_ms))
+    nPs = np.diff(offP).astype(np.float64)
+    nQs = np.diff(offQ).astype(np.float64)
+    flops = float(np.sum(2.0 * 2 * 33 * nPs * nQs))    # both directions: every point vs the other fragment
+    achieved = flops / (scr * 1e-3) / 1e12
+    traffic = None
+    tr_path = os.path.join(ROOT, "profiles", "screen_traffic.json")
+    src = open(os.path.join(ROOT, "paper_1801_01572_amd", "csrc", "match_bf16.hip"), "rb").read()
+    if os.path.exists(tr_path):
+        tr = json.load(open(tr_path))
+        if tr.get("source_sha1") == hashlib.sha1(src).hexdigest() and tr.get("pairs") == npairs \
+                and tr.get("points") == args.points:
+            traffic = tr.get("bytes_per_launch")
+    log(f"screen kernel {scr:.3f} ms/launch -> {achieved:.1f} TFLOP/s algorithmic")
+
+    # plain float32 per-pair baseline (host loop, no graph)
+    base = None
+    if not args.no_baseline:
+        nb = min(args.baseline_pairs, npairs)
+        prm32 = lsr.default_params(precision=lsr.FP32)
+        views = [(Pd[:, offP[k]:offP[k + 1]], Qd[:, offQ[k]:offQ[k + 1]]) for k in range(nb)]
+        bout = torch.empty(lsr._lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        for p, q in views:
+            lsr.register_pair(p, q, prm32, out=bout, sync=False)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for p, q in views:
+            lsr.register_pair(p, q, prm32, out=bout, sync=False)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        base = nb / (t4 - t3)
+        log(f"plain fp32 per-pair: {base:.1f} pairs/s")
+
+    cpu = None
+    if not args.no_cpu and args.cpu_pairs > 0:
+        import oracle
+        k = min(args.cpu_pairs, distinct)
+        t5 = time.perf_counter()
+        for j in range(k):
+            oracle.register_pair(prs[j].P, prs[j].Q)
+        t6 = time.perf_counter()
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        cpu = {"value": k / (t6 - t5), "unit": "fragment pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{k} of the benchmark's 50k/50k pairs, full pipeline, FP64, {threads} OpenMP threads"}
+        log(f"cpu oracle: {cpu['value']:.4f} pairs/s")
+
+    acc = float(np.mean([r["status"] == lsr.ACCEPTED for r in res]))
+    fb = int(sum(r["n_fallback_rows"] for r in res))
+    line = {
+        "metric": "fragment-pair registrations/s at 50k pts/frag, batched BF16 vs plain FP32",
+        "value": round(value, 3),
+        "unit": "fragment pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"indoor-room pairs, {args.points}/{args.points} pts per fragment, "
+                               f"batch of {npairs} ({distinct} distinct, tiled), one graph replay per step",
+                   "pairs": npairs, "points_per_fragment": args.points, "precision": "bf16 screen + fp32 re-rank",
+                   "parallelism": "single GPU"},
+        "plain_fp32_pairs_per_s": None if base is None else round(base, 3),
+        "speedup_vs_plain_fp32": None if base is None else round(value / base, 3),
+        "roofline": {"bound": "mfma", "kernel": "k_screen", "achieved": round(achieved, 2),
+                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                     "traffic": traffic, "ms_per_launch": round(scr, 4), "flops_per_launch": flops},
+        "cpu_baseline": cpu,
+        "stages_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "accepted_fraction": round(acc, 4),
+        "bf16_fallback_rows": fb,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

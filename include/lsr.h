@@ -1,0 +1,219 @@
+/*
+ * lsr: global registration of two surface fragments on MI355X (gfx950).
+ *
+ * Problem (LoopSmart, Sec. III): given two fragments P and Q, each a set of
+ * points with normals, return the rigid transform T_QP that aligns P to Q
+ * (q ~ R p + t) if they can be aligned, starting from T_QP = I (Algorithm 1).
+ * The path: radius neighbourhoods on a 3-D grid (Sec. III, eq. 1) ->
+ * normals -> FPFH descriptors (the descriptor Algorithm 1 computes) ->
+ * reciprocal nearest neighbours in descriptor space (Algorithm 1's
+ * pre-matching cache, both directions) -> quadruple edge-ratio consistency
+ * (Algorithm 1's pre-rejection, tau = 0.9) -> robust pose by graduated
+ * non-convexity on the line-process energy of Sec. IV (eqs. 2-5: 6x6 normal
+ * equations with G = [-[p]x | I], solved in FP64) -> verification by inlier
+ * ratio and fitness on the grid (Algorithm 1's hypothesis test) ->
+ * accepted / rejected.
+ *
+ * Memory and streams
+ *  - Every pointer argument marked "device" is GPU memory owned by the
+ *    caller; "host" pointers are read before the call returns.
+ *  - Clouds are float32 structure-of-arrays: six arrays x, y, z, nx, ny, nz
+ *    of n entries each.  Normals are the fragment's input normals (used to
+ *    orient the estimated normals).
+ *  - All calls enqueue work on `stream` (a hipStream_t; NULL means the
+ *    default stream) and return without waiting.  Outputs are valid once the
+ *    caller synchronises the stream.
+ *  - The context owns all scratch memory.  Scratch grows on demand outside
+ *    stream capture; while the stream is being captured it never allocates.
+ *  - One context may be used from one host thread at a time.
+ *
+ * Errors: every int-returning call returns LSR_OK (0) or a negative code.
+ * LSR_EINVAL: a null pointer, a size out of range, a non-finite parameter;
+ * LSR_ENOMEM: scratch cannot be allocated (or would have to be during
+ * capture); LSR_EHIP: a HIP runtime error.  lsr_last_error() describes the
+ * last failure.  A pair that cannot be aligned is not an error: its result
+ * has status LSR_REJECTED or LSR_DEGENERATE.
+ */
+#ifndef LSR_H
+#define LSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSR_OK        0
+#define LSR_EINVAL   (-1)
+#define LSR_ENOMEM   (-2)
+#define LSR_EHIP     (-3)
+
+#define LSR_ACCEPTED   1
+#define LSR_REJECTED   2
+#define LSR_DEGENERATE 3
+
+/* descriptor matching arithmetic */
+#define LSR_FP32        0   /* exact float32 difference-form scan */
+#define LSR_BF16_SCREEN 1   /* bf16 matrix-core screen, certified float32 re-rank */
+
+typedef struct lsr_ctx lsr_ctx;
+
+typedef struct {
+    const float *x, *y, *z;      /* device, n entries each */
+    const float *nx, *ny, *nz;   /* device, input normals */
+    int64_t n;
+} lsr_cloud;
+
+typedef struct {
+    float r_normal;          /* normal-estimation radius, m (Sec. III uses 2x the leaf) */
+    float r_feature;         /* FPFH radius, m (Sec. III uses 5x the leaf) */
+    float max_corr;          /* inlier distance delta and final kernel scale, m */
+    float tau;               /* polygon similarity threshold (Sec. III: 0.9) */
+    int64_t n_trials;        /* consistency trials per pair; <= 0: min(4e6, 100 N_P) */
+    double gnc_div;          /* mu divisor of the non-convexity schedule */
+    int32_t gnc_every;       /* iterations per mu step */
+    int32_t gnc_max_iter;    /* cap on annealing iterations */
+    int32_t polish_iter;     /* iterations at mu = max_corr^2 */
+    float min_inlier_ratio;  /* acceptance: inliers / N_P */
+    int64_t min_consistent;  /* acceptance: minimum consistent correspondences */
+    int32_t normal_check;    /* 1: an inlier also needs normal agreement */
+    float normal_cos;        /* cosine threshold of the normal check */
+    int32_t precision;       /* LSR_FP32 or LSR_BF16_SCREEN */
+    uint64_t seed;           /* consistency-trial generator seed */
+} lsr_params;
+
+typedef struct {
+    double T[16];            /* row-major 4x4, maps P into Q's frame */
+    double energy;           /* robust energy at the returned pose, mu = mu_final */
+    double mu_final;
+    double inlier_ratio;     /* inliers / N_P */
+    double fitness;          /* RMS distance of inliers */
+    int64_t n_valid_P, n_valid_Q;   /* points with a valid descriptor */
+    int64_t n_recip;         /* reciprocal correspondences */
+    int64_t n_consistent;    /* correspondences kept by the consistency filter */
+    int64_t n_inliers;
+    int64_t n_fallback_rows; /* bf16 screen rows re-scanned exactly */
+    int32_t status;          /* LSR_ACCEPTED / LSR_REJECTED / LSR_DEGENERATE */
+    int32_t iters;           /* pose iterations run */
+} lsr_result;
+
+/* Context for one device.  Returns LSR_OK and *ctx, or an error. */
+int lsr_create(lsr_ctx **ctx, int device);
+void lsr_destroy(lsr_ctx *ctx);
+/* Text of the last error on this context (never NULL). */
+const char *lsr_last_error(const lsr_ctx *ctx);
+/* Defaults: r_normal 0.025, r_feature 0.05, max_corr 0.015, tau 0.9,
+ * n_trials auto, gnc_div 1.4, gnc_every 4, gnc_max_iter 256, polish_iter 32,
+ * min_inlier_ratio 0.15, min_consistent 10, normal check off (cos 30 deg),
+ * precision LSR_FP32. */
+void lsr_default_params(lsr_params *p);
+
+/*
+ * Register one fragment pair (Algorithm 1 and Sec. III's problem
+ * statement).  P and Q: device clouds with n >= 1 points.  d_out: device
+ * pointer to one lsr_result.  Deterministic: the same inputs give the same
+ * bits.
+ */
+int lsr_register_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q,
+                      const lsr_params *prm, lsr_result *d_out, void *stream);
+
+/*
+ * Register n_pairs fragment pairs of uneven sizes in one batched launch
+ * sequence (captured once into a HIP graph and replayed while the inputs'
+ * addresses and sizes are unchanged).  P_all / Q_all: device clouds holding
+ * every pair's fragment back to back; pair b's P is entries
+ * [offP[b], offP[b+1]) of P_all, its Q is [offQ[b], offQ[b+1]) of Q_all.
+ * offP, offQ: host arrays of n_pairs + 1 non-decreasing offsets.
+ * d_out: device array of n_pairs results.  Result b equals what
+ * lsr_register_pair returns for pair b alone.
+ */
+int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all,
+                       const int64_t *offP, const int64_t *offQ, int32_t n_pairs,
+                       const lsr_params *prm, lsr_result *d_out, void *stream);
+
+/*
+ * Robust alignment energy (eq. 2 with l eliminated, Psi of eq. 4):
+ *   E = sum_c mu s_c / (mu + s_c),  s_c = |R p_c + t - q_c|^2,
+ * for n_problems independent problems.  Problem k uses correspondences
+ * [coff[k], coff[k+1]) of d_corr (device int32 pairs (i, j): P index, Q
+ * index into P_xyz / Q_xyz, device float32 SoA x, y, z of nP / nQ points;
+ * a pair with an index out of range contributes nothing), pose d_T[16 k ...]
+ * (device, row-major 4x4 doubles) and d_mu[k] (device).  Writes d_E[k]
+ * (device doubles).  coff: host array of n_problems + 1 offsets.
+ */
+int lsr_align_loss(lsr_ctx *ctx, const float *const P_xyz[3], int64_t nP,
+                   const float *const Q_xyz[3], int64_t nQ, const int32_t *d_corr, const int64_t *coff, int32_t n_problems,
+                   const double *d_T, const double *d_mu, double *d_E, void *stream);
+
+/*
+ * Adjoint of lsr_align_loss, scaled by d_dE[k] (device doubles).  The weights
+ * l_c = (mu/(mu+s_c))^2 are recomputed, not stored.
+ *   dP[i] += dE 2 l_c R^T r_c, dQ[j] += -dE 2 l_c r_c     (float32, device SoA, caller zeroes)
+ *   d_dxi[6 k ...] = dE sum_c 2 l_c [p'_c x r_c ; r_c]     (left se(3) perturbation
+ *                                                          T <- Exp(xi) T, xi = (omega, v))
+ * Points repeated across correspondences accumulate by atomic addition.
+ */
+int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t nP,
+                            const float *const Q_xyz[3], int64_t nQ, const int32_t *d_corr, const int64_t *coff, int32_t n_problems,
+                            const double *d_T, const double *d_mu, const double *d_dE,
+                            float *const dP_xyz[3], float *const dQ_xyz[3], double *d_dxi,
+                            void *stream);
+
+/* ---- stage entry points: one stage on injected inputs (parity checks) ---- */
+
+/* Normals (n x 3 doubles, row-major, device) of one cloud; PCA over the
+ * radius-r_normal neighbourhood plus the point, oriented by the input normal. */
+int lsr_stage_normals(lsr_ctx *ctx, const lsr_cloud *c, float r_normal, double *d_nrm, void *stream);
+
+/* FPFH (n x 33 floats, device) and validity (n int32) of one cloud given its
+ * normals (n x 3 doubles, device). */
+int lsr_stage_fpfh(lsr_ctx *ctx, const lsr_cloud *c, const double *d_nrm, float r_feature,
+                   float *d_F, int32_t *d_valid, void *stream);
+
+/* Nearest neighbours in descriptor space, both directions: d_nnQ[i] (nP int32)
+ * is the index of the closest valid G row to F row i (-1 if F_i is invalid),
+ * d_dQ[i] its float32 squared distance; d_nnP / d_dP likewise for G rows.
+ * F: nP x 33, G: nQ x 33 floats; vF / vG: validity.  Ties go to the lowest
+ * index.  d_fallback (device int64, may be NULL) receives the number of rows
+ * the bf16 screen re-scanned exactly. */
+int lsr_stage_match(lsr_ctx *ctx, const float *d_F, const int32_t *d_vF, int64_t nP,
+                    const float *d_G, const int32_t *d_vG, int64_t nQ, int32_t precision,
+                    int32_t *d_nnQ, float *d_dQ, int32_t *d_nnP, float *d_dP,
+                    int64_t *d_fallback, void *stream);
+
+/* Consistency filter on given correspondences: d_nnQ (nP int32), d_mutual
+ * (nP uint8); writes d_flag (nP uint8) and d_passed (one int64: passing
+ * trials).  n_trials <= 0 means min(4e6, 100 nP). */
+int lsr_stage_consistency(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q,
+                          const int32_t *d_nnQ, const uint8_t *d_mutual, int64_t n_trials,
+                          float tau, uint64_t seed, uint8_t *d_flag, int64_t *d_passed, void *stream);
+
+/* Robust pose from m correspondences (device m x 3 doubles p and q).
+ * Writes d_T (16 doubles) and d_info = {status, iters, mu_final, energy} as
+ * doubles. */
+int lsr_stage_gnc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m,
+                  const lsr_params *prm, double *d_T, double *d_info, void *stream);
+
+/* Verification of pose d_T (device 16 doubles): d_info = {n_inliers, ratio,
+ * fitness} as doubles.  Normals (device n x 3 doubles) may be NULL when the
+ * normal check is off. */
+int lsr_stage_verify(lsr_ctx *ctx, const lsr_cloud *P, const double *d_nrmP,
+                     const lsr_cloud *Q, const double *d_nrmQ, const double *d_T,
+                     float delta, int32_t normal_check, float normal_cos,
+                     double *d_info, void *stream);
+
+/* ---- diagnostics ---- */
+
+/* enable != 0: every following register call runs eagerly (no graph) and
+ * records a HIP event on its stream after each step.  Resets the record. */
+int lsr_set_timing(lsr_ctx *ctx, int enable);
+/* Waits for the device, then returns the steps recorded since the last
+ * call: names (host, max_steps x 32 chars, may be NULL) and durations ms
+ * (host, may be NULL) of step k = time from step k-1's event to its own. */
+int lsr_get_timing(lsr_ctx *ctx, int max_steps, char *names, double *ms, int *n_steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,15 @@
+"""MI355X-native global registration of surface fragments (LoopSmart, Sec. III).
+
+Thin Python binding of the C ABI in ``include/lsr.h`` (``liblsr.so``, HIP for
+gfx950).  Argument marshalling only: every step of the path runs in the HIP
+kernels.  PyTorch provides device memory and the current stream.
+
+A cloud is a float32 CUDA tensor of shape (6, N): rows x, y, z, nx, ny, nz.
+"""
+from ._lib import (  # noqa: F401
+    ACCEPTED, REJECTED, DEGENERATE, FP32, BF16_SCREEN,
+    Params, Result, LsrError, lib, default_params, Context, get_context,
+    register_pair, register_batch, align_loss, align_loss_backward, set_timing, get_timing,
+    stage_normals, stage_fpfh, stage_match, stage_consistency, stage_gnc, stage_verify,
+)
+from .autograd import AlignLoss  # noqa: F401

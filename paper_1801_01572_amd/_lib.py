@@ -1,0 +1,304 @@
+"""ctypes view of liblsr.so.  Fails loudly when the HIP library is missing."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsr.so")
+
+ACCEPTED, REJECTED, DEGENERATE = 1, 2, 3
+FP32, BF16_SCREEN = 0, 1
+
+_LIB = None
+_CTX = {}
+
+
+class LsrError(RuntimeError):
+    pass
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("r_normal", C.c_float), ("r_feature", C.c_float), ("max_corr", C.c_float), ("tau", C.c_float),
+        ("n_trials", C.c_int64), ("gnc_div", C.c_double), ("gnc_every", C.c_int32),
+        ("gnc_max_iter", C.c_int32), ("polish_iter", C.c_int32), ("min_inlier_ratio", C.c_float),
+        ("min_consistent", C.c_int64), ("normal_check", C.c_int32), ("normal_cos", C.c_float),
+        ("precision", C.c_int32), ("seed", C.c_uint64),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("T", C.c_double * 16), ("energy", C.c_double), ("mu_final", C.c_double),
+        ("inlier_ratio", C.c_double), ("fitness", C.c_double),
+        ("n_valid_P", C.c_int64), ("n_valid_Q", C.c_int64), ("n_recip", C.c_int64),
+        ("n_consistent", C.c_int64), ("n_inliers", C.c_int64), ("n_fallback_rows", C.c_int64),
+        ("status", C.c_int32), ("iters", C.c_int32),
+    ]
+
+
+class Cloud(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("nx", C.c_void_p), ("ny", C.c_void_p), ("nz", C.c_void_p), ("n", C.c_int64)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise LsrError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.lsr_create.argtypes = [C.POINTER(vp), C.c_int]
+        L.lsr_destroy.argtypes = [vp]
+        L.lsr_last_error.argtypes = [vp]
+        L.lsr_last_error.restype = C.c_char_p
+        L.lsr_default_params.argtypes = [C.POINTER(Params)]
+        L.lsr_register_pair.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), C.POINTER(Params), vp, vp]
+        L.lsr_register_batch.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32,
+                                         C.POINTER(Params), vp, vp]
+        L.lsr_align_loss.argtypes = [vp, vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, vp]
+        L.lsr_align_loss_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.lsr_stage_normals.argtypes = [vp, C.POINTER(Cloud), C.c_float, vp, vp]
+        L.lsr_stage_fpfh.argtypes = [vp, C.POINTER(Cloud), vp, C.c_float, vp, vp, vp]
+        L.lsr_stage_match.argtypes = [vp, vp, vp, i64, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp]
+        L.lsr_stage_consistency.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i64, C.c_float,
+                                            C.c_uint64, vp, vp, vp]
+        L.lsr_stage_gnc.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, vp, vp]
+        L.lsr_stage_verify.argtypes = [vp, C.POINTER(Cloud), vp, C.POINTER(Cloud), vp, vp, C.c_float, i32,
+                                       C.c_float, vp, vp]
+        L.lsr_set_timing.argtypes = [vp, C.c_int]
+        L.lsr_get_timing.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
+        for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch", "lsr_align_loss",
+                  "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_match",
+                  "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify"):
+            getattr(L, f).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().lsr_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """One lsr_ctx on one device (owns the library's scratch memory)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        rc = lib().lsr_create(C.byref(h), int(device))
+        if rc != 0:
+            raise LsrError(f"lsr_create({device}) failed with {rc}")
+        self.h = h
+        self.device = device
+
+    def check(self, rc):
+        if rc != 0:
+            raise LsrError(f"liblsr error {rc}: {lib().lsr_last_error(self.h).decode()}")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.lsr_destroy(self.h)
+            self.h = None
+
+
+def get_context(device=None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _CTX:
+        _CTX[dev] = Context(dev)
+    return _CTX[dev]
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _cloud(t: torch.Tensor, normals=True) -> Cloud:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[0] in (3, 6)
+            and t.is_contiguous()):
+        raise LsrError("a cloud must be a contiguous CUDA float32 tensor of shape (6, N) or (3, N)")
+    if normals and t.shape[0] != 6:
+        raise LsrError("this call needs input normals: shape (6, N)")
+    n = t.shape[1]
+    rows = [C.c_void_p(t[k].data_ptr() if n else 0) for k in range(t.shape[0])]
+    rows += [C.c_void_p(0)] * (6 - len(rows))
+    return Cloud(*rows, n)
+
+
+RESULT_BYTES = C.sizeof(Result)
+
+
+def _parse_results(buf: torch.Tensor, n: int):
+    raw = buf.cpu().numpy().tobytes()
+    out = []
+    for k in range(n):
+        r = Result.from_buffer_copy(raw[k * RESULT_BYTES:(k + 1) * RESULT_BYTES])
+        d = {name: getattr(r, name) for name, _ in Result._fields_ if name != "T"}
+        d["T"] = np.array(r.T[:]).reshape(4, 4)
+        out.append(d)
+    return out
+
+
+def register_pair(P: torch.Tensor, Q: torch.Tensor, params: Params | None = None, ctx: Context | None = None,
+                  out: torch.Tensor | None = None, sync: bool = True):
+    """Register one pair.  Returns a dict (after a stream sync) or, with
+    sync=False, the raw device result buffer."""
+    ctx = ctx or get_context(P.device.index)
+    prm = params or default_params()
+    cp, cq = _cloud(P), _cloud(Q)
+    if out is None:
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=P.device)
+    ctx.check(lib().lsr_register_pair(ctx.h, C.byref(cp), C.byref(cq), C.byref(prm), _ptr(out), _stream()))
+    return _parse_results(out, 1)[0] if sync else out
+
+
+def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params: Params | None = None,
+                   ctx: Context | None = None, out: torch.Tensor | None = None, sync: bool = True):
+    """Register len(offP) - 1 pairs: pair b's P is columns offP[b]:offP[b+1] of P_all."""
+    ctx = ctx or get_context(P_all.device.index)
+    prm = params or default_params()
+    offP = np.ascontiguousarray(offP, np.int64)
+    offQ = np.ascontiguousarray(offQ, np.int64)
+    n = len(offP) - 1
+    if len(offQ) != n + 1:
+        raise LsrError("offP and offQ must have the same length")
+    cp, cq = _cloud(P_all), _cloud(Q_all)
+    if out is None:
+        out = torch.empty(max(n, 1) * RESULT_BYTES, dtype=torch.uint8, device=P_all.device)
+    ctx.check(lib().lsr_register_batch(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
+                                       offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), _ptr(out), _stream()))
+    return _parse_results(out, n) if sync else out
+
+
+def _xyz_ptrs(t):
+    arr = (C.c_void_p * 3)(*[t[k].data_ptr() for k in range(3)])
+    return arr
+
+
+def align_loss(P_xyz, Q_xyz, corr, coff, T, mu, ctx=None):
+    """E[k] for each problem k (see lsr_align_loss).  T: (n,4,4) float64, mu: (n,) float64."""
+    ctx = ctx or get_context(P_xyz.device.index)
+    coff = np.ascontiguousarray(coff, np.int64)
+    n = len(coff) - 1
+    E = torch.empty(n, dtype=torch.float64, device=P_xyz.device)
+    T = T.contiguous()
+    mu = mu.contiguous()
+    ctx.check(lib().lsr_align_loss(ctx.h, _xyz_ptrs(P_xyz), P_xyz.shape[1], _xyz_ptrs(Q_xyz), Q_xyz.shape[1],
+                                   _ptr(corr),
+                                   coff.ctypes.data_as(C.c_void_p), n, _ptr(T), _ptr(mu), _ptr(E), _stream()))
+    return E
+
+
+def align_loss_backward(P_xyz, Q_xyz, corr, coff, T, mu, dE, ctx=None):
+    """(dP (3,NP) f32, dQ (3,NQ) f32, dxi (n,6) f64) scaled by dE (n,)."""
+    ctx = ctx or get_context(P_xyz.device.index)
+    coff = np.ascontiguousarray(coff, np.int64)
+    n = len(coff) - 1
+    dP = torch.zeros((3, P_xyz.shape[1]), dtype=torch.float32, device=P_xyz.device)
+    dQ = torch.zeros((3, Q_xyz.shape[1]), dtype=torch.float32, device=P_xyz.device)
+    dxi = torch.empty((n, 6), dtype=torch.float64, device=P_xyz.device)
+    ctx.check(lib().lsr_align_loss_backward(ctx.h, _xyz_ptrs(P_xyz), P_xyz.shape[1], _xyz_ptrs(Q_xyz),
+                                            Q_xyz.shape[1], _ptr(corr),
+                                            coff.ctypes.data_as(C.c_void_p), n, _ptr(T.contiguous()),
+                                            _ptr(mu.contiguous()), _ptr(dE.contiguous()), _xyz_ptrs(dP),
+                                            _xyz_ptrs(dQ), _ptr(dxi), _stream()))
+    return dP, dQ, dxi
+
+
+def set_timing(enable: bool, ctx: Context | None = None):
+    ctx = ctx or get_context()
+    ctx.check(lib().lsr_set_timing(ctx.h, int(bool(enable))))
+
+
+def get_timing(ctx: Context | None = None):
+    """[(step name, ms), ...] recorded since the last call (syncs the device)."""
+    ctx = ctx or get_context()
+    mx = 4096
+    names = C.create_string_buffer(32 * mx)
+    ms = (C.c_double * mx)()
+    n = C.c_int()
+    ctx.check(lib().lsr_get_timing(ctx.h, mx, names, ms, C.byref(n)))
+    raw = names.raw
+    return [(raw[32 * k:32 * k + 32].split(b"\0")[0].decode(), ms[k]) for k in range(n.value)]
+
+
+# ---- stage entry points --------------------------------------------------------------------
+
+def stage_normals(cloud, r_normal, ctx=None):
+    ctx = ctx or get_context(cloud.device.index)
+    out = torch.empty((cloud.shape[1], 3), dtype=torch.float64, device=cloud.device)
+    c = _cloud(cloud)
+    ctx.check(lib().lsr_stage_normals(ctx.h, C.byref(c), C.c_float(r_normal), _ptr(out), _stream()))
+    return out
+
+
+def stage_fpfh(xyz, nrm, r_feature, ctx=None):
+    ctx = ctx or get_context(xyz.device.index)
+    n = xyz.shape[1]
+    F = torch.empty((n, 33), dtype=torch.float32, device=xyz.device)
+    v = torch.empty(n, dtype=torch.int32, device=xyz.device)
+    c = _cloud(xyz[:3].contiguous() if xyz.shape[0] == 6 else xyz, normals=False)
+    ctx.check(lib().lsr_stage_fpfh(ctx.h, C.byref(c), _ptr(nrm.contiguous()), C.c_float(r_feature), _ptr(F),
+                                   _ptr(v), _stream()))
+    return F, v
+
+
+def stage_match(F, vF, G, vG, precision=FP32, ctx=None):
+    ctx = ctx or get_context(F.device.index)
+    nP, nQ = F.shape[0], G.shape[0]
+    dev = F.device
+    nnQ = torch.empty(nP, dtype=torch.int32, device=dev)
+    dQ = torch.empty(nP, dtype=torch.float32, device=dev)
+    nnP = torch.empty(nQ, dtype=torch.int32, device=dev)
+    dP = torch.empty(nQ, dtype=torch.float32, device=dev)
+    fb = torch.zeros(1, dtype=torch.int64, device=dev)
+    ctx.check(lib().lsr_stage_match(ctx.h, _ptr(F.contiguous()), _ptr(vF.contiguous()), nP, _ptr(G.contiguous()),
+                                    _ptr(vG.contiguous()), nQ, int(precision), _ptr(nnQ), _ptr(dQ), _ptr(nnP),
+                                    _ptr(dP), _ptr(fb), _stream()))
+    return nnQ, dQ, nnP, dP, fb
+
+
+def stage_consistency(P, Q, nnQ, mutual, n_trials, tau, seed, ctx=None):
+    ctx = ctx or get_context(P.device.index)
+    flag = torch.empty(P.shape[1], dtype=torch.uint8, device=P.device)
+    passed = torch.zeros(1, dtype=torch.int64, device=P.device)
+    cp, cq = _cloud(P, normals=False), _cloud(Q, normals=False)
+    ctx.check(lib().lsr_stage_consistency(ctx.h, C.byref(cp), C.byref(cq), _ptr(nnQ.contiguous()),
+                                          _ptr(mutual.contiguous()), int(n_trials), C.c_float(tau),
+                                          C.c_uint64(seed), _ptr(flag), _ptr(passed), _stream()))
+    return flag, passed
+
+
+def stage_gnc(p, q, params=None, ctx=None):
+    """p, q: (m,3) float64 CUDA tensors -> (T (4,4), info {status, iters, mu_final, energy})."""
+    ctx = ctx or get_context(p.device.index)
+    prm = params or default_params()
+    T = torch.empty(16, dtype=torch.float64, device=p.device)
+    info = torch.empty(4, dtype=torch.float64, device=p.device)
+    ctx.check(lib().lsr_stage_gnc(ctx.h, _ptr(p.contiguous()), _ptr(q.contiguous()), p.shape[0], C.byref(prm),
+                                  _ptr(T), _ptr(info), _stream()))
+    return T.view(4, 4), info
+
+
+def stage_verify(P, nrmP, Q, nrmQ, T, delta, normal_check=0, normal_cos=0.8660254, ctx=None):
+    ctx = ctx or get_context(P.device.index)
+    info = torch.empty(3, dtype=torch.float64, device=P.device)
+    cp, cq = _cloud(P, normals=False), _cloud(Q, normals=False)
+    ctx.check(lib().lsr_stage_verify(ctx.h, C.byref(cp), _ptr(nrmP), C.byref(cq), _ptr(nrmQ),
+                                     _ptr(T.contiguous()), C.c_float(delta), int(normal_check),
+                                     C.c_float(normal_cos), _ptr(info), _stream()))
+    return info

@@ -1,0 +1,778 @@
+// Host runtime behind the C ABI of include/lsr.h.
+//
+// A call is turned into a plan: the batch's fragment table, block tables,
+// consistency-trial table and every scratch array, all in one device
+// allocation owned by the plan.  Plans are cached by the call's signature
+// (kind, sizes, input/output addresses, parameters), so repeated calls reuse
+// their memory and never allocate; a batch plan additionally keeps the HIP
+// graph of its launch sequence and replays it.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "lsr_internal.h"
+#include "match_common.h"
+
+namespace lsr {
+int trials_per_block();
+int64_t align_blocks(const int64_t *coff, int nprob, void *host_tab, int64_t *pblk);
+size_t align_block_bytes();
+hipError_t launch_align(bool bwd, const float *const P[3], int64_t nP, const float *const Q[3], int64_t nQ,
+                        const int32_t *corr,
+                        const void *dev_tab, int64_t nblocks, const int64_t *dev_pblk, int nprob, const double *T,
+                        const double *mu, const double *dE, double *partial, double *out, float *const dP[3],
+                        float *const dQ[3], hipStream_t s);
+hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch,
+                             hipStream_t s);
+size_t match_bf16_scratch(const GridBufs &g, int64_t pk_rows);
+}  // namespace lsr
+
+using namespace lsr;
+
+namespace {
+
+enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN };
+
+struct FragIn {
+    const float *src[6];
+    int64_t n;
+};
+
+struct Plan {
+    std::vector<char> key;
+    char *dmem = nullptr;
+    size_t dbytes = 0;
+    char *hmem = nullptr;          // pinned host copy of the tables
+    size_t hbytes = 0;
+    GridBufs g{};
+    DescBufs d{};
+    MatchBufs m{};
+    PairState *ps = nullptr;
+    int npairs = 0;
+    TrialBlk *tb = nullptr;
+    int ntb = 0;
+    int32_t *scan_tmp = nullptr;
+    double *nrm_orig = nullptr;    // stage calls: normals in original order (3 per point)
+    int64_t *cnt64 = nullptr;      // small device scalars for stage outputs
+    void *mscratch = nullptr;      // matcher scratch
+    int64_t pk_rows = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    // align-loss tables
+    void *atab = nullptr;
+    int64_t *apblk = nullptr;
+    double *apart = nullptr;
+    int64_t anblk = 0;
+    ~Plan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (dmem) (void)hipFree(dmem);
+        if (hmem) (void)hipHostFree(hmem);
+    }
+};
+
+struct Layout {                    // sizes of one plan's buffers, in allocation order
+    std::vector<size_t> sz;
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = (total + 255) & ~size_t(255);
+        sz.push_back(off);
+        total = off + bytes;
+        return off;
+    }
+};
+
+}  // namespace
+
+namespace lsr {
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<std::string> names;
+    size_t used = 0;
+};
+static Timing g_timing;
+void tmark(const char *name, hipStream_t s) {
+    Timing &T = g_timing;
+    if (!T.on) return;
+    if (T.used == T.ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        T.ev.push_back(e);
+        T.names.push_back("");
+    }
+    T.names[T.used] = name;
+    (void)hipEventRecord(T.ev[T.used], s);
+    ++T.used;
+}
+}  // namespace lsr
+
+struct lsr_ctx {
+    int device = 0;
+    std::string err = "no error";
+    std::vector<std::unique_ptr<Plan>> plans;   // most recently used last
+};
+
+namespace {
+
+constexpr size_t MAX_PLANS = 48;
+
+int fail(lsr_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(ctx, LSR_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+void put(std::vector<char> &k, const T &v) {
+    const char *p = reinterpret_cast<const char *>(&v);
+    k.insert(k.end(), p, p + sizeof(T));
+}
+
+Plan *find_plan(lsr_ctx *c, const std::vector<char> &key) {
+    for (size_t i = 0; i < c->plans.size(); ++i)
+        if (c->plans[i]->key == key) {
+            std::unique_ptr<Plan> p = std::move(c->plans[i]);
+            c->plans.erase(c->plans.begin() + i);
+            c->plans.push_back(std::move(p));
+            return c->plans.back().get();
+        }
+    return nullptr;
+}
+
+bool capturing(hipStream_t s) {
+    if (!s) return false;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+int add_plan(lsr_ctx *c, std::unique_ptr<Plan> p, Plan **out) {
+    if (c->plans.size() >= MAX_PLANS) {
+        HIPCHK(c, hipDeviceSynchronize());
+        c->plans.erase(c->plans.begin());
+    }
+    c->plans.push_back(std::move(p));
+    *out = c->plans.back().get();
+    return LSR_OK;
+}
+
+int64_t cells_for(int64_t n) { return 4 * n + 4096; }
+
+// Lay out and allocate a fragment-batch plan.  frags[f] are the inputs;
+// pairs pair fragment 2b with 2b+1 when `paired`.
+int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, const lsr_params *prm,
+                    std::vector<char> key, hipStream_t s, Plan **out) {
+    auto P = std::make_unique<Plan>();
+    P->key = std::move(key);
+    const int nf = (int)frags.size();
+    const int npairs = paired ? nf / 2 : 0;
+    std::vector<Frag> hf(nf);
+    std::vector<Blk> b256, b512;
+    std::vector<TrialBlk> tb;
+    std::vector<int64_t> foff(nf + 1, 0);
+    int64_t ntot = 0, ncells = 0, pk_rows = 0;
+    for (int f = 0; f < nf; ++f) {
+        Frag &F = hf[f];
+        std::memset(&F, 0, sizeof F);
+        for (int a = 0; a < 6; ++a) F.src[a] = frags[f].src[a];
+        F.off = ntot;
+        F.n = (int32_t)frags[f].n;
+        F.partner = paired ? (f ^ 1) : (nf == 2 ? (f ^ 1) : -1);
+        F.pair = paired ? f / 2 : -1;
+        F.cell_off = ncells;
+        F.cell_cap = (int32_t)cells_for(F.n);
+        F.pk_off = pk_rows;
+        F.blk256_first = (int32_t)b256.size();
+        ntot += F.n;
+        ncells += F.cell_cap;
+        foff[f + 1] = ntot;
+        for (int32_t st = 0; st < F.n; st += 256) b256.push_back(Blk{f, st});
+        for (int32_t st = 0; st < F.n; st += 512) b512.push_back(Blk{f, st});
+        pk_rows += ((int64_t)F.n + 127) / 128 * 128;
+    }
+    if (paired && prm) {
+        const int tpb = trials_per_block();
+        for (int b = 0; b < npairs; ++b) {
+            int64_t nP = hf[2 * b].n;
+            int64_t T = prm->n_trials > 0 ? prm->n_trials : std::min<int64_t>(4000000, 100 * nP);
+            if (nP == 0) T = 0;
+            for (int64_t f0 = 0; f0 < T; f0 += tpb) tb.push_back(TrialBlk{b, 0, f0, T});
+        }
+    }
+    int precision = prm ? prm->precision : LSR_FP32;
+    P->npairs = npairs;
+    P->pk_rows = pk_rows;
+    P->g.nfrag = nf;
+    P->g.ntot = ntot;
+    P->g.ncells = ncells;
+    P->g.nblk256 = (int)b256.size();
+    P->g.nblk512 = (int)b512.size();
+    P->g.pk_rows = pk_rows;
+    P->ntb = (int)tb.size();
+
+    // host tables (pinned), copied once
+    Layout H;
+    size_t h_frag = H.add(sizeof(Frag) * nf), h_b256 = H.add(sizeof(Blk) * b256.size()),
+           h_b512 = H.add(sizeof(Blk) * b512.size()), h_tb = H.add(sizeof(TrialBlk) * tb.size()),
+           h_foff = H.add(sizeof(int64_t) * (nf + 1));
+    // device layout
+    Layout D;
+    size_t o_tabs = D.add(H.total);
+    size_t n1 = (size_t)std::max<int64_t>(ntot, 1), c1 = (size_t)std::max<int64_t>(ncells, 1);
+    size_t o_cellpt = D.add(4 * n1), o_cstart = D.add(4 * (c1 + 1)), o_ccount = D.add(4 * c1),
+           o_cursor = D.add(4 * (c1 + scan_tmp_elems(ncells))), o_tmp = D.add(4 * n1);
+    size_t o_s[6];
+    for (int a = 0; a < 6; ++a) o_s[a] = D.add(4 * n1);
+    size_t o_sorig = D.add(4 * n1);
+    size_t o_n[3];
+    for (int a = 0; a < 3; ++a) o_n[a] = D.add(8 * n1);
+    size_t o_spfh = D.add(4 * FD * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
+    size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
+    size_t o_nn = D.add(4 * n1), o_dist = D.add(4 * n1), o_mut = D.add(n1), o_flag = D.add(4 * n1),
+           o_kpos = D.add(4 * n1), o_kp = D.add(12 * n1), o_kq = D.add(12 * n1), o_ki = D.add(4 * n1);
+    size_t o_ps = D.add(sizeof(PairState) * (size_t)std::max(npairs, 1));
+    size_t o_stmp = D.add(4 * scan_tmp_elems(ntot));
+    size_t o_nrm = D.add(24 * n1);
+    size_t o_cnt = D.add(8 * 16);
+    size_t msz = precision == LSR_BF16_SCREEN ? match_bf16_scratch(P->g, pk_rows) : 0;
+    size_t o_msc = D.add(std::max<size_t>(msz, 256));
+
+    if (capturing(s)) return fail(c, LSR_ENOMEM, "a new plan would allocate while the stream is being captured");
+    HIPCHK(c, hipHostMalloc((void **)&P->hmem, std::max<size_t>(H.total, 256), hipHostMallocDefault));
+    P->hbytes = H.total;
+    HIPCHK(c, hipMalloc((void **)&P->dmem, D.total));
+    P->dbytes = D.total;
+    char *hb = P->hmem, *db = P->dmem;
+    std::memcpy(hb + h_frag, hf.data(), sizeof(Frag) * nf);
+    if (!b256.empty()) std::memcpy(hb + h_b256, b256.data(), sizeof(Blk) * b256.size());
+    if (!b512.empty()) std::memcpy(hb + h_b512, b512.data(), sizeof(Blk) * b512.size());
+    if (!tb.empty()) std::memcpy(hb + h_tb, tb.data(), sizeof(TrialBlk) * tb.size());
+    std::memcpy(hb + h_foff, foff.data(), sizeof(int64_t) * (nf + 1));
+    char *tabs = db + o_tabs;
+    P->g.frag = (Frag *)(tabs + h_frag);
+    P->g.blk256 = (Blk *)(tabs + h_b256);
+    P->g.blk512 = (Blk *)(tabs + h_b512);
+    P->tb = (TrialBlk *)(tabs + h_tb);
+    P->g.frag_off = (int64_t *)(tabs + h_foff);
+    P->g.cell_of_pt = (int32_t *)(db + o_cellpt);
+    P->g.cstart = (int32_t *)(db + o_cstart);
+    P->g.ccount = (int32_t *)(db + o_ccount);
+    P->g.cursor = (int32_t *)(db + o_cursor);
+    P->g.tmp = (int32_t *)(db + o_tmp);
+    P->g.sx = (float *)(db + o_s[0]); P->g.sy = (float *)(db + o_s[1]); P->g.sz = (float *)(db + o_s[2]);
+    P->g.snx = (float *)(db + o_s[3]); P->g.sny = (float *)(db + o_s[4]); P->g.snz = (float *)(db + o_s[5]);
+    P->g.sorig = (int32_t *)(db + o_sorig);
+    P->d.nx = (double *)(db + o_n[0]); P->d.ny = (double *)(db + o_n[1]); P->d.nz = (double *)(db + o_n[2]);
+    P->d.spfh = (float *)(db + o_spfh);
+    P->d.knb = (int32_t *)(db + o_knb);
+    P->d.F = (float *)(db + o_F);
+    P->d.valid = (int32_t *)(db + o_valid);
+    P->d.pk = (uint16_t *)(db + o_pk);
+    P->m.nn = (int32_t *)(db + o_nn);
+    P->m.dist = (float *)(db + o_dist);
+    P->m.mutual = (uint8_t *)(db + o_mut);
+    P->m.flag = (int32_t *)(db + o_flag);
+    P->m.kpos = (int32_t *)(db + o_kpos);
+    P->m.kp = (float *)(db + o_kp);
+    P->m.kq = (float *)(db + o_kq);
+    P->m.ki = (int32_t *)(db + o_ki);
+    P->ps = (PairState *)(db + o_ps);
+    P->scan_tmp = (int32_t *)(db + o_stmp);
+    P->nrm_orig = (double *)(db + o_nrm);
+    P->cnt64 = (int64_t *)(db + o_cnt);
+    P->mscratch = db + o_msc;
+    HIPCHK(c, hipMemcpyAsync(tabs, hb, H.total, hipMemcpyHostToDevice, s));
+    return add_plan(c, std::move(P), out);
+}
+
+int check_params(lsr_ctx *c, const lsr_params *p) {
+    if (!p) return fail(c, LSR_EINVAL, "params is NULL");
+    auto fin = [](double v) { return v == v && v < 1e300 && v > -1e300; };
+    if (!fin(p->r_normal) || !fin(p->r_feature) || !fin(p->max_corr) || !fin(p->tau) || !fin(p->gnc_div) ||
+        !fin(p->min_inlier_ratio) || !fin(p->normal_cos))
+        return fail(c, LSR_EINVAL, "non-finite parameter");
+    if (!(p->r_normal > 0) || !(p->r_feature > 0) || !(p->max_corr > 0))
+        return fail(c, LSR_EINVAL, "radii and max_corr must be positive");
+    if (!(p->tau > 0 && p->tau <= 1)) return fail(c, LSR_EINVAL, "tau must lie in (0, 1]");
+    if (!(p->gnc_div > 1) || p->gnc_every < 1 || p->gnc_max_iter < 0 || p->polish_iter < 0)
+        return fail(c, LSR_EINVAL, "invalid non-convexity schedule");
+    if (p->precision != LSR_FP32 && p->precision != LSR_BF16_SCREEN)
+        return fail(c, LSR_EINVAL, "unknown precision %d", p->precision);
+    if (p->n_trials > (int64_t)1 << 40) return fail(c, LSR_EINVAL, "n_trials too large");
+    return LSR_OK;
+}
+
+int check_cloud(lsr_ctx *c, const lsr_cloud *cl, const char *name, bool need_normals) {
+    if (!cl) return fail(c, LSR_EINVAL, "%s is NULL", name);
+    if (cl->n < 0 || cl->n > ((int64_t)1 << 28)) return fail(c, LSR_EINVAL, "%s: size %lld out of range", name, (long long)cl->n);
+    if (cl->n > 0 && (!cl->x || !cl->y || !cl->z)) return fail(c, LSR_EINVAL, "%s: NULL coordinates", name);
+    if (need_normals && cl->n > 0 && (!cl->nx || !cl->ny || !cl->nz)) return fail(c, LSR_EINVAL, "%s: NULL normals", name);
+    return LSR_OK;
+}
+
+FragIn frag_of(const lsr_cloud *c, int64_t off, int64_t n) {
+    FragIn f;
+    const float *a[6] = {c->x, c->y, c->z, c->nx, c->ny, c->nz};
+    for (int k = 0; k < 6; ++k) f.src[k] = a[k] ? a[k] + off : nullptr;
+    f.n = n;
+    return f;
+}
+
+// The full registration sequence over a paired plan.
+int run_pairs(lsr_ctx *c, Plan *P, const lsr_params &prm, lsr_result *d_out, hipStream_t s) {
+    float r_cell = std::max(std::max(prm.r_normal, prm.r_feature), prm.max_corr);
+    tmark("start", s);
+    HIPCHK(c, fill<uint32_t>((uint32_t *)P->ps, 0u, (int64_t)(sizeof(PairState) * P->npairs / 4), s));
+    HIPCHK(c, build_grids(P->g, r_cell, s));
+    tmark("grid", s);
+    HIPCHK(c, launch_normals(P->g, prm.r_normal, P->d, nullptr, s));
+    tmark("normals", s);
+    HIPCHK(c, launch_spfh(P->g, prm.r_feature, P->d, s));
+    tmark("spfh", s);
+    HIPCHK(c, launch_fpfh(P->g, prm.r_feature, P->d, P->ps, s));
+    tmark("fpfh", s);
+    if (prm.precision == LSR_BF16_SCREEN) {
+        HIPCHK(c, launch_match_bf16(P->g, P->d, P->m, P->ps, P->mscratch, s));
+        tmark("fallback", s);
+    } else {
+        HIPCHK(c, launch_match_fp32(P->g, P->d, P->m, s));
+        tmark("match_fp32", s);
+    }
+    HIPCHK(c, launch_mutual(P->g, P->m, P->ps, s));
+    HIPCHK(c, launch_consistency(P->g, P->m, P->ps, P->tb, P->ntb, prm.tau, prm.seed, s));
+    tmark("consistency", s);
+    HIPCHK(c, launch_compact(P->g, P->m, P->ps, P->scan_tmp, s));
+    HIPCHK(c, launch_gnc(P->g, P->m, P->ps, P->npairs, prm, s));
+    tmark("gnc", s);
+    HIPCHK(c, launch_verify(P->g, P->d, P->ps, prm.max_corr, prm.normal_check, prm.normal_cos, s));
+    HIPCHK(c, launch_finalize(P->g, P->ps, P->npairs, prm, d_out, s));
+    tmark("verify", s);
+    return LSR_OK;
+}
+
+__global__ void k_gnc_info(const PairState *ps, double *T, double *info) {
+    if (threadIdx.x < 16) T[threadIdx.x] = ps->T[threadIdx.x];
+    if (threadIdx.x == 0) {
+        info[0] = ps->status; info[1] = ps->iters; info[2] = ps->mu_final; info[3] = ps->energy;
+    }
+}
+
+__global__ void k_verify_info(const PairState *ps, const Frag *frag, double delta2, double *info) {
+    double n = (double)ps->n_inliers;
+    info[0] = n;
+    info[1] = frag[0].n > 0 ? n / (double)frag[0].n : 0.0;
+    info[2] = ps->n_inliers ? sqrt((double)ps->sum_d2_fixed / 1099511627776.0 * delta2 / n) : 0.0;
+}
+
+__global__ void k_set_T(PairState *ps, const double *T) {
+    if (threadIdx.x < 16) ps->T[threadIdx.x] = T[threadIdx.x];
+}
+
+__global__ void k_flag_out(const int32_t *flag, int64_t n, uint8_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = flag[i] ? 1 : 0;
+}
+
+__global__ void k_passed_out(const PairState *ps, int64_t *out) { *out = (int64_t)ps->trials_passed; }
+
+__global__ void k_fallback_out(const PairState *ps, int64_t *out) { *out = (int64_t)ps->n_fallback; }
+
+unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+
+extern "C" {
+
+int lsr_set_timing(lsr_ctx *ctx, int enable) {
+    if (!ctx) return LSR_EINVAL;
+    g_timing.on = enable != 0;
+    g_timing.used = 0;
+    return LSR_OK;
+}
+
+int lsr_get_timing(lsr_ctx *ctx, int max_steps, char *names, double *ms, int *n_steps) {
+    if (!ctx || !n_steps || max_steps < 0) return LSR_EINVAL;
+    Timing &T = g_timing;
+    HIPCHK(ctx, hipDeviceSynchronize());
+    int n = (int)T.used > 0 ? (int)T.used - 1 : 0;
+    if (n > max_steps) n = max_steps;
+    for (int k = 0; k < n; ++k) {
+        float t = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, T.ev[k], T.ev[k + 1]));
+        if (ms) ms[k] = t;
+        if (names) { std::strncpy(names + 32 * k, T.names[k + 1].c_str(), 31); names[32 * k + 31] = 0; }
+    }
+    *n_steps = n;
+    T.used = 0;
+    return LSR_OK;
+}
+
+void lsr_default_params(lsr_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->r_normal = 0.025f;
+    p->r_feature = 0.05f;
+    p->max_corr = 0.015f;
+    p->tau = 0.9f;
+    p->n_trials = 0;
+    p->gnc_div = 1.4;
+    p->gnc_every = 4;
+    p->gnc_max_iter = 256;
+    p->polish_iter = 32;
+    p->min_inlier_ratio = 0.15f;
+    p->min_consistent = 10;
+    p->normal_check = 0;
+    p->normal_cos = 0.8660254f;
+    p->precision = LSR_FP32;
+    p->seed = 0x1801015720ULL;
+}
+
+int lsr_create(lsr_ctx **ctx, int device) {
+    if (!ctx) return LSR_EINVAL;
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LSR_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return LSR_EHIP;
+    lsr_ctx *c = new lsr_ctx;
+    c->device = device;
+    *ctx = c;
+    return LSR_OK;
+}
+
+void lsr_destroy(lsr_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->plans.clear();
+    delete ctx;
+}
+
+const char *lsr_last_error(const lsr_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int lsr_register_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, const lsr_params *prm,
+                      lsr_result *d_out, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_params(ctx, prm)) || (rc = check_cloud(ctx, P, "P", true)) || (rc = check_cloud(ctx, Q, "Q", true)))
+        return rc;
+    if (!d_out) return fail(ctx, LSR_EINVAL, "d_out is NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr = {frag_of(P, 0, P->n), frag_of(Q, 0, Q->n)};
+    std::vector<char> key;
+    put(key, (int)K_PAIRS);
+    put(key, *prm);
+    for (auto &f : fr) { put(key, f.n); for (int a = 0; a < 6; ++a) put(key, f.src[a]); }
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, prm, key, s, &pl))) return rc;
+    return run_pairs(ctx, pl, *prm, d_out, s);
+}
+
+int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                       const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_params(ctx, prm)) || (rc = check_cloud(ctx, P_all, "P_all", true)) ||
+        (rc = check_cloud(ctx, Q_all, "Q_all", true)))
+        return rc;
+    if (n_pairs < 0 || n_pairs > (1 << 20)) return fail(ctx, LSR_EINVAL, "n_pairs %d out of range", n_pairs);
+    if (n_pairs == 0) return LSR_OK;
+    if (!offP || !offQ || !d_out) return fail(ctx, LSR_EINVAL, "NULL offsets or output");
+    for (int b = 0; b < n_pairs; ++b) {
+        if (offP[b] < 0 || offP[b + 1] < offP[b] || offP[b + 1] > P_all->n || offQ[b] < 0 || offQ[b + 1] < offQ[b] ||
+            offQ[b + 1] > Q_all->n)
+            return fail(ctx, LSR_EINVAL, "bad offsets at pair %d", b);
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr;
+    fr.reserve(2 * n_pairs);
+    for (int b = 0; b < n_pairs; ++b) {
+        fr.push_back(frag_of(P_all, offP[b], offP[b + 1] - offP[b]));
+        fr.push_back(frag_of(Q_all, offQ[b], offQ[b + 1] - offQ[b]));
+    }
+    std::vector<char> key;
+    put(key, (int)K_PAIRS + 100);
+    put(key, *prm);
+    put(key, d_out);
+    for (auto &f : fr) { put(key, f.n); for (int a = 0; a < 6; ++a) put(key, f.src[a]); }
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, prm, key, s, &pl))) return rc;
+    if (!s || capturing(s) || g_timing.on) return run_pairs(ctx, pl, *prm, d_out, s);   // eager
+    if (!pl->gexec) {
+        HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rc = run_pairs(ctx, pl, *prm, d_out, s);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &gr);
+        if (rc) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+        if (e != hipSuccess) return fail(ctx, LSR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        pl->graph = gr;
+        HIPCHK(ctx, hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0));
+    }
+    HIPCHK(ctx, hipGraphLaunch(pl->gexec, s));
+    return LSR_OK;
+}
+
+int lsr_stage_normals(lsr_ctx *ctx, const lsr_cloud *c, float r_normal, double *d_nrm, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_cloud(ctx, c, "cloud", true))) return rc;
+    if (!d_nrm || !(r_normal > 0)) return fail(ctx, LSR_EINVAL, "bad normals arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr = {frag_of(c, 0, c->n)};
+    std::vector<char> key;
+    put(key, (int)K_NORMALS);
+    put(key, fr[0]);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, false, nullptr, key, s, &pl))) return rc;
+    HIPCHK(ctx, build_grids(pl->g, r_normal, s));
+    HIPCHK(ctx, launch_normals(pl->g, r_normal, pl->d, d_nrm, s));
+    return LSR_OK;
+}
+
+int lsr_stage_fpfh(lsr_ctx *ctx, const lsr_cloud *c, const double *d_nrm, float r_feature, float *d_F,
+                   int32_t *d_valid, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_cloud(ctx, c, "cloud", false))) return rc;
+    if (!d_nrm || !d_F || !d_valid || !(r_feature > 0)) return fail(ctx, LSR_EINVAL, "bad fpfh arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr = {frag_of(c, 0, c->n)};
+    std::vector<char> key;
+    put(key, (int)K_FPFH);
+    put(key, fr[0]);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, false, nullptr, key, s, &pl))) return rc;
+    HIPCHK(ctx, build_grids(pl->g, r_feature, s));
+    HIPCHK(ctx, launch_normals_inject(pl->g, d_nrm, pl->d, s));
+    HIPCHK(ctx, launch_spfh(pl->g, r_feature, pl->d, s));
+    HIPCHK(ctx, launch_fpfh(pl->g, r_feature, pl->d, nullptr, s));
+    HIPCHK(ctx, copy<float>(d_F, pl->d.F, c->n * FD, s));
+    HIPCHK(ctx, copy<int32_t>(d_valid, pl->d.valid, c->n, s));
+    return LSR_OK;
+}
+
+int lsr_stage_match(lsr_ctx *ctx, const float *d_F, const int32_t *d_vF, int64_t nP, const float *d_G,
+                    const int32_t *d_vG, int64_t nQ, int32_t precision, int32_t *d_nnQ, float *d_dQ,
+                    int32_t *d_nnP, float *d_dP, int64_t *d_fallback, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (nP < 0 || nQ < 0 || nP > (1 << 28) || nQ > (1 << 28)) return fail(ctx, LSR_EINVAL, "bad sizes");
+    if ((nP && (!d_F || !d_vF || !d_nnQ || !d_dQ)) || (nQ && (!d_G || !d_vG || !d_nnP || !d_dP)))
+        return fail(ctx, LSR_EINVAL, "NULL match argument");
+    if (precision != LSR_FP32 && precision != LSR_BF16_SCREEN) return fail(ctx, LSR_EINVAL, "unknown precision");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    FragIn a{}, b{};
+    a.n = nP; b.n = nQ;
+    std::vector<FragIn> fr = {a, b};
+    lsr_params prm;
+    lsr_default_params(&prm);
+    prm.precision = precision;
+    prm.n_trials = 1;
+    std::vector<char> key;
+    put(key, (int)K_MATCH);
+    put(key, nP); put(key, nQ); put(key, precision);
+    int rc;
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, &prm, key, s, &pl))) return rc;
+    HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
+    HIPCHK(ctx, copy<float>(pl->d.F, d_F, nP * FD, s));
+    HIPCHK(ctx, copy<float>(pl->d.F + nP * FD, d_G, nQ * FD, s));
+    HIPCHK(ctx, copy<int32_t>(pl->d.valid, d_vF, nP, s));
+    HIPCHK(ctx, copy<int32_t>(pl->d.valid + nP, d_vG, nQ, s));
+    if (precision == LSR_BF16_SCREEN) {
+        HIPCHK(ctx, launch_match_bf16(pl->g, pl->d, pl->m, pl->ps, pl->mscratch, s));
+    } else {
+        HIPCHK(ctx, launch_match_fp32(pl->g, pl->d, pl->m, s));
+    }
+    HIPCHK(ctx, copy<int32_t>(d_nnQ, pl->m.nn, nP, s));
+    HIPCHK(ctx, copy<float>(d_dQ, pl->m.dist, nP, s));
+    HIPCHK(ctx, copy<int32_t>(d_nnP, pl->m.nn + nP, nQ, s));
+    HIPCHK(ctx, copy<float>(d_dP, pl->m.dist + nP, nQ, s));
+    if (d_fallback) {
+        hipLaunchKernelGGL(k_fallback_out, dim3(1), dim3(1), 0, s, (const PairState *)pl->ps, d_fallback);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return LSR_OK;
+}
+
+int lsr_stage_consistency(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, const int32_t *d_nnQ,
+                          const uint8_t *d_mutual, int64_t n_trials, float tau, uint64_t seed, uint8_t *d_flag,
+                          int64_t *d_passed, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_cloud(ctx, P, "P", false)) || (rc = check_cloud(ctx, Q, "Q", false))) return rc;
+    if (!d_nnQ || !d_mutual || !d_flag || !d_passed || !(tau > 0 && tau <= 1))
+        return fail(ctx, LSR_EINVAL, "bad consistency arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr = {frag_of(P, 0, P->n), frag_of(Q, 0, Q->n)};
+    lsr_params prm;
+    lsr_default_params(&prm);
+    prm.n_trials = n_trials;
+    prm.tau = tau;
+    std::vector<char> key;
+    put(key, (int)K_CONS);
+    put(key, n_trials);
+    for (auto &f : fr) put(key, f);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, &prm, key, s, &pl))) return rc;
+    HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
+    HIPCHK(ctx, copy<int32_t>(pl->m.nn, d_nnQ, P->n, s));
+    HIPCHK(ctx, copy<uint8_t>(pl->m.mutual, d_mutual, P->n, s));
+    HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, tau, seed, s));
+    if (P->n > 0) {
+        hipLaunchKernelGGL(k_flag_out, dim3(nblk(P->n, 256)), dim3(256), 0, s, (const int32_t *)pl->m.flag, P->n, d_flag);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_passed_out, dim3(1), dim3(1), 0, s, (const PairState *)pl->ps, d_passed);
+    HIPCHK(ctx, hipGetLastError());
+    return LSR_OK;
+}
+
+int lsr_stage_gnc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m, const lsr_params *prm, double *d_T,
+                  double *d_info, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_params(ctx, prm))) return rc;
+    if (m < 0 || (m > 0 && (!d_p || !d_q)) || !d_T || !d_info) return fail(ctx, LSR_EINVAL, "bad gnc arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<char> key;
+    put(key, (int)K_ALIGN + 50);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl) {
+        auto P = std::make_unique<Plan>();
+        P->key = key;
+        if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
+        HIPCHK(ctx, hipMalloc((void **)&P->dmem, sizeof(PairState)));
+        P->ps = (PairState *)P->dmem;
+        if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
+    }
+    HIPCHK(ctx, launch_gnc_direct(d_p, d_q, m, *prm, pl->ps, s));
+    hipLaunchKernelGGL(k_gnc_info, dim3(1), dim3(64), 0, s, (const PairState *)pl->ps, d_T, d_info);
+    HIPCHK(ctx, hipGetLastError());
+    return LSR_OK;
+}
+
+int lsr_stage_verify(lsr_ctx *ctx, const lsr_cloud *P, const double *d_nrmP, const lsr_cloud *Q,
+                     const double *d_nrmQ, const double *d_T, float delta, int32_t normal_check, float normal_cos,
+                     double *d_info, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_cloud(ctx, P, "P", false)) || (rc = check_cloud(ctx, Q, "Q", false))) return rc;
+    if (!d_T || !d_info || !(delta > 0) || (normal_check && (!d_nrmP || !d_nrmQ)))
+        return fail(ctx, LSR_EINVAL, "bad verify arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr = {frag_of(P, 0, P->n), frag_of(Q, 0, Q->n)};
+    std::vector<char> key;
+    put(key, (int)K_VERIFY);
+    for (auto &f : fr) put(key, f);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, nullptr, key, s, &pl))) return rc;
+    HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
+    HIPCHK(ctx, build_grids(pl->g, delta, s));
+    if (normal_check) {
+        HIPCHK(ctx, copy<double>(pl->nrm_orig, d_nrmP, 3 * P->n, s));
+        HIPCHK(ctx, copy<double>(pl->nrm_orig + 3 * P->n, d_nrmQ, 3 * Q->n, s));
+        HIPCHK(ctx, launch_normals_inject(pl->g, pl->nrm_orig, pl->d, s));
+    }
+    hipLaunchKernelGGL(k_set_T, dim3(1), dim3(64), 0, s, pl->ps, d_T);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, launch_verify(pl->g, pl->d, pl->ps, delta, normal_check, normal_cos, s));
+    hipLaunchKernelGGL(k_verify_info, dim3(1), dim3(1), 0, s, (const PairState *)pl->ps, (const Frag *)pl->g.frag,
+                       (double)delta * (double)delta, d_info);
+    HIPCHK(ctx, hipGetLastError());
+    return LSR_OK;
+}
+
+static int align_common(lsr_ctx *ctx, bool bwd, const float *const P_xyz[3], int64_t nP,
+                        const float *const Q_xyz[3], int64_t nQ,
+                        const int32_t *d_corr, const int64_t *coff, int32_t n_problems, const double *d_T,
+                        const double *d_mu, const double *d_dE, double *out, float *const dP[3], float *const dQ[3],
+                        void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (nP < 0 || nQ < 0 || !P_xyz || !Q_xyz || !coff || n_problems <= 0 || n_problems > (1 << 20) || !d_T || !d_mu || !out)
+        return fail(ctx, LSR_EINVAL, "bad align-loss arguments");
+    for (int a = 0; a < 3; ++a)
+        if (!P_xyz[a] || !Q_xyz[a] || (bwd && (!dP || !dQ || !dP[a] || !dQ[a])))
+            return fail(ctx, LSR_EINVAL, "NULL coordinate or gradient array");
+    if (bwd && !d_dE) return fail(ctx, LSR_EINVAL, "NULL dE");
+    for (int k = 0; k < n_problems; ++k)
+        if (coff[k] < 0 || coff[k + 1] < coff[k]) return fail(ctx, LSR_EINVAL, "bad correspondence offsets");
+    if (coff[n_problems] > 0 && !d_corr) return fail(ctx, LSR_EINVAL, "NULL correspondences");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<char> key;
+    put(key, (int)K_ALIGN);
+    put(key, n_problems);
+    key.insert(key.end(), (const char *)coff, (const char *)(coff + n_problems + 1));
+    Plan *pl = find_plan(ctx, key);
+    if (!pl) {
+        auto P = std::make_unique<Plan>();
+        P->key = key;
+        std::vector<int64_t> pblk(n_problems + 1);
+        int64_t nb = align_blocks(coff, n_problems, nullptr, pblk.data());
+        std::vector<char> tab(align_block_bytes() * (size_t)std::max<int64_t>(nb, 1));
+        align_blocks(coff, n_problems, tab.data(), pblk.data());
+        Layout H;
+        size_t h_tab = H.add(tab.size()), h_pb = H.add(sizeof(int64_t) * pblk.size());
+        Layout D;
+        size_t o_tabs = D.add(H.total), o_part = D.add(sizeof(double) * 6 * (size_t)std::max<int64_t>(nb, 1));
+        if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
+        HIPCHK(ctx, hipHostMalloc((void **)&P->hmem, H.total, hipHostMallocDefault));
+        HIPCHK(ctx, hipMalloc((void **)&P->dmem, D.total));
+        std::memcpy(P->hmem + h_tab, tab.data(), tab.size());
+        std::memcpy(P->hmem + h_pb, pblk.data(), sizeof(int64_t) * pblk.size());
+        P->atab = P->dmem + o_tabs + h_tab;
+        P->apblk = (int64_t *)(P->dmem + o_tabs + h_pb);
+        P->apart = (double *)(P->dmem + o_part);
+        P->anblk = nb;
+        HIPCHK(ctx, hipMemcpyAsync(P->dmem + o_tabs, P->hmem, H.total, hipMemcpyHostToDevice, s));
+        int rc;
+        if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
+    }
+    HIPCHK(ctx, launch_align(bwd, P_xyz, nP, Q_xyz, nQ, d_corr, pl->atab, pl->anblk, pl->apblk, n_problems, d_T, d_mu, d_dE,
+                             pl->apart, out, dP, dQ, s));
+    return LSR_OK;
+}
+
+int lsr_align_loss(lsr_ctx *ctx, const float *const P_xyz[3], int64_t nP, const float *const Q_xyz[3], int64_t nQ,
+                   const int32_t *d_corr, const int64_t *coff, int32_t n_problems, const double *d_T,
+                   const double *d_mu, double *d_E, void *stream) {
+    return align_common(ctx, false, P_xyz, nP, Q_xyz, nQ, d_corr, coff, n_problems, d_T, d_mu, nullptr, d_E, nullptr,
+                        nullptr, stream);
+}
+
+int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t nP,
+                            const float *const Q_xyz[3], int64_t nQ, const int32_t *d_corr, const int64_t *coff, int32_t n_problems, const double *d_T,
+                            const double *d_mu, const double *d_dE, float *const dP_xyz[3], float *const dQ_xyz[3],
+                            double *d_dxi, void *stream) {
+    if (!d_dxi) return ctx ? fail(ctx, LSR_EINVAL, "NULL d_dxi") : LSR_EINVAL;
+    return align_common(ctx, true, P_xyz, nP, Q_xyz, nQ, d_corr, coff, n_problems, d_T, d_mu, d_dE, d_dxi, dP_xyz, dQ_xyz,
+                        stream);
+}
+
+}  // extern "C"

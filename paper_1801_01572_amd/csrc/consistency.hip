@@ -1,0 +1,155 @@
+// Reciprocal test, quadruple consistency filter and compaction.
+//
+// Reciprocal: (i, nnQ(i)) is kept when nnP(nnQ(i)) = i.
+// Consistency (Algorithm 1's pre-rejection, used as a filter): trial t draws
+// four distinct P indices that have a reciprocal correspondence; slot s takes
+// the first of up to 64 draws i = ((r >> 32) * N_P) >> 32 that qualifies, with
+// r the n-th output of SplitMix64 (Steele, Lea and Flood 2014) for the given
+// seed and n = (t << 8) | (s << 6) | attempt.  The closed quadrilateral passes
+// when every edge length ratio lies within tau in both directions (squared,
+// FP64); the correspondences of a passing trial are flagged.
+// Compaction: flagged correspondences in ascending P index, as float xyz of p
+// and q, the input of the pose solve.
+#include "lsr_internal.h"
+
+namespace lsr {
+
+__global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk, const int32_t *nn, uint8_t *mutual,
+                                                PairState *ps) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    bool m = false;
+    if (i < F.n && F.partner >= 0) {
+        const Frag &G = frag[F.partner];
+        int32_t j = nn[F.off + i];
+        m = j >= 0 && nn[G.off + j] == i;
+        mutual[F.off + i] = m ? 1 : 0;
+    }
+    unsigned long long bal = __ballot(m);
+    __shared__ int cnt[4];
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0 && ps && F.pair >= 0 && (b.frag & 1) == 0) {
+        int t = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        if (t) atomicAdd(&ps[F.pair].n_recip, (unsigned long long)t);
+    }
+}
+
+hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mutual, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)m.nn, m.mutual, ps);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr int CT = 256;      // threads per block
+constexpr int CPT = 8;       // trials per thread
+
+__global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const int32_t *nn,
+                                                    const uint8_t *mutual, int32_t *flag, double t2, uint64_t seed,
+                                                    PairState *ps) {
+    const TrialBlk b = tb[blockIdx.x];
+    const Frag &P = frag[2 * b.pair];
+    const Frag &Q = frag[2 * b.pair + 1];
+    const uint64_t nP = (uint64_t)P.n;
+    int passed = 0;
+    for (int r = 0; r < CPT; ++r) {
+        int64_t t = b.first + (int64_t)r * CT + threadIdx.x;
+        if (t >= b.count || nP == 0) break;
+        int32_t id[4];
+        bool ok = true;
+        for (int sl = 0; sl < 4 && ok; ++sl) {
+            bool found = false;
+            for (int a = 0; a < 64; ++a) {
+                uint64_t rr = splitmix64_at(seed, ((uint64_t)t << 8) | ((uint64_t)sl << 6) | (uint64_t)a);
+                int32_t i = (int32_t)(((rr >> 32) * nP) >> 32);
+                if (!mutual[P.off + i]) continue;
+                bool dup = false;
+                for (int u = 0; u < sl; ++u) dup |= id[u] == i;
+                if (dup) continue;
+                id[sl] = i;
+                found = true;
+                break;
+            }
+            ok = found;
+        }
+        if (!ok) continue;
+        const float *px = P.src[0], *py = P.src[1], *pz = P.src[2];
+        const float *qx = Q.src[0], *qy = Q.src[1], *qz = Q.src[2];
+        for (int k = 0; k < 4 && ok; ++k) {
+            int32_t i0 = id[k], i1 = id[(k + 1) & 3];
+            int32_t j0 = nn[P.off + i0], j1 = nn[P.off + i1];
+            if (j0 < 0 || j0 >= Q.n || j1 < 0 || j1 >= Q.n) { ok = false; break; }
+            double a = pdist2(px[i0], py[i0], pz[i0], px[i1], py[i1], pz[i1]);
+            double c = pdist2(qx[j0], qy[j0], qz[j0], qx[j1], qy[j1], qz[j1]);
+            if (a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a) ok = false;
+        }
+        if (!ok) continue;
+        ++passed;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) flag[P.off + id[k]] = 1;
+    }
+    // passing-trial count per pair (integer, order independent)
+    for (int o = 32; o > 0; o >>= 1) passed += __shfl_xor(passed, o, 64);
+    if ((threadIdx.x & 63) == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
+}
+
+hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb, float tau,
+                              uint64_t seed, hipStream_t s) {
+    hipError_t e = fill<int32_t>(m.flag, 0, g.ntot, s);
+    if (e != hipSuccess || ntb == 0) return e;
+    double t2 = (double)tau * (double)tau;
+    hipLaunchKernelGGL(k_consistency, dim3(ntb), dim3(CT), 0, s, (const Frag *)g.frag, tb, (const int32_t *)m.nn,
+                       (const uint8_t *)m.mutual, m.flag, t2, seed, ps);
+    return hipGetLastError();
+}
+
+int trials_per_block() { return CT * CPT; }
+
+// Flagged correspondences, in ascending P index, gathered into compact xyz
+// arrays; per pair the list starts at kpos[P.off].
+__global__ void __launch_bounds__(256) k_compact(const Frag *frag, const Blk *blk, const int32_t *flag,
+                                                 const int32_t *kpos, const int32_t *nn, float *kp, float *kq,
+                                                 int32_t *ki, PairState *ps) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &P = frag[b.frag];
+    if ((b.frag & 1) || P.partner < 0) return;          // P fragments only
+    const Frag &Q = frag[P.partner];
+    int i = b.start + threadIdx.x;
+    bool f = i < P.n && flag[P.off + i];
+    if (f) {
+        int64_t pos = kpos[P.off + i];
+        int32_t j = nn[P.off + i];
+        kp[3 * pos] = P.src[0][i]; kp[3 * pos + 1] = P.src[1][i]; kp[3 * pos + 2] = P.src[2][i];
+        kq[3 * pos] = Q.src[0][j]; kq[3 * pos + 1] = Q.src[1][j]; kq[3 * pos + 2] = Q.src[2][j];
+        ki[pos] = i;
+    }
+    if (b.start == 0 && threadIdx.x == 0 && ps && P.pair >= 0) ps[P.pair].k_off = kpos[P.off];
+    unsigned long long bal = __ballot(f);
+    __shared__ int cnt[4];
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0 && ps && P.pair >= 0) {
+        int t = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        if (t) atomicAdd(&ps[P.pair].n_consistent, (unsigned long long)t);
+    }
+}
+
+hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipError_t e = exclusive_scan_i32(m.flag, m.kpos, g.ntot, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)m.flag, (const int32_t *)m.kpos, (const int32_t *)m.nn, m.kp, m.kq, m.ki, ps);
+    return hipGetLastError();
+}
+
+}  // namespace lsr

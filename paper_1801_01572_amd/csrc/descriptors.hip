@@ -1,0 +1,305 @@
+// Per-point geometry on the grid: normals, SPFH and FPFH.
+//
+// Normals: principal component analysis of the radius-r_normal neighbourhood
+// plus the point (normal estimation radius of Sec. III), FP64, oriented by
+// the input normal; fewer than 3 points keep the normalised input normal.
+//
+// FPFH (the descriptor of Algorithm 1; definition from the cited FPFH work):
+// for each neighbour pair, a Darboux frame u = n_s, v = u x e / |u x e|,
+// w = u x v, with the source s the endpoint whose normal makes the smaller
+// angle with the line towards the other; features alpha = v.n_t,
+// phi = u.e, theta = atan2(w.n_t, u.n_t) binned into 11 bins each.  SPFH_i is
+// the histogram divided by the number of non-degenerate pairs;
+// FPFH_i = SPFH_i + (1/k_i) sum_j SPFH_j / |p_j - p_i|, each 11-bin block then
+// scaled to unit sum.  Pair features are computed in FP64 so that bin and
+// source decisions agree with an FP64 evaluation except within rounding of a
+// boundary.
+#include "lsr_internal.h"
+
+namespace lsr {
+
+struct GridView {
+    const int32_t *cstart, *ccount;
+    const float *sx, *sy, *sz;
+};
+
+// Visit every sorted point within the 27-cell stencil of (px, py, pz): the
+// three cells adjacent along x are consecutive in the table, so the stencil is
+// nine contiguous runs of the sorted arrays.
+template <class Fn>
+__device__ __forceinline__ void for_stencil(const Frag &F, const GridView &g, double px, double py, double pz, Fn &&fn) {
+    int cx, cy, cz;
+    cell_of(F, px, py, pz, cx, cy, cz);
+    int x0 = max(cx - 1, 0), x1 = min(cx + 1, F.gx - 1);
+    if (x0 > x1) return;
+    for (int z = max(cz - 1, 0); z <= min(cz + 1, F.gz - 1); ++z) {
+        for (int y = max(cy - 1, 0); y <= min(cy + 1, F.gy - 1); ++y) {
+            int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
+            int32_t b = g.cstart[row + x0];
+            int32_t e = g.cstart[row + x1] + g.ccount[row + x1];
+            for (int32_t k = b; k < e; ++k) fn(k);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- normals
+
+// Smallest-eigenvalue eigenvector of a symmetric 3x3 matrix by cyclic Jacobi
+// rotations (each rotation zeroes one off-diagonal entry).
+__device__ void jacobi_min_vec(double a00, double a01, double a02, double a11, double a12, double a22, double v[3]) {
+    double A[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
+    double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        double off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+        double diag = fabs(A[0][0]) + fabs(A[1][1]) + fabs(A[2][2]);
+        if (off == 0.0 || off <= 1e-18 * diag) break;
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            double apq = A[p][q];
+            if (apq == 0.0) continue;
+            double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+            double t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+            double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double kp = A[k][p], kq = A[k][q];
+                A[k][p] = c * kp - s * kq;
+                A[k][q] = s * kp + c * kq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double pk = A[p][k], qk = A[q][k];
+                A[p][k] = c * pk - s * qk;
+                A[q][k] = s * pk + c * qk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double kp = V[k][p], kq = V[k][q];
+                V[k][p] = c * kp - s * kq;
+                V[k][q] = s * kp + c * kq;
+            }
+        }
+    }
+    int m = 0;
+    if (A[1][1] < A[m][m]) m = 1;
+    if (A[2][2] < A[m][m]) m = 2;
+    double x = m == 0 ? V[0][0] : (m == 1 ? V[0][1] : V[0][2]);
+    double y = m == 0 ? V[1][0] : (m == 1 ? V[1][1] : V[1][2]);
+    double z = m == 0 ? V[2][0] : (m == 1 ? V[2][1] : V[2][2]);
+    double inv = 1.0 / sqrt(x * x + y * y + z * z);
+    v[0] = x * inv; v[1] = y * inv; v[2] = z * inv;
+}
+
+__global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *blk, GridView g,
+                                                 const float *snx, const float *sny, const float *snz,
+                                                 const int32_t *sorig, double r2, double *nx, double *ny, double *nz,
+                                                 double *nrm_orig) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    if (i >= F.n) return;
+    int64_t s = F.off + i;
+    double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+    // shifted sums (origin at p_i): sum d, sum d d^T
+    double m = 1, s1x = 0, s1y = 0, s1z = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+    for_stencil(F, g, px, py, pz, [&](int32_t k) {
+        double qx = g.sx[k], qy = g.sy[k], qz = g.sz[k];
+        double d2 = pdist2(px, py, pz, qx, qy, qz);
+        if (d2 > 0.0 && d2 <= r2) {
+            double dx = qx - px, dy = qy - py, dz = qz - pz;
+            m += 1; s1x += dx; s1y += dy; s1z += dz;
+            sxx += dx * dx; sxy += dx * dy; sxz += dx * dz; syy += dy * dy; syz += dy * dz; szz += dz * dz;
+        }
+    });
+    double ix = snx[s], iy = sny[s], iz = snz[s];
+    double v[3];
+    if (m < 3) {
+        double l = sqrt(ix * ix + iy * iy + iz * iz);
+        double inv = l > 0 ? 1.0 / l : 0.0;
+        v[0] = ix * inv; v[1] = iy * inv; v[2] = iz * inv;
+    } else {
+        double im = 1.0 / m;
+        double mx = s1x * im, my = s1y * im, mz = s1z * im;
+        jacobi_min_vec(sxx * im - mx * mx, sxy * im - mx * my, sxz * im - mx * mz,
+                       syy * im - my * my, syz * im - my * mz, szz * im - mz * mz, v);
+        if (v[0] * ix + v[1] * iy + v[2] * iz < 0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
+    }
+    nx[s] = v[0]; ny[s] = v[1]; nz[s] = v[2];
+    if (nrm_orig) {
+        int64_t o = (F.off + sorig[s]) * 3;
+        nrm_orig[o] = v[0]; nrm_orig[o + 1] = v[1]; nrm_orig[o + 2] = v[2];
+    }
+}
+
+hipError_t launch_normals(const GridBufs &g, float r_normal, DescBufs &d, double *nrm_orig, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
+    double r2 = (double)r_normal * (double)r_normal;
+    hipLaunchKernelGGL(k_normals, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
+                       (const float *)g.snx, (const float *)g.sny, (const float *)g.snz, (const int32_t *)g.sorig,
+                       r2, d.nx, d.ny, d.nz, nrm_orig);
+    return hipGetLastError();
+}
+
+// Normals given by the caller (original order, n x 3) copied into sorted order.
+__global__ void __launch_bounds__(256) k_normals_inject(const Frag *frag, const Blk *blk, const int32_t *sorig,
+                                                        const double *nrm_orig, double *nx, double *ny, double *nz) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    if (i >= F.n) return;
+    int64_t s = F.off + i;
+    int64_t o = (F.off + sorig[s]) * 3;
+    nx[s] = nrm_orig[o]; ny[s] = nrm_orig[o + 1]; nz[s] = nrm_orig[o + 2];
+}
+
+hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, DescBufs &d, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_normals_inject, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)g.sorig, nrm_orig, d.nx, d.ny, d.nz);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- SPFH
+
+__device__ __forceinline__ int bin11(double x) {       // x in bin units
+    double f = floor(x);
+    f = fmin(fmax(f, 0.0), (double)(NB - 1));
+    return (int)f;
+}
+
+constexpr int SPFH_T = 256;
+
+__global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, GridView g, const double *nxa,
+                                                 const double *nya, const double *nza, double r2, float *spfh,
+                                                 int32_t *knb) {
+    __shared__ uint32_t hist[SPFH_T * FD];
+    uint32_t *h = hist + threadIdx.x * FD;
+#pragma unroll
+    for (int c = 0; c < FD; ++c) h[c] = 0;
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    if (i >= F.n) return;                       // no block-wide barrier follows
+    int64_t s = F.off + i;
+    const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+    const double ax = nxa[s], ay = nya[s], az = nza[s];
+    int k = 0, kp = 0;
+    const double PI = 3.14159265358979323846;
+    for_stencil(F, g, px, py, pz, [&](int32_t j) {
+        double qx = g.sx[j], qy = g.sy[j], qz = g.sz[j];
+        double d2 = pdist2(px, py, pz, qx, qy, qz);
+        if (!(d2 > 0.0 && d2 <= r2)) return;
+        ++k;
+        double inv = 1.0 / sqrt(d2);
+        double ex = (qx - px) * inv, ey = (qy - py) * inv, ez = (qz - pz) * inv;
+        double bx = nxa[j], by = nya[j], bz = nza[j];
+        double ci = ax * ex + ay * ey + az * ez;
+        double cj = bx * ex + by * ey + bz * ez;
+        // source = i when n_i.e >= -(n_j.e): then u = n_i, target normal n_j, line e
+        bool src_i = ci >= -cj;
+        double ux = src_i ? ax : bx, uy = src_i ? ay : by, uz = src_i ? az : bz;
+        double tx = src_i ? bx : ax, ty = src_i ? by : ay, tz = src_i ? bz : az;
+        double sg = src_i ? 1.0 : -1.0;
+        ex *= sg; ey *= sg; ez *= sg;
+        double vx = uy * ez - uz * ey, vy = uz * ex - ux * ez, vz = ux * ey - uy * ex;
+        double vn = sqrt(vx * vx + vy * vy + vz * vz);
+        if (vn <= 1e-12) return;
+        vx /= vn; vy /= vn; vz /= vn;
+        double wx = uy * vz - uz * vy, wy = uz * vx - ux * vz, wz = ux * vy - uy * vx;
+        double alpha = vx * tx + vy * ty + vz * tz;
+        double phi = ux * ex + uy * ey + uz * ez;
+        double theta = atan2(wx * tx + wy * ty + wz * tz, ux * tx + uy * ty + uz * tz);
+        ++kp;
+        h[bin11(NB * (alpha + 1.0) / 2.0)] += 1;
+        h[NB + bin11(NB * (phi + 1.0) / 2.0)] += 1;
+        h[2 * NB + bin11(NB * (theta + PI) / (2.0 * PI))] += 1;
+    });
+    float sc = kp > 0 ? 1.0f / (float)kp : 0.0f;
+    float *o = spfh + s * FD;
+#pragma unroll
+    for (int c = 0; c < FD; ++c) o[c] = kp > 0 ? (float)h[c] * sc : 0.0f;
+    knb[s] = k;
+}
+
+hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
+    double r2 = (double)r_feature * (double)r_feature;
+    hipLaunchKernelGGL(k_spfh, dim3(g.nblk256), dim3(SPFH_T), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
+                       (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, r2, d.spfh, d.knb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- FPFH
+
+__global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, GridView g, const int32_t *sorig,
+                                              const float *spfh, const int32_t *knb, double r2, float *Fout,
+                                              int32_t *valid, PairState *ps) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    bool ok = false;
+    if (i < F.n) {
+        int64_t s = F.off + i;
+        const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+        float acc[FD];
+#pragma unroll
+        for (int c = 0; c < FD; ++c) acc[c] = 0.f;
+        for_stencil(F, g, px, py, pz, [&](int32_t j) {
+            double d2 = pdist2(px, py, pz, (double)g.sx[j], (double)g.sy[j], (double)g.sz[j]);
+            if (!(d2 > 0.0 && d2 <= r2)) return;
+            float w = (float)(1.0 / sqrt(d2));
+            const float *sj = spfh + (int64_t)j * FD;
+#pragma unroll
+            for (int c = 0; c < FD; ++c) acc[c] = fmaf(sj[c], w, acc[c]);
+        });
+        int k = knb[s];
+        float ik = k > 0 ? 1.0f / (float)k : 0.0f;
+        const float *si = spfh + s * FD;
+        float f[FD];
+#pragma unroll
+        for (int c = 0; c < FD; ++c) f[c] = si[c] + acc[c] * ik;
+        ok = k >= 1;
+#pragma unroll
+        for (int blk3 = 0; blk3 < 3; ++blk3) {
+            float sum = 0.f;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) sum += f[NB * blk3 + c];
+            if (sum > 0.f) {
+                float inv = 1.0f / sum;
+#pragma unroll
+                for (int c = 0; c < NB; ++c) f[NB * blk3 + c] *= inv;
+            } else {
+                ok = false;
+            }
+        }
+        int64_t o = F.off + sorig[s];
+        float *dst = Fout + o * FD;
+#pragma unroll
+        for (int c = 0; c < FD; ++c) dst[c] = ok ? f[c] : 0.f;
+        valid[o] = ok ? 1 : 0;
+    }
+    // per-pair count of valid descriptors
+    unsigned long long bal = __ballot(ok);
+    __shared__ int cnt[4];
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0 && ps && F.pair >= 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += cnt[w];
+        if (t) atomicAdd(&ps[F.pair].n_valid[b.frag & 1], (unsigned long long)t);
+    }
+}
+
+hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairState *ps, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
+    double r2 = (double)r_feature * (double)r_feature;
+    hipLaunchKernelGGL(k_fpfh, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
+                       (const int32_t *)g.sorig, (const float *)d.spfh, (const int32_t *)d.knb, r2, d.F, d.valid, ps);
+    return hipGetLastError();
+}
+
+}  // namespace lsr

@@ -1,0 +1,195 @@
+// Internal declarations shared by the HIP translation units of liblsr.
+//
+// Data model.  A launch works on a batch of fragments (two per pair: P at
+// 2b, Q at 2b+1).  Points of all fragments live in one internal index space
+// [0, Ntot): fragment f owns [Frag::off, Frag::off + Frag::n).  Each stage is
+// one kernel over the whole batch, so the launch count does not grow with the
+// number of pairs.  A block of a per-point kernel never spans two fragments:
+// the host builds a block table (fragment, first point) per block size.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lsr.h"
+
+namespace lsr {
+
+constexpr int FD = 33;          // descriptor length: 3 features x 11 bins
+constexpr int NB = 11;          // bins per feature
+constexpr int PK = 32;          // packed screen row: 30 projected dims + 2 norm slots
+
+struct Frag {
+    const float *src[6];        // caller's SoA arrays for this fragment (already offset)
+    int64_t off;                // first internal point index
+    int32_t n;                  // points
+    int32_t partner;            // the other fragment of the pair, or -1
+    int64_t cell_off;           // first cell of this fragment's grid table
+    int32_t cell_cap;           // cells reserved for the grid table
+    int32_t pair;               // pair index, or -1
+    int64_t pk_off;             // first packed screen row (rows padded to a multiple of 128)
+    int32_t blk256_first;       // index of the fragment's first entry in the 256-point block table
+    int32_t pad0;
+    // filled on the device by the grid kernels
+    float ox, oy, oz, cell;     // grid origin (bounding-box minimum) and cell edge
+    int32_t gx, gy, gz, pad;    // grid dimensions
+    uint32_t bmin[3], bmax[3];  // bounding box, order-preserving integer encoding
+};
+
+struct Blk {                    // one entry of a block table
+    int32_t frag;
+    int32_t start;              // first point of the block, relative to the fragment
+};
+
+// Per-pair counters and scalars accumulated across stages.
+struct PairState {
+    unsigned long long n_valid[2];
+    unsigned long long n_recip;
+    unsigned long long n_consistent;
+    unsigned long long n_inliers;
+    unsigned long long sum_d2_fixed;   // inlier squared distances, fixed point
+    unsigned long long n_fallback;
+    unsigned long long trials_passed;
+    double T[16];
+    double energy, mu_final;
+    int32_t status, iters;
+    int64_t k_off;                     // first consistent correspondence in the compact list
+    float mean_desc[PK];               // centring vector of the bf16 screen (projected space)
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ double pdist2(double xi, double yi, double zi, double xj, double yj, double zj) {
+    double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    return __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+}
+
+__device__ __forceinline__ uint32_t f2ord(float f) {   // order-preserving float -> uint
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __host__ __forceinline__ float ord2f(uint32_t u) {
+    uint32_t v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+#ifdef __HIP_DEVICE_COMPILE__
+    return __uint_as_float(v);
+#else
+    float f; __builtin_memcpy(&f, &v, 4); return f;
+#endif
+}
+
+// Cell coordinates of a point in a fragment's grid (double precision keeps
+// |cell(a) - cell(b)| <= 1 whenever |a - b| <= r < cell).
+__device__ __forceinline__ void cell_of(const Frag &F, double x, double y, double z, int &cx, int &cy, int &cz) {
+    double c = (double)F.cell;
+    cx = (int)floor((x - (double)F.ox) / c);
+    cy = (int)floor((y - (double)F.oy) / c);
+    cz = (int)floor((z - (double)F.oz) / c);
+}
+
+// ---------------------------------------------------------------- workspace views
+
+struct GridBufs {              // built per batch by build_grids()
+    Frag *frag;                // device, nfrag
+    int nfrag;
+    int64_t ntot;              // total points
+    int64_t ncells;            // total cells
+    int32_t *cell_of_pt;       // internal index -> linear cell (within fragment table)
+    int32_t *cstart;           // ncells + 1: global sorted position of each cell
+    int32_t *ccount;           // ncells
+    int32_t *cursor;           // ncells, scatter cursor
+    int32_t *tmp;              // ntot, unstable scatter
+    float *sx, *sy, *sz;       // sorted coordinates
+    float *snx, *sny, *snz;    // sorted input normals
+    int32_t *sorig;            // sorted position -> original index within the fragment
+    Blk *blk256; int nblk256;  // block tables: 256 points per block
+    Blk *blk512; int nblk512;  // 512 points per block
+    int64_t *frag_off;         // nfrag + 1 internal offsets (device)
+    int64_t pk_rows;           // packed screen rows (each fragment padded to a multiple of 128)
+};
+
+struct DescBufs {
+    double *nx, *ny, *nz;      // estimated normals, sorted order
+    float *spfh;               // sorted order, ntot x 33
+    int32_t *knb;              // neighbour count within r_feature, sorted order
+    float *F;                  // descriptors, original order (fragment-relative via Frag::off), ntot x 33
+    int32_t *valid;            // original order
+    uint16_t *pk;              // bf16 packed screen rows, original order, ntot x 32
+};
+
+struct MatchBufs {
+    int32_t *nn;               // original order: nearest neighbour (index in partner fragment)
+    float *dist;
+    uint8_t *mutual;           // original order
+    int32_t *flag;             // consistency flags, original order (int32 for the scan)
+    int32_t *kpos;             // exclusive scan of flags over the batch
+    float *kp, *kq;            // consistent correspondences, compacted: xyz of p and q (3 floats each)
+    int32_t *ki;               // compacted P index of each consistent correspondence
+};
+
+struct TrialBlk {              // consistency trials handled by one block
+    int32_t pair;
+    int32_t pad;
+    int64_t first;             // first trial index of the block
+    int64_t count;             // trials of this pair (all blocks)
+};
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t build_grids(GridBufs &g, float r_cell, hipStream_t s);
+hipError_t launch_normals(const GridBufs &g, float r_normal, DescBufs &d, double *nrm_orig, hipStream_t s);
+hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, DescBufs &d, hipStream_t s);
+hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStream_t s);
+hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairState *ps, hipStream_t s);
+hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s);
+hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
+                              float tau, uint64_t seed, hipStream_t s);
+hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);
+hipError_t launch_gnc(const GridBufs &g, const MatchBufs &m, PairState *ps, int npairs, const lsr_params &prm,
+                      hipStream_t s);
+hipError_t launch_gnc_direct(const double *p, const double *q, int64_t m, const lsr_params &prm, PairState *ps,
+                             hipStream_t s);
+hipError_t launch_verify(const GridBufs &g, const DescBufs &d, PairState *ps, float delta, int normal_check,
+                         float normal_cos, hipStream_t s);
+hipError_t launch_finalize(const GridBufs &g, PairState *ps, int npairs, const lsr_params &prm, lsr_result *out,
+                           hipStream_t s);
+hipError_t launch_align_loss(const float *const P[3], const float *const Q[3], const int32_t *corr,
+                             const int32_t *corr_prob, int64_t m_tot, const double *T, const double *mu,
+                             const double *dE, double *partial, int64_t nblocks, const int64_t *blk_first,
+                             const int32_t *blk_prob_first, int nprob, double *E_out, float *const dP[3],
+                             float *const dQ[3], double *dxi, hipStream_t s);
+
+// Optional stage timing: when enabled, launchers record an event after each
+// named step on the launch stream (eager runs only, never under capture).
+void tmark(const char *name, hipStream_t s);
+
+// device scans
+hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+
+template <typename T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+template <typename T>
+inline hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)nb), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_copy(T *dst, const T *src, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+template <typename T>
+inline hipError_t copy(T *dst, const T *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)nb), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace lsr

@@ -1,0 +1,414 @@
+// Descriptor nearest neighbours screened on the matrix cores (bf16 inputs,
+// float32 accumulation), re-ranked exactly, with a proof that the re-ranked
+// winner is the float32 scan's winner or a float32 rescan of the row.
+//
+// Packing.  Each 11-bin block of an FPFH descriptor sums to 1, so a distance
+// between two descriptors only sees the sum-free part of each block: with the
+// Helmert contrasts h_k = (x_0 + .. + x_{k-1} - k x_k) / sqrt(k (k+1)),
+// k = 1..10, the 33-vector maps to y (30 numbers) with |F_i - F_j| = |y_i - y_j|.
+// y is centred on the pair's mean descriptor (distances unchanged, smaller
+// magnitudes, smaller bf16 error).  A candidate row is [y_j, hi_j, lo_j] with
+// hi + lo = -|y_j|^2 / 2 split across two bf16 values; a query row is
+// [y_i, 1, 1].  One 16x16x32 bf16 MFMA then gives
+//   s_ij = y_i . y_j - |y_j|^2 / 2 = (|y_i|^2 - D_ij) / 2,
+// so the best candidate maximises s.  K = 32 exactly: no padding lanes.
+//
+// Screen.  A wave owns 8 blocks of 16 queries and sweeps the partner's rows
+// 16 at a time from LDS (chunks of 128 rows, double buffered).  Lane l sees
+// query column l % 16 and candidate rows 4 (l / 16) + {0..3} of every tile
+// (lane group g = l / 16).  Per chunk a lane keeps only the maximum score;
+// across chunks it keeps the best chunk and the second-best chunk maximum.
+//
+// Certification.  With bf16 round-to-nearest inputs and float32
+// accumulation, |s~ - s| <= E_i = 2^-8 |y_i| max_j |y_j| + 2^-18 max_j |y_j|^2
+// (plus rounding slack).  The rows of each group's best chunk are re-ranked
+// with the exact float32 distance d2_row; every row outside them has
+// D >= |y_i|^2 - 2 (A2 + E_i), A2 the largest second-best chunk maximum.  If
+// the re-ranked minimum is below that bound it is the float32 scan's answer;
+// otherwise the row is rescanned exactly.
+#include "match_common.h"
+
+namespace lsr {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int SW = 4;              // waves per block
+constexpr int SQB = 8;             // 16-query blocks per wave
+constexpr int CH = 8;              // 16-row tiles per chunk
+constexpr int CROWS = CH * 16;     // rows per chunk (128)
+
+__device__ __forceinline__ uint16_t f2bf(float f) {     // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct ScreenScratch {
+    float *mean;          // (nfrag/2 + 1) x 32: projected centring vector per pair
+    float *part;          // nblk256 x 34: per-block sums of valid descriptors and their count
+    uint32_t *ymax;       // nfrag: max |y| (float bits)
+    float *yn2;           // pk_rows: |y|^2
+    int32_t *c1;          // ntot x 4: best chunk per lane group
+    float *v2;            // ntot x 4: second-best chunk maximum per lane group
+    int32_t *fb_row, *fb_frag, *fb_count;
+};
+
+static ScreenScratch carve(void *base, const GridBufs &g, int64_t pk_rows) {
+    char *p = (char *)base;
+    auto take = [&](size_t bytes) { char *r = p; p += (bytes + 255) & ~size_t(255); return r; };
+    ScreenScratch s;
+    s.mean = (float *)take(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
+    s.part = (float *)take(sizeof(float) * 34 * (size_t)std::max(g.nblk256, 1));
+    s.ymax = (uint32_t *)take(sizeof(uint32_t) * (size_t)std::max(g.nfrag, 1));
+    s.yn2 = (float *)take(sizeof(float) * (size_t)std::max<int64_t>(pk_rows, 1));
+    s.c1 = (int32_t *)take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
+    s.v2 = (float *)take(sizeof(float) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
+    s.fb_row = (int32_t *)take(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
+    s.fb_frag = (int32_t *)take(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
+    s.fb_count = (int32_t *)take(256);
+    return s;
+}
+
+size_t match_bf16_scratch(const GridBufs &g, int64_t pk_rows) {
+    size_t t = 0;
+    auto add = [&](size_t bytes) { t += (bytes + 255) & ~size_t(255); };
+    add(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
+    add(sizeof(float) * 34 * (size_t)std::max(g.nblk256, 1));
+    add(sizeof(uint32_t) * (size_t)std::max(g.nfrag, 1));
+    add(sizeof(float) * (size_t)std::max<int64_t>(pk_rows, 1));
+    add(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
+    add(sizeof(float) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
+    add(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
+    add(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
+    add(256);
+    return t;
+}
+
+// ---------------------------------------------------------------- centring
+
+__global__ void __launch_bounds__(256) k_desc_partials(const Frag *frag, const Blk *blk, const float *F,
+                                                       const int32_t *valid, float *part) {
+    __shared__ float sh[4][34];
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fr = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    bool v = i < Fr.n && valid[Fr.off + i];
+    const int w = threadIdx.x >> 6;
+    for (int c = 0; c < 34; ++c) {
+        float x = v ? (c < FD ? F[(Fr.off + i) * FD + c] : 1.0f) : 0.0f;
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[w][c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 34)
+        part[(int64_t)blockIdx.x * 34 + threadIdx.x] = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] +
+                                                     sh[3][threadIdx.x];
+}
+
+// Helmert contrasts of one 11-bin block (orthonormal, orthogonal to all-ones).
+__device__ __forceinline__ void helmert11(const float *x, float *h) {
+    float s = x[0];
+#pragma unroll
+    for (int k = 1; k < NB; ++k) {
+        h[k - 1] = (s - (float)k * x[k]) * rsqrtf((float)(k * (k + 1)));
+        s += x[k];
+    }
+}
+
+// One thread per pair or stand-alone fragment pair: mean descriptor of both
+// fragments (fixed block order), projected.
+__global__ void k_desc_mean(const Frag *frag, int nfrag, const float *part, PairState *ps, float *mean_out) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * b >= nfrag) return;
+    float acc[34];
+    for (int c = 0; c < 34; ++c) acc[c] = 0.f;
+    for (int f = 2 * b; f <= 2 * b + 1 && f < nfrag; ++f) {
+        const Frag &Fr = frag[f];
+        int nb = (Fr.n + 255) / 256;
+        for (int k = 0; k < nb; ++k)
+            for (int c = 0; c < 34; ++c) acc[c] += part[(int64_t)(Fr.blk256_first + k) * 34 + c];
+    }
+    float inv = acc[33] > 0 ? 1.0f / acc[33] : 0.f;
+    float m[FD];
+    for (int c = 0; c < FD; ++c) m[c] = acc[c] * inv;
+    float h[30];
+    for (int k = 0; k < 3; ++k) helmert11(m + NB * k, h + 10 * k);
+    float *dst = mean_out + 32 * b;
+    for (int c = 0; c < 30; ++c) dst[c] = h[c];
+    (void)ps;
+}
+
+__global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
+                                              const float *mean, uint16_t *pk, float *yn2, uint32_t *ymax) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fr = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    int npad = (Fr.n + CROWS - 1) / CROWS * CROWS;
+    if (i >= npad) return;
+    int64_t row = Fr.pk_off + i;
+    uint16_t out[32];
+    float n2 = 0.f;
+    bool v = i < Fr.n && valid[Fr.off + i];
+    if (v) {
+        const float *x = F + (Fr.off + i) * FD;
+        const float *m = mean + 32 * (b.frag >> 1);
+        float h[30];
+        float xb[FD];
+#pragma unroll
+        for (int c = 0; c < FD; ++c) xb[c] = x[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) helmert11(xb + NB * k, h + 10 * k);
+#pragma unroll
+        for (int c = 0; c < 30; ++c) { h[c] -= m[c]; n2 = fmaf(h[c], h[c], n2); out[c] = f2bf(h[c]); }
+        float cc = -0.5f * n2;
+        uint16_t hi = f2bf(cc);
+        out[30] = hi;
+        out[31] = f2bf(cc - bf2f(hi));
+        atomicMax(&ymax[b.frag], __float_as_uint(sqrtf(n2)));
+    } else {
+#pragma unroll
+        for (int c = 0; c < 30; ++c) out[c] = 0;
+        out[30] = f2bf(-1.0e30f);
+        out[31] = 0;
+    }
+    uint4 *dst = (uint4 *)(pk + row * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint4 w;
+        w.x = out[8 * q] | ((uint32_t)out[8 * q + 1] << 16);
+        w.y = out[8 * q + 2] | ((uint32_t)out[8 * q + 3] << 16);
+        w.z = out[8 * q + 4] | ((uint32_t)out[8 * q + 5] << 16);
+        w.w = out[8 * q + 6] | ((uint32_t)out[8 * q + 7] << 16);
+        dst[q] = w;
+    }
+    yn2[row] = n2;
+}
+
+// ---------------------------------------------------------------- screen
+
+struct SBlk {          // one block of the screen: 512 queries of one fragment
+    int32_t frag;
+    int32_t qstart;
+};
+
+__global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk512, const uint16_t *pk,
+                                                    int32_t *c1_out, float *v2_out) {
+    __shared__ __align__(16) uint16_t lds[2][CROWS * 32];     // 2 x 8 KB
+    const Blk b = blk512[blockIdx.x];
+    const Frag &Fq = frag[b.frag];
+    if (Fq.partner < 0) return;
+    const Frag &Fc = frag[Fq.partner];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+
+    // query operands: rows [y, 1, 1] of this wave's 8 blocks of 16 queries
+    bf16x8 B[SQB];
+    const int qw = b.start + wv * SQB * 16;
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) {
+        int q = qw + 16 * k + col;
+        uint4 w = make_uint4(0, 0, 0, 0);
+        if (q < Fq.n) w = *(const uint4 *)(pk + (Fq.pk_off + q) * 32 + 8 * grp);
+        if (grp == 3) w.w = 0x3f803f80u;                      // slots 30, 31 = 1.0
+        B[k] = __builtin_bit_cast(bf16x8, w);
+    }
+    float cm[SQB], v1[SQB], v2[SQB];
+    int32_t c1[SQB];
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) { cm[k] = -INFINITY; v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
+
+    const int nch = (Fc.n + CROWS - 1) / CROWS;
+    const uint4 *src = (const uint4 *)(pk + Fc.pk_off * 32);   // 4 uint4 per row
+    // stage chunk 0
+    uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0;
+    if (nch > 0) { r0 = src[threadIdx.x]; r1 = src[threadIdx.x + 256]; }
+    ((uint4 *)lds[0])[threadIdx.x] = r0;
+    ((uint4 *)lds[0])[threadIdx.x + 256] = r1;
+    __syncthreads();
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) {
+            const uint4 *nx = src + (int64_t)(ch + 1) * CROWS * 4;
+            r0 = nx[threadIdx.x];
+            r1 = nx[threadIdx.x + 256];
+        }
+        const uint16_t *L = lds[buf];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4 *)(L + (t * 16 + col) * 32 + 8 * grp));
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) {
+                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[k], zero, 0, 0, 0);
+                cm[k] = fmaxf(cm[k], fmaxf(acc[0], acc[1]));
+                cm[k] = fmaxf(cm[k], fmaxf(acc[2], acc[3]));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) {
+            float m = cm[k];
+            v2[k] = fmaxf(v2[k], fminf(v1[k], m));
+            c1[k] = m > v1[k] ? ch : c1[k];
+            v1[k] = fmaxf(v1[k], m);
+            cm[k] = -INFINITY;
+        }
+        if (ch + 1 < nch) {
+            ((uint4 *)lds[buf ^ 1])[threadIdx.x] = r0;
+            ((uint4 *)lds[buf ^ 1])[threadIdx.x + 256] = r1;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) {
+        // lane (col, grp) holds rows 4 grp + {0..3} of query column col; the
+        // MFMA output row index is the candidate, the column the query
+        int q = qw + 16 * k + col;
+        if (q < Fq.n) {
+            int64_t o = (Fq.off + q) * 4 + grp;
+            c1_out[o] = c1[k];
+            v2_out[o] = v2[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- re-rank
+
+__global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
+                                                const float *yn2, const uint32_t *ymax, const int32_t *c1,
+                                                const float *v2, int32_t *nn, float *dist, int32_t *fb_row,
+                                                int32_t *fb_frag, int32_t *fb_count, PairState *ps) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fq = frag[b.frag];
+    const int i = b.start + threadIdx.x;
+    bool fb = false;
+    if (i < Fq.n && Fq.partner >= 0) {
+        const Frag &Fc = frag[Fq.partner];
+        const int64_t gi = Fq.off + i;
+        if (!valid[gi]) {
+            nn[gi] = -1;
+            dist[gi] = INFINITY;
+        } else {
+            float q[FD];
+#pragma unroll
+            for (int c = 0; c < FD; ++c) q[c] = F[gi * FD + c];
+            float best = INFINITY;
+            int32_t bj = -1;
+            float a2 = -INFINITY;
+            for (int g = 0; g < 4; ++g) {
+                int32_t ch = c1[gi * 4 + g];
+                a2 = fmaxf(a2, v2[gi * 4 + g]);
+                if (ch < 0) continue;
+                for (int t = 0; t < CH; ++t)
+                    for (int e = 0; e < 4; ++e) {
+                        int32_t j = ch * CROWS + t * 16 + 4 * g + e;
+                        if (j >= Fc.n || !valid[Fc.off + j]) continue;
+                        float x[FD];
+                        const float *xr = F + (Fc.off + j) * FD;
+#pragma unroll
+                        for (int c = 0; c < FD; ++c) x[c] = xr[c];
+                        float d = d2_row(q, x);
+                        if (d < best || (d == best && j < bj)) { best = d; bj = j; }
+                    }
+            }
+            float ym = __uint_as_float(ymax[Fq.partner]);
+            float ny2 = yn2[Fq.pk_off + i];
+            float E = 1.01f * (0.00390625f * sqrtf(ny2) * ym + 3.8147e-6f * ym * ym) + 1e-6f;
+            float L = ny2 - 2.0f * (a2 + E);
+            bool cert = bj >= 0 && (best + 1e-5f * (1.0f + sqrtf(best)) + 2e-5f * best < L);
+            if (a2 == -INFINITY && bj >= 0) cert = true;       // every row was re-ranked
+            if (cert) {
+                nn[gi] = bj;
+                dist[gi] = best;
+            } else {
+                fb = true;
+                int k = atomicAdd(fb_count, 1);
+                fb_row[k] = i;
+                fb_frag[k] = b.frag;
+            }
+        }
+    }
+    unsigned long long bal = __ballot(fb);
+    if ((threadIdx.x & 63) == 0 && bal && ps && Fq.pair >= 0)
+        atomicAdd(&ps[Fq.pair].n_fallback, (unsigned long long)__popcll(bal));
+}
+
+// Exact float32 rescan of the listed rows (grid-stride over the list).
+__global__ void __launch_bounds__(256) k_fallback(const Frag *frag, const float *F, const int32_t *valid,
+                                                  const int32_t *rows, const int32_t *rfrag, const int32_t *count,
+                                                  int32_t *nn, float *dist) {
+    __shared__ float sv[256];
+    __shared__ int32_t si[256];
+    const int n = *count;
+    for (int r = blockIdx.x; r < n; r += gridDim.x) {
+        const Frag &Fq = frag[rfrag[r]];
+        const Frag &Fc = frag[Fq.partner];
+        const int32_t i = rows[r];
+        float q[FD];
+        const float *src = F + (Fq.off + i) * FD;
+#pragma unroll
+        for (int c = 0; c < FD; ++c) q[c] = src[c];
+        float best = INFINITY;
+        int32_t bj = -1;
+        for (int j = threadIdx.x; j < Fc.n; j += 256) {
+            if (!valid[Fc.off + j]) continue;
+            float x[FD];
+            const float *cr = F + (Fc.off + j) * FD;
+#pragma unroll
+            for (int c = 0; c < FD; ++c) x[c] = cr[c];
+            float d = d2_row(q, x);
+            if (d < best) { best = d; bj = j; }
+        }
+        sv[threadIdx.x] = best;
+        si[threadIdx.x] = bj;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                float w2 = sv[threadIdx.x + o];
+                int32_t j2 = si[threadIdx.x + o];
+                float w1 = sv[threadIdx.x];
+                int32_t j1 = si[threadIdx.x];
+                if (w2 < w1 || (w2 == w1 && j2 >= 0 && (j1 < 0 || j2 < j1))) { sv[threadIdx.x] = w2; si[threadIdx.x] = j2; }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            nn[Fq.off + i] = si[0];
+            dist[Fq.off + i] = sv[0];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch,
+                             hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    ScreenScratch S = carve(scratch, g, g.pk_rows);
+    hipError_t e;
+    if ((e = fill<uint32_t>(S.ymax, 0u, g.nfrag, s)) != hipSuccess) return e;
+    if ((e = fill<int32_t>(S.fb_count, 0, 1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_desc_partials, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const float *)d.F, (const int32_t *)d.valid, S.part);
+    float *mean = S.mean;
+    int npair = (g.nfrag + 1) / 2;
+    hipLaunchKernelGGL(k_desc_mean, dim3((npair + 63) / 64), dim3(64), 0, s, (const Frag *)g.frag, g.nfrag,
+                       (const float *)S.part, ps, mean);
+    hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)mean, d.pk, S.yn2, S.ymax);
+    tmark("pack", s);
+    hipLaunchKernelGGL(k_screen, dim3(g.nblk512), dim3(SW * 64), 0, s, (const Frag *)g.frag, (const Blk *)g.blk512,
+                       (const uint16_t *)d.pk, S.c1, S.v2);
+    tmark("screen", s);
+    hipLaunchKernelGGL(k_rerank, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.yn2, (const uint32_t *)S.ymax,
+                       (const int32_t *)S.c1, (const float *)S.v2, m.nn, m.dist, S.fb_row, S.fb_frag, S.fb_count, ps);
+    tmark("rerank", s);
+    unsigned grid = (unsigned)std::min<int64_t>(g.ntot, 2048);
+    hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(256), 0, s, (const Frag *)g.frag, (const float *)d.F,
+                       (const int32_t *)d.valid, (const int32_t *)S.fb_row, (const int32_t *)S.fb_frag,
+                       (const int32_t *)S.fb_count, m.nn, m.dist);
+    return hipGetLastError();
+}
+
+}  // namespace lsr

@@ -1,0 +1,111 @@
+// Verification of the returned pose (Algorithm 1's hypothesis test on the
+// final transform): p is an inlier when some q lies within delta of T p
+// (optionally with normal agreement), found on Q's 3-D grid; inlier ratio =
+// inliers / N_P, fitness = RMS distance of inliers to their nearest q.  The
+// pair is accepted when the solve succeeded, at least min_consistent
+// correspondences survived the consistency filter and the ratio reaches
+// min_inlier_ratio.
+#include "lsr_internal.h"
+
+namespace lsr {
+
+constexpr double FIX_SCALE = 1099511627776.0;   // 2^40: inlier d^2 / delta^2 in fixed point
+
+__global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk, const int32_t *cstart,
+                                                const int32_t *ccount, const float *sx, const float *sy,
+                                                const float *sz, const double *nxa, const double *nya,
+                                                const double *nza, PairState *ps, double delta2, int normal_check,
+                                                double ncos) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &P = frag[b.frag];
+    if ((b.frag & 1) || P.partner < 0) return;
+    const Frag &Q = frag[P.partner];
+    PairState &S = ps[P.pair];
+    int i = b.start + threadIdx.x;
+    bool inl = false;
+    double best = INFINITY;
+    if (i < P.n) {
+        int64_t s = P.off + i;                      // sorted position in P
+        const double *T = S.T;
+        double px = sx[s], py = sy[s], pz = sz[s];
+        double x = T[0] * px + T[1] * py + T[2] * pz + T[3];
+        double y = T[4] * px + T[5] * py + T[6] * pz + T[7];
+        double z = T[8] * px + T[9] * py + T[10] * pz + T[11];
+        double rnx = 0, rny = 0, rnz = 0;
+        if (normal_check) {
+            double a = nxa[s], bb = nya[s], c = nza[s];
+            rnx = T[0] * a + T[1] * bb + T[2] * c;
+            rny = T[4] * a + T[5] * bb + T[6] * c;
+            rnz = T[8] * a + T[9] * bb + T[10] * c;
+        }
+        int cx, cy, cz;
+        cell_of(Q, x, y, z, cx, cy, cz);
+        int x0 = max(cx - 1, 0), x1 = min(cx + 1, Q.gx - 1);
+        if (x0 <= x1) {
+            for (int zz = max(cz - 1, 0); zz <= min(cz + 1, Q.gz - 1); ++zz)
+                for (int yy = max(cy - 1, 0); yy <= min(cy + 1, Q.gy - 1); ++yy) {
+                    int64_t row = Q.cell_off + ((int64_t)zz * Q.gy + yy) * Q.gx;
+                    int32_t kb = cstart[row + x0], ke = cstart[row + x1] + ccount[row + x1];
+                    for (int32_t k = kb; k < ke; ++k) {
+                        if (normal_check && rnx * nxa[k] + rny * nya[k] + rnz * nza[k] < ncos) continue;
+                        double d2 = pdist2(x, y, z, (double)sx[k], (double)sy[k], (double)sz[k]);
+                        best = fmin(best, d2);
+                    }
+                }
+        }
+        inl = best <= delta2;
+    }
+    unsigned long long fx = inl ? (unsigned long long)(best / delta2 * FIX_SCALE) : 0ull;
+    unsigned long long bal = __ballot(inl);
+    for (int o = 32; o > 0; o >>= 1) fx += __shfl_xor(fx, o, 64);
+    if ((threadIdx.x & 63) == 0 && bal) {
+        atomicAdd(&S.n_inliers, (unsigned long long)__popcll(bal));
+        atomicAdd(&S.sum_d2_fixed, fx);
+    }
+}
+
+hipError_t launch_verify(const GridBufs &g, const DescBufs &d, PairState *ps, float delta, int normal_check,
+                         float normal_cos, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    double d2 = (double)delta * (double)delta;
+    hipLaunchKernelGGL(k_verify, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)g.cstart, (const int32_t *)g.ccount, (const float *)g.sx, (const float *)g.sy,
+                       (const float *)g.sz, (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, ps, d2,
+                       normal_check, (double)normal_cos);
+    return hipGetLastError();
+}
+
+__global__ void k_finalize(const Frag *frag, PairState *ps, int npairs, double delta2, int64_t min_cons,
+                           double min_ratio, lsr_result *out) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= npairs) return;
+    const PairState &S = ps[b];
+    lsr_result r;
+    for (int i = 0; i < 16; ++i) r.T[i] = S.T[i];
+    int64_t nP = frag[2 * b].n;
+    r.energy = S.energy;
+    r.mu_final = S.mu_final;
+    r.n_inliers = (int64_t)S.n_inliers;
+    r.inlier_ratio = nP > 0 ? (double)S.n_inliers / (double)nP : 0.0;
+    r.fitness = S.n_inliers ? sqrt((double)S.sum_d2_fixed / FIX_SCALE * delta2 / (double)S.n_inliers) : 0.0;
+    r.n_valid_P = (int64_t)S.n_valid[0];
+    r.n_valid_Q = (int64_t)S.n_valid[1];
+    r.n_recip = (int64_t)S.n_recip;
+    r.n_consistent = (int64_t)S.n_consistent;
+    r.n_fallback_rows = (int64_t)S.n_fallback;
+    r.iters = S.iters;
+    if (S.status == LSR_DEGENERATE) r.status = LSR_DEGENERATE;
+    else r.status = (r.n_consistent >= min_cons && r.inlier_ratio >= min_ratio) ? LSR_ACCEPTED : LSR_REJECTED;
+    out[b] = r;
+}
+
+hipError_t launch_finalize(const GridBufs &g, PairState *ps, int npairs, const lsr_params &prm, lsr_result *out,
+                           hipStream_t s) {
+    if (npairs <= 0) return hipSuccess;
+    double d2 = (double)prm.max_corr * (double)prm.max_corr;
+    hipLaunchKernelGGL(k_finalize, dim3((npairs + 63) / 64), dim3(64), 0, s, (const Frag *)g.frag, ps, npairs, d2,
+                       (int64_t)prm.min_consistent, (double)prm.min_inlier_ratio, out);
+    return hipGetLastError();
+}
+
+}  // namespace lsr

@@ -1,0 +1,175 @@
+"""End-to-end parity of register_pair / register_batch against the oracle,
+batch == per-pair, bf16 == fp32, graph replays, determinism, alignment
+energy and its adjoint."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import POSE_TOL, dev, pair, rot_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1801_01572_amd as lsr
+    lsr.lib()
+    return lsr
+
+
+def _orc_params(orc, L, prm):
+    return orc.default_params(r_normal=prm.r_normal, r_feature=prm.r_feature, max_corr=prm.max_corr,
+                              tau=prm.tau, n_trials=prm.n_trials, gnc_div=prm.gnc_div,
+                              gnc_every=prm.gnc_every, gnc_max_iter=prm.gnc_max_iter,
+                              polish_iter=prm.polish_iter, min_inlier_ratio=prm.min_inlier_ratio,
+                              min_consistent=prm.min_consistent, seed=prm.seed)
+
+
+def _compare(orc, r, o, nnQ_o, cons_o, tie_exempt_ok=True):
+    d = orc.result_dict(o)
+    assert r["n_valid_P"] == d["n_valid_P"] and r["n_valid_Q"] == d["n_valid_Q"]
+    same_c = r["n_recip"] == d["n_recip"]
+    if same_c and r["n_consistent"] == d["n_consistent"]:
+        assert r["status"] == d["status"]
+        if d["status"] != orc.DEGENERATE:
+            ang, tr = rot_err(r["T"], d["T"])
+            assert ang <= POSE_TOL and tr <= POSE_TOL, (ang, tr)
+            assert abs(r["inlier_ratio"] - d["inlier_ratio"]) <= 5.0 / max(1, d["n_inliers"])
+    else:
+        assert tie_exempt_ok
+    return d
+
+
+@pytest.mark.parametrize("cfg,idx,n", [(0, 0, None), (0, 1, None), (5, 0, None), (4, 2, 15000)])
+def test_register_pair_parity(L, orc, cfg, idx, n):
+    pr = pair(cfg, idx, n)
+    print(f"pair cfg={cfg} idx={idx} nP={pr.P.shape[1]} nQ={pr.Q.shape[1]}", flush=True)
+    prm = L.default_params()
+    r = L.register_pair(dev(pr.P), dev(pr.Q), prm)
+    o, nnQ, cons = orc.register_pair(pr.P, pr.Q, _orc_params(orc, L, prm))
+    d = _compare(orc, r, o, nnQ, cons)
+    print(f"  gpu status {r['status']} recip {r['n_recip']} K {r['n_consistent']} | oracle status {d['status']} "
+          f"recip {d['n_recip']} K {d['n_consistent']}; err vs T_gt {rot_err(r['T'], pr.T_gt)}", flush=True)
+    R = r["T"][:3, :3]
+    assert abs(np.linalg.det(R) - 1) < 1e-12 and np.abs(R.T @ R - np.eye(3)).max() < 1e-12
+
+
+def test_bf16_equals_fp32_end_to_end(L):
+    pr = pair(4, 4, 20000)
+    a = L.register_pair(dev(pr.P), dev(pr.Q), L.default_params(precision=L.FP32))
+    b = L.register_pair(dev(pr.P), dev(pr.Q), L.default_params(precision=L.BF16_SCREEN))
+    for k in a:
+        if k != "n_fallback_rows":
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def _batch(prs):
+    P = np.concatenate([p.P for p in prs], 1)
+    Q = np.concatenate([p.Q for p in prs], 1)
+    offP = np.concatenate([[0], np.cumsum([p.P.shape[1] for p in prs])])
+    offQ = np.concatenate([[0], np.cumsum([p.Q.shape[1] for p in prs])])
+    return P, Q, offP, offQ
+
+
+def test_batch_equals_pairs_and_replays(L):
+    prs = [pair(2, k, (int(n1), int(n2))) for k, (n1, n2) in enumerate([(3000, 5000), (700, 9000), (6000, 200),
+                                                                         (0, 100), (4000, 4000)])]
+    P, Q, offP, offQ = _batch(prs)
+    Pd, Qd = dev(P), dev(Q)
+    for prec in (L.FP32, L.BF16_SCREEN):
+        prm = L.default_params(precision=prec)
+        want = [L.register_pair(dev(p.P), dev(p.Q), prm) for p in prs]
+        outs = []
+        for rep in range(3):
+            outs.append(L.register_batch(Pd, Qd, offP, offQ, prm))
+            torch.cuda.synchronize()
+            _ = (Pd * 2).sum().item()                     # unrelated eager work between replays
+        for res in outs:
+            for b in range(len(prs)):
+                for k in want[b]:
+                    assert np.array_equal(np.asarray(res[b][k]), np.asarray(want[b][k])), (prec, b, k)
+    assert want[3]["status"] == L.DEGENERATE
+
+
+def test_deterministic(L):
+    pr = pair(4, 6, 12000)
+    a = L.register_pair(dev(pr.P), dev(pr.Q))
+    b = L.register_pair(dev(pr.P.copy()), dev(pr.Q.copy()))
+    for k in a:
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_invalid_arguments(L):
+    import paper_1801_01572_amd._lib as lib
+    pr = pair(0, 2)
+    P = dev(pr.P)
+    with pytest.raises(lib.LsrError):
+        L.register_pair(P, dev(pr.Q), L.default_params(r_feature=-1.0))
+    with pytest.raises(lib.LsrError):
+        L.register_pair(P, dev(pr.Q), L.default_params(tau=1.5))
+    with pytest.raises(lib.LsrError):
+        L.register_batch(P, dev(pr.Q), [0, 10 ** 7], [0, 5], L.default_params())
+
+
+def test_align_loss_and_adjoint(L, orc):
+    rng = np.random.default_rng(2)
+    nprob = 5
+    Ps, Qs, corr, coff, Ts, mus = [], [], [], [0], [], []
+    baseP = baseQ = 0
+    for k in range(nprob):
+        n = int(rng.integers(50, 3000))
+        p = rng.uniform(-1, 1, (n, 3))
+        th = rng.uniform(0, 1)
+        R = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+        T = np.eye(4); T[:3, :3] = R; T[:3, 3] = rng.uniform(-0.3, 0.3, 3)
+        q = p @ R.T + T[:3, 3] + rng.normal(0, 0.01, (n, 3))
+        q[: n // 3] += rng.normal(0, 0.3, (n // 3, 3))
+        Ps.append(p); Qs.append(q)
+        idx = np.arange(n)
+        corr.append(np.stack([baseP + idx, baseQ + idx], 1))
+        baseP += n; baseQ += n
+        coff.append(coff[-1] + n)
+        Ts.append(T); mus.append(rng.uniform(1e-4, 1e-2))
+    Pf = np.concatenate(Ps).astype(np.float32)
+    Qf = np.concatenate(Qs).astype(np.float32)
+    C = np.concatenate(corr).astype(np.int32)
+    Td, mud = dev(np.stack(Ts)), dev(np.array(mus))
+    E = L.align_loss(dev(Pf.T), dev(Qf.T), dev(C), coff, Td, mud).cpu().numpy()
+    dE = rng.uniform(0.5, 2.0, nprob)
+    dP, dQ, dxi = [t.cpu().numpy() for t in L.align_loss_backward(dev(Pf.T), dev(Qf.T), dev(C), coff, Td, mud,
+                                                                  dev(dE))]
+    for k in range(nprob):
+        s = slice(coff[k], coff[k + 1])
+        Eo, gp, gq, gx = orc.align_loss(Pf[s].astype(np.float64), Qf[s].astype(np.float64), Ts[k], mus[k])
+        assert abs(E[k] - Eo) <= 1e-12 * (1 + abs(Eo))
+        assert np.abs(dxi[k] - dE[k] * gx).max() <= 1e-10 * (1 + np.abs(dE[k] * gx).max())
+        assert np.abs(dP[:, s].T - dE[k] * gp).max() <= 1e-6 * (1 + np.abs(gp).max())
+        assert np.abs(dQ[:, s].T - dE[k] * gq).max() <= 1e-6 * (1 + np.abs(gq).max())
+
+
+def test_autograd_function_fd(L):
+    rng = np.random.default_rng(3)
+    n = 400
+    p = rng.uniform(-1, 1, (n, 3))
+    q = p + rng.normal(0, 0.05, (n, 3))
+    C = np.stack([np.arange(n), np.arange(n)], 1).astype(np.int32)
+    P = dev(p.T.astype(np.float32)).requires_grad_(True)
+    Q = dev(q.T.astype(np.float32)).requires_grad_(True)
+    T = dev(np.eye(4)[None])
+    mu = dev(np.array([0.004]))
+    xi = torch.zeros((1, 6), dtype=torch.float64, device="cuda", requires_grad=True)
+    E = L.AlignLoss.apply(P, Q, dev(C), [0, n], T, mu, xi)
+    E.sum().backward()
+    h = 1e-4
+    for k in range(6):
+        Ts = []
+        for s in (1, -1):
+            w = np.zeros(3); v = np.zeros(3)
+            (w if k < 3 else v)[k % 3] = s * h
+            K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+            D = np.eye(4); D[:3, :3] = np.eye(3) + K + 0.5 * K @ K; D[:3, 3] = v
+            Ts.append(dev((D @ np.eye(4))[None]))
+        Ep = L.align_loss(P.detach(), Q.detach(), dev(C), [0, n], Ts[0], mu).item()
+        Em = L.align_loss(P.detach(), Q.detach(), dev(C), [0, n], Ts[1], mu).item()
+        fd = (Ep - Em) / (2 * h)
+        assert abs(fd - xi.grad[0, k].item()) <= 1e-4 * (1 + abs(fd))

@@ -1,0 +1,185 @@
+"""Stage-by-stage parity of the HIP path against the CPU FP64 oracle, each
+stage fed the oracle's own inputs for that stage.  Calls go through the C ABI
+(paper_1801_01572_amd -> liblsr.so)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import DESC_RTOL, MARGIN, NORMAL_TOL, desc_exempt, dev, pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1801_01572_amd as lsr
+    lsr.lib()
+    return lsr
+
+
+CASES = [(0, 0, None), (4, 1, 12000), (1, 2, 9000)]
+
+
+@pytest.mark.parametrize("cfg,idx,n", CASES)
+def test_normals_parity(L, orc, cfg, idx, n):
+    pr = pair(cfg, idx, n)
+    print(f"normals cfg={cfg} idx={idx} n={pr.P.shape[1]}", flush=True)
+    for cloud in (pr.P, pr.Q):
+        want, gap, ori, cnt = orc.normals(cloud, 0.025)
+        got = L.stage_normals(dev(cloud), 0.025).cpu().numpy()
+        torch.cuda.synchronize()
+        ok = ((gap < 0) | (gap > 1e-7)) & (ori > 1e-9)
+        assert ok.mean() > 0.999
+        err = np.abs(got - want).max(1)
+        assert err[ok].max() <= NORMAL_TOL, err[ok].max()
+        fb = gap < 0                                   # fewer than 3 points: normalised input, exact
+        assert np.array_equal(got[fb], want[fb])
+
+
+@pytest.mark.parametrize("cfg,idx,n", CASES)
+def test_fpfh_parity(L, orc, cfg, idx, n):
+    pr = pair(cfg, idx, n)
+    print(f"fpfh cfg={cfg} idx={idx} n={pr.P.shape[1]}", flush=True)
+    for cloud in (pr.P, pr.Q):
+        nrm, gap, ori, _ = orc.normals(cloud, 0.025)
+        F, v, exempt = desc_exempt(orc, cloud, nrm, gap, ori, 0.05)
+        Fg, vg = L.stage_fpfh(dev(cloud[:3]), dev(nrm), 0.05)
+        Fg, vg = Fg.cpu().numpy().astype(np.float64), vg.cpu().numpy()
+        assert np.array_equal(vg, v)
+        keep = (v == 1) & ~exempt
+        assert keep.mean() > 0.99
+        rel = np.linalg.norm(Fg[keep] - F[keep], axis=1) / np.linalg.norm(F[keep], axis=1)
+        print(f"  max rel {rel.max():.2e}  exempt {exempt.sum()}", flush=True)
+        assert rel.max() <= DESC_RTOL
+
+
+def _oracle_descriptors(orc, pr):
+    out = []
+    for cloud in (pr.P, pr.Q):
+        nrm, *_ = orc.normals(cloud, 0.025)
+        F, v, _, _ = orc.fpfh(cloud[:3], nrm, 0.05)
+        out += [F, v]
+    return out
+
+
+@pytest.mark.parametrize("cfg,idx,n", CASES)
+def test_match_parity_fp32_and_bf16(L, orc, cfg, idx, n):
+    """Injected oracle descriptors (rounded to float32): indices equal the
+    oracle's outside the near-tie margin; the bf16 screen returns the float32
+    scan's bits exactly."""
+    pr = pair(cfg, idx, n)
+    print(f"match cfg={cfg} idx={idx} n={pr.P.shape[1]}", flush=True)
+    F, vF, G, vG = _oracle_descriptors(orc, pr)
+    m = orc.match(F, vF, G, vG)
+    tP, tQ = orc.tie_flags(F, G, m)
+    args = (dev(F.astype(np.float32)), dev(vF), dev(G.astype(np.float32)), dev(vG))
+    nnQ, dQ, nnP, dP, _ = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.FP32)]
+    okP, okQ = ~tP, ~tQ
+    assert np.array_equal(nnQ[okP], m["nnQ"][okP])
+    assert np.array_equal(nnP[okQ], m["nnP"][okQ])
+    print(f"  tie-exempt rows {tP.mean():.4f}, exempt rows that still agree "
+          f"{(nnQ[tP] == m['nnQ'][tP]).mean() if tP.any() else 1.0:.3f}", flush=True)
+    b = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.BF16_SCREEN)]
+    assert np.array_equal(b[0], nnQ) and np.array_equal(b[2], nnP)
+    assert np.array_equal(b[1].view(np.uint32), dQ.view(np.uint32))
+    assert np.array_equal(b[3].view(np.uint32), dP.view(np.uint32))
+    print(f"  bf16 fallback rows {int(b[4][0])} of {len(nnQ) + len(nnP)}", flush=True)
+
+
+def test_match_bf16_random_and_edge_sizes(L):
+    """bf16 screen == float32 scan on random descriptors, ragged sizes,
+    invalid rows, exact duplicates (ties) and an empty side."""
+    rng = np.random.default_rng(0)
+    for nP, nQ in [(1, 1), (17, 300), (1000, 129), (4099, 2500), (0, 50), (60, 0)]:
+        def desc(n):
+            x = rng.random((n, 33)) ** 4
+            x = x.reshape(n, 3, 11)
+            x /= x.sum(2, keepdims=True)
+            return x.reshape(n, 33).astype(np.float32)
+        F, G = desc(nP), desc(nQ)
+        if nP > 10 and nQ > 10:
+            G[:5] = F[:5]
+            G[5] = G[6]
+        vF = (rng.random(nP) > 0.05).astype(np.int32)
+        vG = (rng.random(nQ) > 0.05).astype(np.int32)
+        args = (dev(F), dev(vF), dev(G), dev(vG))
+        a = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.FP32)]
+        b = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.BF16_SCREEN)]
+        for k in range(4):
+            assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), (nP, nQ, k)
+        # float32 scan == brute force in numpy's float64 on non-tied rows
+        if nP and nQ:
+            D = ((F[:, None, :].astype(np.float64) - G[None].astype(np.float64)) ** 2).sum(2)
+            D[:, vG == 0] = np.inf
+            srt = np.sort(D, 1)
+            clear = (vF == 1) & (srt[:, 1] - srt[:, 0] > 1e-5)
+            assert np.array_equal(a[0][clear], np.argmin(D, 1)[clear])
+            assert (a[0][vF == 0] == -1).all()
+
+
+def test_consistency_parity(L, orc):
+    pr = pair(4, 3, 15000)
+    F, vF, G, vG = _oracle_descriptors(orc, pr)
+    m = orc.match(F, vF, G, vG)
+    mut = orc.mutual(m["nnQ"], m["nnP"])
+    for T in (1, 1000, orc.default_trials(pr.P.shape[1])):
+        want, npass = orc.consistency(pr.P[:3], pr.Q[:3], m["nnQ"], mut, T, 0.9, 1234)
+        flag, passed = L.stage_consistency(dev(pr.P[:3]), dev(pr.Q[:3]), dev(m["nnQ"]),
+                                           dev(mut.astype(np.uint8)), T, 0.9, 1234)
+        assert np.array_equal(flag.cpu().numpy().astype(bool), want)
+        assert int(passed.cpu()[0]) == npass
+    # closed form: Q = 2 P rejects everything
+    P = pr.P[:3]
+    ident = np.arange(P.shape[1], dtype=np.int32)
+    flag, passed = L.stage_consistency(dev(P), dev((2 * P).astype(np.float32)), dev(ident),
+                                       dev(np.ones(P.shape[1], np.uint8)), 5000, 0.9, 1)
+    assert int(passed.cpu()[0]) == 0 and not flag.cpu().numpy().any()
+
+
+def _corr(rng, n, frac_out=0.5, noise=0.003):
+    a = rng.normal(size=3)
+    a /= np.linalg.norm(a)
+    th = rng.uniform(0.1, 1.0)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    R = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K
+    t = rng.uniform(-0.5, 0.5, 3)
+    p = rng.uniform(-1.5, 1.5, (n, 3))
+    q = p @ R.T + t + rng.normal(0, noise, (n, 3))
+    out = rng.random(n) < frac_out
+    q[out] = rng.uniform(-2, 2, (out.sum(), 3))
+    return p, q
+
+
+@pytest.mark.parametrize("n,frac", [(3, 0.0), (200, 0.3), (5000, 0.6), (40000, 0.5)])
+def test_gnc_parity(L, orc, n, frac):
+    rng = np.random.default_rng(n)
+    p, q = _corr(rng, n, frac)
+    st, T, mu, E, it = orc.gnc(p, q)
+    Tg, info = L.stage_gnc(dev(p), dev(q))
+    Tg, info = Tg.cpu().numpy(), info.cpu().numpy()
+    assert int(info[0]) == st and int(info[1]) == it
+    assert np.abs(Tg - T).max() <= 1e-9
+    assert abs(info[3] - E) <= 1e-9 * (1 + E)
+    R = Tg[:3, :3]
+    assert abs(np.linalg.det(R) - 1) < 1e-12
+
+
+def test_gnc_degenerate(L, orc):
+    s = np.linspace(0, 1, 50)[:, None] * np.array([[1.0, 2.0, 3.0]])
+    Tg, info = L.stage_gnc(dev(s), dev(s + 0.1))
+    assert int(info.cpu()[0]) == 3 == orc.gnc(s, s + 0.1)[0]
+    Tg, info = L.stage_gnc(dev(np.zeros((2, 3))), dev(np.zeros((2, 3))))
+    assert int(info.cpu()[0]) == 3
+
+
+@pytest.mark.parametrize("normal_check", [0, 1])
+def test_verify_parity(L, orc, normal_check):
+    pr = pair(4, 5, 15000)
+    nP, *_ = orc.normals(pr.P, 0.025)
+    nQ, *_ = orc.normals(pr.Q, 0.025)
+    for T in (pr.T_gt, np.eye(4)):
+        ni, ratio, fit = orc.verify(pr.P, nP, pr.Q, nQ, T, 0.015, normal_check)
+        info = L.stage_verify(dev(pr.P[:3]), dev(nP), dev(pr.Q[:3]), dev(nQ), dev(T), 0.015,
+                              normal_check).cpu().numpy()
+        assert abs(info[0] - ni) <= 2                 # decisions at |Tp - q| = delta within rounding
+        assert abs(info[2] - fit) <= 1e-6 * (1 + fit)
