@@ -339,22 +339,12 @@ static inline double bin_margin(double xbin) {    /* distance to the nearest int
     return fabs(xbin - r);
 }
 
-/* returns 0 if the pair is skipped (degenerate frame) */
-static int pair_features(const double pi[3], const double ni[3], const double pj[3], const double nj[3],
-                         int bins[3], double *margin) {
-    double dv[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
-    double d = sqrt(fma(dv[2], dv[2], fma(dv[1], dv[1], dv[0] * dv[0])));
-    double e[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
-    double ci = ni[0] * e[0] + ni[1] * e[1] + ni[2] * e[2];
-    double cj = nj[0] * e[0] + nj[1] * e[1] + nj[2] * e[2];
-    const double *u, *nt;
-    double es[3];
-    if (ci >= -cj) { u = ni; nt = nj; es[0] = e[0]; es[1] = e[1]; es[2] = e[2]; }
-    else { u = nj; nt = ni; es[0] = -e[0]; es[1] = -e[1]; es[2] = -e[2]; }
-    double m = fabs(ci + cj);
+/* Features of a pair seen from source u (normal n_s) towards the target
+ * normal nt along es; returns 0 for a degenerate frame. */
+static int features_from(const double *u, const double *nt, const double es[3], int bins[3], double *mb) {
     double v[3] = {u[1] * es[2] - u[2] * es[1], u[2] * es[0] - u[0] * es[2], u[0] * es[1] - u[1] * es[0]};
     double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    if (vn <= 1e-12) { *margin = m; return 0; }
+    if (vn <= 1e-12) return 0;
     for (int a = 0; a < 3; ++a) v[a] /= vn;
     double w[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
     double alpha = v[0] * nt[0] + v[1] * nt[1] + v[2] * nt[2];
@@ -364,11 +354,38 @@ static int pair_features(const double pi[3], const double ni[3], const double pj
     double xp = NB * (phi + 1.0) / 2.0;
     double xt = NB * (theta + M_PI) / (2.0 * M_PI);
     bins[0] = bin_of(xa); bins[1] = bin_of(xp); bins[2] = bin_of(xt);
-    double mb = bin_margin(xa);
-    if (bin_margin(xp) < mb) mb = bin_margin(xp);
-    if (bin_margin(xt) < mb) mb = bin_margin(xt);
-    *margin = m < mb ? m : mb;
+    double m = bin_margin(xa);
+    if (bin_margin(xp) < m) m = bin_margin(xp);
+    if (bin_margin(xt) < m) m = bin_margin(xt);
+    *mb = m;
     return 1;
+}
+
+/* Pair (i, j): returns 0 if the pair is skipped (degenerate frame).  The
+ * margin is the smallest distance of a decision to its boundary; the source
+ * test counts only when choosing the other source would change a bin. */
+static int pair_features(const double pi[3], const double ni[3], const double pj[3], const double nj[3],
+                         int bins[3], double *margin) {
+    double dv[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
+    double d = sqrt(fma(dv[2], dv[2], fma(dv[1], dv[1], dv[0] * dv[0])));
+    double e[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
+    double ne[3] = {-e[0], -e[1], -e[2]};
+    double ci = ni[0] * e[0] + ni[1] * e[1] + ni[2] * e[2];
+    double cj = nj[0] * e[0] + nj[1] * e[1] + nj[2] * e[2];
+    int src_i = ci >= -cj;
+    double mb;
+    int ok = src_i ? features_from(ni, nj, e, bins, &mb) : features_from(nj, ni, ne, bins, &mb);
+    double m = ok ? mb : INFINITY;
+    double sw = fabs(ci + cj);
+    if (sw < 1e-6) {                 /* source choice near its boundary: does it matter? */
+        int b2[3]; double mb2;
+        int ok2 = src_i ? features_from(nj, ni, ne, b2, &mb2) : features_from(ni, nj, e, b2, &mb2);
+        int same = ok == ok2 && (!ok || (b2[0] == bins[0] && b2[1] == bins[1] && b2[2] == bins[2]));
+        if (same) { if (ok2 && mb2 < m) m = mb2; }
+        else if (sw < m) m = sw;
+    }
+    *margin = m;
+    return ok;
 }
 
 static void spfh_core(const float *x, const float *y, const float *z, const double *nrm, int64_t n,

@@ -198,7 +198,10 @@ __global__ void __launch_bounds__(256) k_rankfix(const Frag *frag, const Blk *bl
     for (int32_t k = 0; k < cnt; ++k) rank += tmp[st + k] < g;
     int32_t d = st + rank;
     sx[d] = F.src[0][i]; sy[d] = F.src[1][i]; sz[d] = F.src[2][i];
-    snx[d] = F.src[3][i]; sny[d] = F.src[4][i]; snz[d] = F.src[5][i];
+    const bool has_n = F.src[3] && F.src[4] && F.src[5];       // stage calls may omit normals
+    snx[d] = has_n ? F.src[3][i] : 0.f;
+    sny[d] = has_n ? F.src[4][i] : 0.f;
+    snz[d] = has_n ? F.src[5][i] : 0.f;
     sorig[d] = i;
 }
 

@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
             float E = 1.01f * (0.00390625f * sqrtf(ny2) * ym + 3.8147e-6f * ym * ym) + 1e-6f;
             float L = ny2 - 2.0f * (a2 + E);
             bool cert = bj >= 0 && (best + 1e-5f * (1.0f + sqrtf(best)) + 2e-5f * best < L);
-            if (a2 == -INFINITY && bj >= 0) cert = true;       // every row was re-ranked
+            if (a2 == -INFINITY) cert = true;                  // every row was re-ranked (bj may be -1: none valid)
             if (cert) {
                 nn[gi] = bj;
                 dist[gi] = best;

@@ -80,8 +80,10 @@ def test_batch_equals_pairs_and_replays(L):
         prm = L.default_params(precision=prec)
         want = [L.register_pair(dev(p.P), dev(p.Q), prm) for p in prs]
         outs = []
+        side = torch.cuda.Stream()                        # a non-default stream: captured once, then replayed
         for rep in range(3):
-            outs.append(L.register_batch(Pd, Qd, offP, offQ, prm))
+            with torch.cuda.stream(side):
+                outs.append(L.register_batch(Pd, Qd, offP, offQ, prm))
             torch.cuda.synchronize()
             _ = (Pd * 2).sum().item()                     # unrelated eager work between replays
         for res in outs:
