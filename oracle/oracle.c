@@ -339,6 +339,15 @@ static inline double bin_margin(double xbin) {    /* distance to the nearest int
     return fabs(xbin - r);
 }
 
+/* theta lives on a circle: its bins also meet at the cut theta = +-pi
+ * (bin units 0 and 11), where atan2 jumps from +pi to -pi. */
+static inline double theta_margin(double xbin) {
+    double r = floor(xbin + 0.5);
+    if (r < 0) r = 0;
+    if (r > NB) r = NB;
+    return fabs(xbin - r);
+}
+
 /* Features of a pair seen from source u (normal n_s) towards the target
  * normal nt along es; returns 0 for a degenerate frame. */
 static int features_from(const double *u, const double *nt, const double es[3], int bins[3], double *mb) {
@@ -356,7 +365,7 @@ static int features_from(const double *u, const double *nt, const double es[3], 
     bins[0] = bin_of(xa); bins[1] = bin_of(xp); bins[2] = bin_of(xt);
     double m = bin_margin(xa);
     if (bin_margin(xp) < m) m = bin_margin(xp);
-    if (bin_margin(xt) < m) m = bin_margin(xt);
+    if (theta_margin(xt) < m) m = theta_margin(xt);
     *mb = m;
     return 1;
 }
