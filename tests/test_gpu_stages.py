@@ -113,8 +113,8 @@ def test_match_bf16_random_and_edge_sizes(L):
         if nP and nQ:
             D = ((F[:, None, :].astype(np.float64) - G[None].astype(np.float64)) ** 2).sum(2)
             D[:, vG == 0] = np.inf
-            srt = np.sort(D, 1)
-            clear = (vF == 1) & (srt[:, 1] - srt[:, 0] > 1e-5)
+            srt = np.sort(np.concatenate([D, np.full((nP, 1), np.inf)], 1), 1)
+            clear = (vF == 1) & (srt[:, 1] - srt[:, 0] > 1e-5) & np.isfinite(srt[:, 0])
             assert np.array_equal(a[0][clear], np.argmin(D, 1)[clear])
             assert (a[0][vF == 0] == -1).all()
 
