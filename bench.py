@@ -72,15 +72,17 @@ def main():
 
     prm = lsr.default_params(precision=lsr.BF16_SCREEN)
     out = torch.empty(npairs * lsr._lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
+        tw = time.perf_counter()
         lsr.register_batch(Pd, Qd, offP, offQ, prm, out=out, sync=False)
-    torch.cuda.synchronize()
-    log("warmup done")
+        torch.cuda.synchronize()
+        log(f"warmup step {w}: {time.perf_counter() - tw:.2f}s")
     t1 = time.perf_counter()
     for _ in range(args.steps):
         lsr.register_batch(Pd, Qd, offP, offQ, prm, out=out, sync=False)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    log(f"timed {args.steps} steps in {t2 - t1:.2f}s")
     ms_step = (t2 - t1) * 1e3 / args.steps
     value = npairs * args.steps / (t2 - t1)
     res = lsr._lib._parse_results(out, npairs)

@@ -17,7 +17,7 @@ namespace lsr {
 
 constexpr int FD = 33;          // descriptor length: 3 features x 11 bins
 constexpr int NB = 11;          // bins per feature
-constexpr int PK = 32;          // packed screen row: 30 projected dims + 2 norm slots
+constexpr int PK = 64;          // packed screen row: hi and lo bf16 halves, 32 each (30 dims + 2 slots)
 
 struct Frag {
     const float *src[6];        // caller's SoA arrays for this fragment (already offset)
@@ -113,7 +113,7 @@ struct DescBufs {
     int32_t *knb;              // neighbour count within r_feature, sorted order
     float *F;                  // descriptors, original order (fragment-relative via Frag::off), ntot x 33
     int32_t *valid;            // original order
-    uint16_t *pk;              // bf16 packed screen rows, original order, ntot x 32
+    uint16_t *pk;              // bf16 packed screen rows (hi | lo), padded per fragment, pk_rows x 64
 };
 
 struct MatchBufs {

@@ -1,31 +1,33 @@
 // Descriptor nearest neighbours screened on the matrix cores (bf16 inputs,
 // float32 accumulation), re-ranked exactly, with a proof that the re-ranked
-// winner is the float32 scan's winner or a float32 rescan of the row.
+// winner is the float32 scan's winner, or else a float32 rescan of the row.
 //
 // Packing.  Each 11-bin block of an FPFH descriptor sums to 1, so a distance
 // between two descriptors only sees the sum-free part of each block: with the
 // Helmert contrasts h_k = (x_0 + .. + x_{k-1} - k x_k) / sqrt(k (k+1)),
 // k = 1..10, the 33-vector maps to y (30 numbers) with |F_i - F_j| = |y_i - y_j|.
 // y is centred on the pair's mean descriptor (distances unchanged, smaller
-// magnitudes, smaller bf16 error).  A candidate row is [y_j, hi_j, lo_j] with
-// hi + lo = -|y_j|^2 / 2 split across two bf16 values; a query row is
-// [y_i, 1, 1].  One 16x16x32 bf16 MFMA then gives
-//   s_ij = y_i . y_j - |y_j|^2 / 2 = (|y_i|^2 - D_ij) / 2,
-// so the best candidate maximises s.  K = 32 exactly: no padding lanes.
+// magnitudes).  y is split into bf16 hi + lo parts.  A candidate row is
+// [y_hi, c_hi, c_lo | y_lo, 0, 0] with c_hi + c_lo = -|y_j|^2 / 2; a query row
+// is [y_hi, 1, 1 | y_lo, 0, 0].  Three chained 16x16x32 bf16 MFMAs
+// (hi.hi, lo_cand.hi_query, hi_cand.lo_query) give
+//   s_ij = y_i . y_j - |y_j|^2 / 2 = (|y_i|^2 - D_ij) / 2
+// to about 2^-16 relative, so the best candidate maximises s.
 //
-// Screen.  A wave owns 8 blocks of 16 queries and sweeps the partner's rows
+// Screen.  A wave owns 4 blocks of 16 queries and sweeps the partner's rows
 // 16 at a time from LDS (chunks of 128 rows, double buffered).  Lane l sees
 // query column l % 16 and candidate rows 4 (l / 16) + {0..3} of every tile
 // (lane group g = l / 16).  Per chunk a lane keeps only the maximum score;
 // across chunks it keeps the best chunk and the second-best chunk maximum.
 //
-// Certification.  With bf16 round-to-nearest inputs and float32
-// accumulation, |s~ - s| <= E_i = 2^-8 |y_i| max_j |y_j| + 2^-18 max_j |y_j|^2
-// (plus rounding slack).  The rows of each group's best chunk are re-ranked
-// with the exact float32 distance d2_row; every row outside them has
-// D >= |y_i|^2 - 2 (A2 + E_i), A2 the largest second-best chunk maximum.  If
-// the re-ranked minimum is below that bound it is the float32 scan's answer;
-// otherwise the row is rescanned exactly.
+// Certification.  The rows of each group's best chunk are re-ranked with the
+// exact float32 distance d2_row, giving D*.  A row j outside them has a
+// screened score <= A2, the largest second-best chunk maximum.  Only rows
+// with D_ij <= D* can matter, and those have |y_j| <= |y_i| + sqrt(D*) = R,
+// so their screen error is at most E = 2^-15 (|y_i| R + R^2 / 2) (bf16 split
+// rounding and float32 accumulation, with margin).  If
+// D* + slack < |y_i|^2 - 2 (A2 + E) no outside row can win and D* with its
+// index is the float32 scan's answer; otherwise the row is rescanned exactly.
 #include "match_common.h"
 
 namespace lsr {
@@ -34,7 +36,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int SW = 4;              // waves per block
-constexpr int SQB = 8;             // 16-query blocks per wave
 constexpr int CH = 8;              // 16-row tiles per chunk
 constexpr int CROWS = CH * 16;     // rows per chunk (128)
 
@@ -48,7 +49,6 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 struct ScreenScratch {
     float *mean;          // (nfrag/2 + 1) x 32: projected centring vector per pair
     float *part;          // nblk256 x 34: per-block sums of valid descriptors and their count
-    uint32_t *ymax;       // nfrag: max |y| (float bits)
     float *yn2;           // pk_rows: |y|^2
     int32_t *c1;          // ntot x 4: best chunk per lane group
     float *v2;            // ntot x 4: second-best chunk maximum per lane group
@@ -61,7 +61,6 @@ static ScreenScratch carve(void *base, const GridBufs &g, int64_t pk_rows) {
     ScreenScratch s;
     s.mean = (float *)take(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
     s.part = (float *)take(sizeof(float) * 34 * (size_t)std::max(g.nblk256, 1));
-    s.ymax = (uint32_t *)take(sizeof(uint32_t) * (size_t)std::max(g.nfrag, 1));
     s.yn2 = (float *)take(sizeof(float) * (size_t)std::max<int64_t>(pk_rows, 1));
     s.c1 = (int32_t *)take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
     s.v2 = (float *)take(sizeof(float) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
@@ -76,7 +75,6 @@ size_t match_bf16_scratch(const GridBufs &g, int64_t pk_rows) {
     auto add = [&](size_t bytes) { t += (bytes + 255) & ~size_t(255); };
     add(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
     add(sizeof(float) * 34 * (size_t)std::max(g.nblk256, 1));
-    add(sizeof(uint32_t) * (size_t)std::max(g.nfrag, 1));
     add(sizeof(float) * (size_t)std::max<int64_t>(pk_rows, 1));
     add(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
     add(sizeof(float) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
@@ -141,14 +139,14 @@ __global__ void k_desc_mean(const Frag *frag, int nfrag, const float *part, Pair
 }
 
 __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                              const float *mean, uint16_t *pk, float *yn2, uint32_t *ymax) {
+                                              const float *mean, uint16_t *pk, float *yn2) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
     int i = b.start + threadIdx.x;
     int npad = (Fr.n + CROWS - 1) / CROWS * CROWS;
     if (i >= npad) return;
     int64_t row = Fr.pk_off + i;
-    uint16_t out[32];
+    uint16_t hi[32], lo[32];
     float n2 = 0.f;
     bool v = i < Fr.n && valid[Fr.off + i];
     if (v) {
@@ -161,26 +159,32 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
 #pragma unroll
         for (int k = 0; k < 3; ++k) helmert11(xb + NB * k, h + 10 * k);
 #pragma unroll
-        for (int c = 0; c < 30; ++c) { h[c] -= m[c]; n2 = fmaf(h[c], h[c], n2); out[c] = f2bf(h[c]); }
+        for (int c = 0; c < 30; ++c) {
+            h[c] -= m[c];
+            n2 = fmaf(h[c], h[c], n2);
+            hi[c] = f2bf(h[c]);
+            lo[c] = f2bf(h[c] - bf2f(hi[c]));
+        }
         float cc = -0.5f * n2;
-        uint16_t hi = f2bf(cc);
-        out[30] = hi;
-        out[31] = f2bf(cc - bf2f(hi));
-        atomicMax(&ymax[b.frag], __float_as_uint(sqrtf(n2)));
+        hi[30] = f2bf(cc);
+        hi[31] = f2bf(cc - bf2f(hi[30]));
     } else {
 #pragma unroll
-        for (int c = 0; c < 30; ++c) out[c] = 0;
-        out[30] = f2bf(-1.0e30f);
-        out[31] = 0;
+        for (int c = 0; c < 30; ++c) { hi[c] = 0; lo[c] = 0; }
+        hi[30] = f2bf(-1.0e30f);
+        hi[31] = 0;
     }
-    uint4 *dst = (uint4 *)(pk + row * 32);
+    lo[30] = 0;
+    lo[31] = 0;
+    uint4 *dst = (uint4 *)(pk + row * PK);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
+        const uint16_t *o = q < 4 ? hi + 8 * q : lo + 8 * (q - 4);
         uint4 w;
-        w.x = out[8 * q] | ((uint32_t)out[8 * q + 1] << 16);
-        w.y = out[8 * q + 2] | ((uint32_t)out[8 * q + 3] << 16);
-        w.z = out[8 * q + 4] | ((uint32_t)out[8 * q + 5] << 16);
-        w.w = out[8 * q + 6] | ((uint32_t)out[8 * q + 7] << 16);
+        w.x = o[0] | ((uint32_t)o[1] << 16);
+        w.y = o[2] | ((uint32_t)o[3] << 16);
+        w.z = o[4] | ((uint32_t)o[5] << 16);
+        w.w = o[6] | ((uint32_t)o[7] << 16);
         dst[q] = w;
     }
     yn2[row] = n2;
@@ -188,31 +192,33 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
 
 // ---------------------------------------------------------------- screen
 
-struct SBlk {          // one block of the screen: 512 queries of one fragment
-    int32_t frag;
-    int32_t qstart;
-};
+constexpr int SQB = 4;             // 16-query blocks per wave
 
-__global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk512, const uint16_t *pk,
+__global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, const uint16_t *pk,
                                                     int32_t *c1_out, float *v2_out) {
-    __shared__ __align__(16) uint16_t lds[2][CROWS * 32];     // 2 x 8 KB
-    const Blk b = blk512[blockIdx.x];
+    __shared__ __align__(16) uint16_t lds[2][CROWS * PK];     // 2 x 16 KB
+    const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
     const Frag &Fc = frag[Fq.partner];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
 
-    // query operands: rows [y, 1, 1] of this wave's 8 blocks of 16 queries
-    bf16x8 B[SQB];
+    // query operands: [y_hi, 1, 1] and [y_lo, 0, 0] of this wave's 4 blocks of 16 queries
+    bf16x8 Bh[SQB], Bl[SQB];
     const int qw = b.start + wv * SQB * 16;
 #pragma unroll
     for (int k = 0; k < SQB; ++k) {
         int q = qw + 16 * k + col;
-        uint4 w = make_uint4(0, 0, 0, 0);
-        if (q < Fq.n) w = *(const uint4 *)(pk + (Fq.pk_off + q) * 32 + 8 * grp);
-        if (grp == 3) w.w = 0x3f803f80u;                      // slots 30, 31 = 1.0
-        B[k] = __builtin_bit_cast(bf16x8, w);
+        uint4 wh = make_uint4(0, 0, 0, 0), wl = wh;
+        if (q < Fq.n) {
+            const uint16_t *r = pk + (Fq.pk_off + q) * PK;
+            wh = *(const uint4 *)(r + 8 * grp);
+            wl = *(const uint4 *)(r + 32 + 8 * grp);
+        }
+        if (grp == 3) wh.w = 0x3f803f80u;                     // slots 30, 31 = 1.0
+        Bh[k] = __builtin_bit_cast(bf16x8, wh);
+        Bl[k] = __builtin_bit_cast(bf16x8, wl);
     }
     float cm[SQB], v1[SQB], v2[SQB];
     int32_t c1[SQB];
@@ -220,28 +226,34 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     for (int k = 0; k < SQB; ++k) { cm[k] = -INFINITY; v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
 
     const int nch = (Fc.n + CROWS - 1) / CROWS;
-    const uint4 *src = (const uint4 *)(pk + Fc.pk_off * 32);   // 4 uint4 per row
-    // stage chunk 0
-    uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0;
-    if (nch > 0) { r0 = src[threadIdx.x]; r1 = src[threadIdx.x + 256]; }
-    ((uint4 *)lds[0])[threadIdx.x] = r0;
-    ((uint4 *)lds[0])[threadIdx.x + 256] = r1;
+    constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk (1024)
+    constexpr int PER = U4 / (SW * 64);                         // per thread (4)
+    const uint4 *src = (const uint4 *)(pk + Fc.pk_off * PK);
+    uint4 r[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) r[u] = nch > 0 ? src[threadIdx.x + u * SW * 64] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[threadIdx.x + u * SW * 64] = r[u];
     __syncthreads();
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     for (int ch = 0; ch < nch; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nch) {
-            const uint4 *nx = src + (int64_t)(ch + 1) * CROWS * 4;
-            r0 = nx[threadIdx.x];
-            r1 = nx[threadIdx.x + 256];
+            const uint4 *nx = src + (int64_t)(ch + 1) * U4;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) r[u] = nx[threadIdx.x + u * SW * 64];
         }
         const uint16_t *L = lds[buf];
-#pragma unroll
+#pragma unroll 2
         for (int t = 0; t < CH; ++t) {
-            bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4 *)(L + (t * 16 + col) * 32 + 8 * grp));
+            const uint16_t *rowp = L + (t * 16 + col) * PK + 8 * grp;
+            bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4 *)rowp);
+            bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4 *)(rowp + 32));
 #pragma unroll
             for (int k = 0; k < SQB; ++k) {
-                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[k], zero, 0, 0, 0);
+                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bl[k], acc, 0, 0, 0);
                 cm[k] = fmaxf(cm[k], fmaxf(acc[0], acc[1]));
                 cm[k] = fmaxf(cm[k], fmaxf(acc[2], acc[3]));
             }
@@ -255,15 +267,14 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             cm[k] = -INFINITY;
         }
         if (ch + 1 < nch) {
-            ((uint4 *)lds[buf ^ 1])[threadIdx.x] = r0;
-            ((uint4 *)lds[buf ^ 1])[threadIdx.x + 256] = r1;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) ((uint4 *)lds[buf ^ 1])[threadIdx.x + u * SW * 64] = r[u];
         }
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < SQB; ++k) {
-        // lane (col, grp) holds rows 4 grp + {0..3} of query column col; the
-        // MFMA output row index is the candidate, the column the query
+        // lane (col, grp): candidate rows 4 grp + {0..3} (MFMA output rows) of query column col
         int q = qw + 16 * k + col;
         if (q < Fq.n) {
             int64_t o = (Fq.off + q) * 4 + grp;
@@ -276,7 +287,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 // ---------------------------------------------------------------- re-rank
 
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                                const float *yn2, const uint32_t *ymax, const int32_t *c1,
+                                                const float *yn2, const int32_t *c1,
                                                 const float *v2, int32_t *nn, float *dist, int32_t *fb_row,
                                                 int32_t *fb_frag, int32_t *fb_count, PairState *ps) {
     const Blk b = blk[blockIdx.x];
@@ -312,11 +323,12 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                         if (d < best || (d == best && j < bj)) { best = d; bj = j; }
                     }
             }
-            float ym = __uint_as_float(ymax[Fq.partner]);
             float ny2 = yn2[Fq.pk_off + i];
-            float E = 1.01f * (0.00390625f * sqrtf(ny2) * ym + 3.8147e-6f * ym * ym) + 1e-6f;
+            float yi = sqrtf(ny2);
+            float R = (yi + sqrtf(best)) * 1.0001f + 1e-6f;       // competitors satisfy |y_j| <= R
+            float E = 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;   // 2^-15 (|y_i| R + R^2/2)
             float L = ny2 - 2.0f * (a2 + E);
-            bool cert = bj >= 0 && (best + 1e-5f * (1.0f + sqrtf(best)) + 2e-5f * best < L);
+            bool cert = bj >= 0 && (best * (1.0f + 3e-6f) + 1e-7f < L);
             if (a2 == -INFINITY) cert = true;                  // every row was re-ranked (bj may be -1: none valid)
             if (cert) {
                 nn[gi] = bj;
@@ -386,7 +398,6 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     if (g.ntot == 0) return hipSuccess;
     ScreenScratch S = carve(scratch, g, g.pk_rows);
     hipError_t e;
-    if ((e = fill<uint32_t>(S.ymax, 0u, g.nfrag, s)) != hipSuccess) return e;
     if ((e = fill<int32_t>(S.fb_count, 0, 1, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_desc_partials, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const float *)d.F, (const int32_t *)d.valid, S.part);
@@ -395,14 +406,13 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     hipLaunchKernelGGL(k_desc_mean, dim3((npair + 63) / 64), dim3(64), 0, s, (const Frag *)g.frag, g.nfrag,
                        (const float *)S.part, ps, mean);
     hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)mean, d.pk, S.yn2, S.ymax);
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)mean, d.pk, S.yn2);
     tmark("pack", s);
-    hipLaunchKernelGGL(k_screen, dim3(g.nblk512), dim3(SW * 64), 0, s, (const Frag *)g.frag, (const Blk *)g.blk512,
+    hipLaunchKernelGGL(k_screen, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const uint16_t *)d.pk, S.c1, S.v2);
     tmark("screen", s);
     hipLaunchKernelGGL(k_rerank, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.yn2, (const uint32_t *)S.ymax,
-                       (const int32_t *)S.c1, (const float *)S.v2, m.nn, m.dist, S.fb_row, S.fb_frag, S.fb_count, ps);
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.yn2, (const int32_t *)S.c1, (const float *)S.v2, m.nn, m.dist, S.fb_row, S.fb_frag, S.fb_count, ps);
     tmark("rerank", s);
     unsigned grid = (unsigned)std::min<int64_t>(g.ntot, 2048);
     hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(256), 0, s, (const Frag *)g.frag, (const float *)d.F,
