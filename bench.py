@@ -114,6 +114,7 @@ def main():
                 and tr.get("points") == args.points:
             traffic = tr.get("bytes_per_launch")
     log(f"screen kernel {scr:.3f} ms/launch -> {achieved:.1f} TFLOP/s algorithmic")
+    log("stages (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in stage_ms.items()))
 
     # plain float32 per-pair baseline (host loop, no graph)
     base = None

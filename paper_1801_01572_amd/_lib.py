@@ -129,8 +129,8 @@ def _ptr(t):
 
 def _cloud(t: torch.Tensor, normals=True) -> Cloud:
     if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[0] in (3, 6)
-            and t.is_contiguous()):
-        raise LsrError("a cloud must be a contiguous CUDA float32 tensor of shape (6, N) or (3, N)")
+            and (t.shape[1] <= 1 or t.stride(1) == 1)):
+        raise LsrError("a cloud must be a CUDA float32 tensor of shape (6, N) or (3, N) with contiguous rows")
     if normals and t.shape[0] != 6:
         raise LsrError("this call needs input normals: shape (6, N)")
     n = t.shape[1]
