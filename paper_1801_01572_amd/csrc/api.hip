@@ -243,6 +243,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     for (int a = 0; a < 3; ++a) o_n[a] = D.add(8 * n1);
     size_t o_spfh = D.add(4 * FD * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
     size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
+    size_t o_bits = D.add(8 * (size_t)mbits_words(ntot, nf));
     size_t o_nn = D.add(4 * n1), o_dist = D.add(4 * n1), o_mut = D.add(n1), o_flag = D.add(4 * n1),
            o_kpos = D.add(4 * n1), o_kp = D.add(12 * n1), o_kq = D.add(12 * n1), o_ki = D.add(4 * n1);
     size_t o_ps = D.add(sizeof(PairState) * (size_t)std::max(npairs, 1));
@@ -286,6 +287,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->m.nn = (int32_t *)(db + o_nn);
     P->m.dist = (float *)(db + o_dist);
     P->m.mutual = (uint8_t *)(db + o_mut);
+    P->m.mbits = (uint64_t *)(db + o_bits);
     P->m.flag = (int32_t *)(db + o_flag);
     P->m.kpos = (int32_t *)(db + o_kpos);
     P->m.kp = (float *)(db + o_kp);
@@ -641,6 +643,7 @@ int lsr_stage_consistency(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, 
     HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
     HIPCHK(ctx, copy<int32_t>(pl->m.nn, d_nnQ, P->n, s));
     HIPCHK(ctx, copy<uint8_t>(pl->m.mutual, d_mutual, P->n, s));
+    HIPCHK(ctx, launch_mutual_bits(pl->g, pl->m, s));
     HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, tau, seed, s));
     if (P->n > 0) {
         hipLaunchKernelGGL(k_flag_out, dim3(nblk(P->n, 256)), dim3(256), 0, s, (const int32_t *)pl->m.flag, P->n, d_flag);

@@ -1,6 +1,8 @@
 // Reciprocal test, quadruple consistency filter and compaction.
 //
-// Reciprocal: (i, nnQ(i)) is kept when nnP(nnQ(i)) = i.
+// Reciprocal: (i, nnQ(i)) is kept when nnP(nnQ(i)) = i; the flags are also
+// written as a bitmap (one wavefront ballot per 64 points) that the
+// consistency trials read from LDS.
 // Consistency (Algorithm 1's pre-rejection, used as a filter): trial t draws
 // four distinct P indices that have a reciprocal correspondence; slot s takes
 // the first of up to 64 draws i = ((r >> 32) * N_P) >> 32 that qualifies, with
@@ -14,8 +16,10 @@
 
 namespace lsr {
 
+__device__ __forceinline__ int64_t mbits_base(const Frag &F, int f) { return F.off / 64 + f; }
+
 __global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk, const int32_t *nn, uint8_t *mutual,
-                                                PairState *ps) {
+                                                uint64_t *mbits, PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     int i = b.start + threadIdx.x;
@@ -27,8 +31,10 @@ __global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk
         mutual[F.off + i] = m ? 1 : 0;
     }
     unsigned long long bal = __ballot(m);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0 && b.start + 64 * w < F.n) mbits[mbits_base(F, b.frag) + (b.start + 64 * w) / 64] = bal;
     __shared__ int cnt[4];
-    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+    if ((threadIdx.x & 63) == 0) cnt[w] = __popcll(bal);
     __syncthreads();
     if (threadIdx.x == 0 && ps && F.pair >= 0 && (b.frag & 1) == 0) {
         int t = cnt[0] + cnt[1] + cnt[2] + cnt[3];
@@ -39,7 +45,26 @@ __global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk
 hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mutual, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)m.nn, m.mutual, ps);
+                       (const int32_t *)m.nn, m.mutual, m.mbits, ps);
+    return hipGetLastError();
+}
+
+// Bitmap of given reciprocal flags (stage calls).
+__global__ void __launch_bounds__(256) k_mutual_bits(const Frag *frag, const Blk *blk, const uint8_t *mutual,
+                                                     uint64_t *mbits) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    bool m = i < F.n && mutual[F.off + i];
+    unsigned long long bal = __ballot(m);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0 && b.start + 64 * w < F.n) mbits[mbits_base(F, b.frag) + (b.start + 64 * w) / 64] = bal;
+}
+
+hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mutual_bits, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const uint8_t *)m.mutual, m.mbits);
     return hipGetLastError();
 }
 
@@ -51,15 +76,24 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
 }
 
 constexpr int CT = 256;      // threads per block
-constexpr int CPT = 8;       // trials per thread
+constexpr int CPT = 32;      // trials per thread
+constexpr int MB_LDS = 8192; // bitmap words staged in LDS (fragments up to 524,288 points)
 
 __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const int32_t *nn,
-                                                    const uint8_t *mutual, int32_t *flag, double t2, uint64_t seed,
+                                                    const uint64_t *mbits, int32_t *flag, double t2, uint64_t seed,
                                                     PairState *ps) {
+    __shared__ uint64_t bm[MB_LDS];
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
     const Frag &Q = frag[2 * b.pair + 1];
     const uint64_t nP = (uint64_t)P.n;
+    const int nw = (P.n + 63) / 64;
+    const uint64_t *gbits = mbits + mbits_base(P, 2 * b.pair);
+    const bool in_lds = nw <= MB_LDS;
+    if (in_lds)
+        for (int k = threadIdx.x; k < nw; k += CT) bm[k] = gbits[k];
+    __syncthreads();
+    const uint64_t *bits = in_lds ? bm : gbits;
     int passed = 0;
     for (int r = 0; r < CPT; ++r) {
         int64_t t = b.first + (int64_t)r * CT + threadIdx.x;
@@ -71,7 +105,7 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
             for (int a = 0; a < 64; ++a) {
                 uint64_t rr = splitmix64_at(seed, ((uint64_t)t << 8) | ((uint64_t)sl << 6) | (uint64_t)a);
                 int32_t i = (int32_t)(((rr >> 32) * nP) >> 32);
-                if (!mutual[P.off + i]) continue;
+                if (!((bits[i >> 6] >> (i & 63)) & 1ull)) continue;
                 bool dup = false;
                 for (int u = 0; u < sl; ++u) dup |= id[u] == i;
                 if (dup) continue;
@@ -108,7 +142,7 @@ hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, co
     if (e != hipSuccess || ntb == 0) return e;
     double t2 = (double)tau * (double)tau;
     hipLaunchKernelGGL(k_consistency, dim3(ntb), dim3(CT), 0, s, (const Frag *)g.frag, tb, (const int32_t *)m.nn,
-                       (const uint8_t *)m.mutual, m.flag, t2, seed, ps);
+                       (const uint64_t *)m.mbits, m.flag, t2, seed, ps);
     return hipGetLastError();
 }
 

@@ -120,6 +120,7 @@ struct MatchBufs {
     int32_t *nn;               // original order: nearest neighbour (index in partner fragment)
     float *dist;
     uint8_t *mutual;           // original order
+    uint64_t *mbits;           // the same flags as a bitmap, per fragment from word off/64 + f
     int32_t *flag;             // consistency flags, original order (int32 for the scan)
     int32_t *kpos;             // exclusive scan of flags over the batch
     float *kp, *kq;            // consistent correspondences, compacted: xyz of p and q (3 floats each)
@@ -141,6 +142,8 @@ hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, Desc
 hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStream_t s);
 hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairState *ps, hipStream_t s);
 hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s);
+hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s);
+inline int64_t mbits_words(int64_t ntot, int nfrag) { return ntot / 64 + nfrag + 1; }
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
                               float tau, uint64_t seed, hipStream_t s);
 hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);

@@ -17,17 +17,21 @@
 // Screen.  A wave owns 4 blocks of 16 queries and sweeps the partner's rows
 // 16 at a time from LDS (chunks of 128 rows, double buffered).  Lane l sees
 // query column l % 16 and candidate rows 4 (l / 16) + {0..3} of every tile
-// (lane group g = l / 16).  Per chunk a lane keeps only the maximum score;
-// across chunks it keeps the best chunk and the second-best chunk maximum.
+// (lane group g = l / 16).  Per tile a lane takes the maximum of its four
+// scores; across tiles it keeps the best tile and the second-best tile maximum.
 //
-// Certification.  The rows of each group's best chunk are re-ranked with the
-// exact float32 distance d2_row, giving D*.  A row j outside them has a
-// screened score <= A2, the largest second-best chunk maximum.  Only rows
+// Certification.  The 16 rows of the four groups' best tiles are re-ranked
+// with the exact float32 distance d2_row, giving D*.  A row j outside them has
+// a screened score <= A2, the largest second-best tile maximum.  Only rows
 // with D_ij <= D* can matter, and those have |y_j| <= |y_i| + sqrt(D*) = R,
 // so their screen error is at most E = 2^-15 (|y_i| R + R^2 / 2) (bf16 split
 // rounding and float32 accumulation, with margin).  If
 // D* + slack < |y_i|^2 - 2 (A2 + E) no outside row can win and D* with its
-// index is the float32 scan's answer; otherwise the row is rescanned exactly.
+// index is the float32 scan's answer.  Otherwise the row goes to a second
+// screen that collects every candidate whose score reaches
+// theta = (|y_i|^2 - D* - slack) / 2 - E (a superset of all rows that can tie
+// or beat D*), and those are re-ranked exactly.  Only a row with more than
+// LCAP such candidates is rescanned in float32.
 #include "match_common.h"
 
 namespace lsr {
@@ -36,8 +40,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int SW = 4;              // waves per block
-constexpr int CH = 8;              // 16-row tiles per chunk
-constexpr int CROWS = CH * 16;     // rows per chunk (128)
+constexpr int SQB = 4;             // 16-query blocks per wave (64 queries per wave, 256 per block)
+constexpr int CH = 8;              // 16-row tiles per LDS chunk
+constexpr int CROWS = CH * 16;     // rows per chunk (128); fragments are padded to this
+constexpr int LCAP = 64;           // candidates collected per uncertified row
 
 __device__ __forceinline__ uint16_t f2bf(float f) {     // round to nearest even
     uint32_t u = __float_as_uint(f);
@@ -48,62 +54,53 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 struct ScreenScratch {
     float *mean;          // (nfrag/2 + 1) x 32: projected centring vector per pair
-    float *part;          // nblk256 x 34: per-block sums of valid descriptors and their count
     float *yn2;           // pk_rows: |y|^2
-    int32_t *c1;          // ntot x 4: best chunk per lane group
-    float *v2;            // ntot x 4: second-best chunk maximum per lane group
-    int32_t *fb_row, *fb_frag, *fb_count;
+    int32_t *c1;          // ntot x 4: best tile per lane group
+    float *v2;            // ntot x 4: second-best tile maximum per lane group
+    int32_t *fb_row;      // ntot: uncertified rows, per fragment from Frag::off
+    float *thr;           // ntot: collection threshold of each uncertified row
+    int32_t *fb_cnt;      // nfrag
+    int32_t *lst;         // list slots x LCAP
+    int32_t *lst_cnt;     // list slots
+    int32_t *full_row, *full_frag, *full_cnt;
 };
 
-static ScreenScratch carve(void *base, const GridBufs &g, int64_t pk_rows) {
+// list slots of fragment f: [off/16 + 64 f, ... + n/16 + 64)
+__device__ __forceinline__ int64_t lst_base(const Frag &F, int f) { return F.off / 16 + 64 * (int64_t)f; }
+__device__ __forceinline__ int32_t lst_cap(const Frag &F) { return F.n / 16 + 64; }
+static int64_t lst_slots(const GridBufs &g) { return g.ntot / 16 + 64 * (int64_t)g.nfrag + 64; }
+
+static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     char *p = (char *)base;
-    auto take = [&](size_t bytes) { char *r = p; p += (bytes + 255) & ~size_t(255); return r; };
+    size_t tot = 0;
+    auto take = [&](size_t n) { char *r = p; size_t a = (n + 255) & ~size_t(255); p += a; tot += a; return r; };
+    const size_t n1 = (size_t)std::max<int64_t>(g.ntot, 1);
     ScreenScratch s;
     s.mean = (float *)take(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
-    s.part = (float *)take(sizeof(float) * 34 * (size_t)std::max(g.nblk256, 1));
-    s.yn2 = (float *)take(sizeof(float) * (size_t)std::max<int64_t>(pk_rows, 1));
-    s.c1 = (int32_t *)take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
-    s.v2 = (float *)take(sizeof(float) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
-    s.fb_row = (int32_t *)take(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
-    s.fb_frag = (int32_t *)take(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
-    s.fb_count = (int32_t *)take(256);
+    s.yn2 = (float *)take(sizeof(float) * (size_t)std::max<int64_t>(g.pk_rows, 1));
+    s.c1 = (int32_t *)take(sizeof(int32_t) * 4 * n1);
+    s.v2 = (float *)take(sizeof(float) * 4 * n1);
+    s.fb_row = (int32_t *)take(sizeof(int32_t) * n1);
+    s.thr = (float *)take(sizeof(float) * n1);
+    s.fb_cnt = (int32_t *)take(sizeof(int32_t) * (size_t)std::max(g.nfrag, 1));
+    s.lst = (int32_t *)take(sizeof(int32_t) * LCAP * (size_t)lst_slots(g));
+    s.lst_cnt = (int32_t *)take(sizeof(int32_t) * (size_t)lst_slots(g));
+    s.full_row = (int32_t *)take(sizeof(int32_t) * n1);
+    s.full_frag = (int32_t *)take(sizeof(int32_t) * n1);
+    s.full_cnt = (int32_t *)take(256);
+    if (bytes) *bytes = tot;
     return s;
 }
 
 size_t match_bf16_scratch(const GridBufs &g, int64_t pk_rows) {
-    size_t t = 0;
-    auto add = [&](size_t bytes) { t += (bytes + 255) & ~size_t(255); };
-    add(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
-    add(sizeof(float) * 34 * (size_t)std::max(g.nblk256, 1));
-    add(sizeof(float) * (size_t)std::max<int64_t>(pk_rows, 1));
-    add(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
-    add(sizeof(float) * 4 * (size_t)std::max<int64_t>(g.ntot, 1));
-    add(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
-    add(sizeof(int32_t) * (size_t)std::max<int64_t>(g.ntot, 1));
-    add(256);
-    return t;
+    GridBufs h = g;
+    h.pk_rows = pk_rows;
+    size_t bytes = 0;
+    (void)carve(nullptr, h, &bytes);
+    return bytes;
 }
 
 // ---------------------------------------------------------------- centring
-
-__global__ void __launch_bounds__(256) k_desc_partials(const Frag *frag, const Blk *blk, const float *F,
-                                                       const int32_t *valid, float *part) {
-    __shared__ float sh[4][34];
-    const Blk b = blk[blockIdx.x];
-    const Frag &Fr = frag[b.frag];
-    int i = b.start + threadIdx.x;
-    bool v = i < Fr.n && valid[Fr.off + i];
-    const int w = threadIdx.x >> 6;
-    for (int c = 0; c < 34; ++c) {
-        float x = v ? (c < FD ? F[(Fr.off + i) * FD + c] : 1.0f) : 0.0f;
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if ((threadIdx.x & 63) == 0) sh[w][c] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < 34)
-        part[(int64_t)blockIdx.x * 34 + threadIdx.x] = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] +
-                                                     sh[3][threadIdx.x];
-}
 
 // Helmert contrasts of one 11-bin block (orthonormal, orthogonal to all-ones).
 __device__ __forceinline__ void helmert11(const float *x, float *h) {
@@ -115,27 +112,44 @@ __device__ __forceinline__ void helmert11(const float *x, float *h) {
     }
 }
 
-// One thread per pair or stand-alone fragment pair: mean descriptor of both
-// fragments (fixed block order), projected.
-__global__ void k_desc_mean(const Frag *frag, int nfrag, const float *part, PairState *ps, float *mean_out) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (2 * b >= nfrag) return;
+// One block per pair: the mean of up to 4096 valid descriptors of each
+// fragment (any centre gives the same distances; a nearby one keeps the
+// screen's magnitudes small), projected.  Fixed summation order.
+__global__ void __launch_bounds__(256) k_desc_mean(const Frag *frag, int nfrag, const float *F, const int32_t *valid,
+                                                   float *mean_out) {
+    __shared__ float sh[4][34];
+    const int b = blockIdx.x;
     float acc[34];
+#pragma unroll
     for (int c = 0; c < 34; ++c) acc[c] = 0.f;
     for (int f = 2 * b; f <= 2 * b + 1 && f < nfrag; ++f) {
         const Frag &Fr = frag[f];
-        int nb = (Fr.n + 255) / 256;
-        for (int k = 0; k < nb; ++k)
-            for (int c = 0; c < 34; ++c) acc[c] += part[(int64_t)(Fr.blk256_first + k) * 34 + c];
+        int lim = min(Fr.n, 4096);
+        for (int i = threadIdx.x; i < lim; i += 256) {
+            if (!valid[Fr.off + i]) continue;
+            const float *x = F + (Fr.off + i) * FD;
+#pragma unroll
+            for (int c = 0; c < FD; ++c) acc[c] += x[c];
+            acc[33] += 1.f;
+        }
     }
-    float inv = acc[33] > 0 ? 1.0f / acc[33] : 0.f;
-    float m[FD];
-    for (int c = 0; c < FD; ++c) m[c] = acc[c] * inv;
-    float h[30];
-    for (int k = 0; k < 3; ++k) helmert11(m + NB * k, h + 10 * k);
-    float *dst = mean_out + 32 * b;
-    for (int c = 0; c < 30; ++c) dst[c] = h[c];
-    (void)ps;
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 34; ++c) {
+        float v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[w][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m[34];
+        for (int c = 0; c < 34; ++c) m[c] = ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c];
+        float inv = m[33] > 0 ? 1.0f / m[33] : 0.f;
+        for (int c = 0; c < FD; ++c) m[c] *= inv;
+        float h[30];
+        for (int k = 0; k < 3; ++k) helmert11(m + NB * k, h + 10 * k);
+        for (int c = 0; c < 30; ++c) mean_out[32 * b + c] = h[c];
+    }
 }
 
 __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
@@ -192,38 +206,53 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
 
 // ---------------------------------------------------------------- screen
 
-constexpr int SQB = 4;             // 16-query blocks per wave
-
+// COLLECT = false: every row of the fragment is a query; write the best tile
+// and second-best tile maximum per lane group.
+// COLLECT = true: the queries are the fragment's uncertified rows (slots
+// [start, start + 256) of its list); append every candidate whose score
+// reaches the row's threshold to the row's candidate list.
+template <bool COLLECT>
 __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, const uint16_t *pk,
-                                                    int32_t *c1_out, float *v2_out) {
+                                                    int32_t *c1_out, float *v2_out, const int32_t *fb_row,
+                                                    const int32_t *fb_cnt, const float *thr, int32_t *lst,
+                                                    int32_t *lst_cnt) {
     __shared__ __align__(16) uint16_t lds[2][CROWS * PK];     // 2 x 16 KB
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
+    int nq = Fq.n;
+    if (COLLECT) {
+        nq = min(fb_cnt[b.frag], lst_cap(Fq));
+        if (b.start >= nq) return;
+    }
     const Frag &Fc = frag[Fq.partner];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
 
     // query operands: [y_hi, 1, 1] and [y_lo, 0, 0] of this wave's 4 blocks of 16 queries
     bf16x8 Bh[SQB], Bl[SQB];
+    float th[SQB];
     const int qw = b.start + wv * SQB * 16;
 #pragma unroll
     for (int k = 0; k < SQB; ++k) {
-        int q = qw + 16 * k + col;
+        int slot = qw + 16 * k + col;
         uint4 wh = make_uint4(0, 0, 0, 0), wl = wh;
-        if (q < Fq.n) {
+        th[k] = INFINITY;
+        if (slot < nq) {
+            int q = COLLECT ? fb_row[Fq.off + slot] : slot;
             const uint16_t *r = pk + (Fq.pk_off + q) * PK;
             wh = *(const uint4 *)(r + 8 * grp);
             wl = *(const uint4 *)(r + 32 + 8 * grp);
+            if (COLLECT) th[k] = thr[Fq.off + slot];
         }
         if (grp == 3) wh.w = 0x3f803f80u;                     // slots 30, 31 = 1.0
         Bh[k] = __builtin_bit_cast(bf16x8, wh);
         Bl[k] = __builtin_bit_cast(bf16x8, wl);
     }
-    float cm[SQB], v1[SQB], v2[SQB];
+    float v1[SQB], v2[SQB];
     int32_t c1[SQB];
 #pragma unroll
-    for (int k = 0; k < SQB; ++k) { cm[k] = -INFINITY; v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
+    for (int k = 0; k < SQB; ++k) { v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
 
     const int nch = (Fc.n + CROWS - 1) / CROWS;
     constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk (1024)
@@ -249,22 +278,30 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             const uint16_t *rowp = L + (t * 16 + col) * PK + 8 * grp;
             bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4 *)rowp);
             bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4 *)(rowp + 32));
+            const int tile = ch * CH + t;
 #pragma unroll
             for (int k = 0; k < SQB; ++k) {
                 f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bl[k], acc, 0, 0, 0);
-                cm[k] = fmaxf(cm[k], fmaxf(acc[0], acc[1]));
-                cm[k] = fmaxf(cm[k], fmaxf(acc[2], acc[3]));
-            }
-        }
+                if (!COLLECT) {
+                    float tm = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+                    v2[k] = fmaxf(v2[k], fminf(v1[k], tm));
+                    c1[k] = tm > v1[k] ? tile : c1[k];
+                    v1[k] = fmaxf(v1[k], tm);
+                } else {
+                    bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
+                    if (hit) {                                 // rare: near-ties of uncertified rows
+                        int64_t slot = lst_base(Fq, b.frag) + qw + 16 * k + col;
 #pragma unroll
-        for (int k = 0; k < SQB; ++k) {
-            float m = cm[k];
-            v2[k] = fmaxf(v2[k], fminf(v1[k], m));
-            c1[k] = m > v1[k] ? ch : c1[k];
-            v1[k] = fmaxf(v1[k], m);
-            cm[k] = -INFINITY;
+                        for (int e = 0; e < 4; ++e)
+                            if (acc[e] >= th[k]) {
+                                int pos = atomicAdd(&lst_cnt[slot], 1);
+                                if (pos < LCAP) lst[slot * LCAP + pos] = tile * 16 + 4 * grp + e;
+                            }
+                    }
+                }
+            }
         }
         if (ch + 1 < nch) {
 #pragma unroll
@@ -272,24 +309,42 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
         }
         __syncthreads();
     }
+    if (!COLLECT) {
 #pragma unroll
-    for (int k = 0; k < SQB; ++k) {
-        // lane (col, grp): candidate rows 4 grp + {0..3} (MFMA output rows) of query column col
-        int q = qw + 16 * k + col;
-        if (q < Fq.n) {
-            int64_t o = (Fq.off + q) * 4 + grp;
-            c1_out[o] = c1[k];
-            v2_out[o] = v2[k];
+        for (int k = 0; k < SQB; ++k) {
+            // lane (col, grp): candidate rows tile*16 + 4 grp + {0..3} (MFMA output rows) of query col
+            int q = qw + 16 * k + col;
+            if (q < Fq.n) {
+                int64_t o = (Fq.off + q) * 4 + grp;
+                c1_out[o] = c1[k];
+                v2_out[o] = v2[k];
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------- re-rank
 
+__device__ __forceinline__ void load_row(const float *F, int64_t r, float *x) {
+    const float *p = F + r * FD;
+#pragma unroll
+    for (int c = 0; c < FD; ++c) x[c] = p[c];
+}
+
+// Error bound of the screen for competitors of a row with |y_i|^2 = ny2 and
+// current best D (see the file header).
+__device__ __forceinline__ float screen_err(float ny2, float best) {
+    float yi = sqrtf(ny2);
+    float R = (yi + sqrtf(best)) * 1.0001f + 1e-6f;
+    return 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;      // 2^-15 (|y_i| R + R^2 / 2)
+}
+__device__ __forceinline__ float slack(float best) { return best * 3e-6f + 1e-7f; }
+
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                                const float *yn2, const int32_t *c1,
-                                                const float *v2, int32_t *nn, float *dist, int32_t *fb_row,
-                                                int32_t *fb_frag, int32_t *fb_count, PairState *ps) {
+                                                const float *yn2, const int32_t *c1, const float *v2, int32_t *nn,
+                                                float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
+                                                int32_t *full_row, int32_t *full_frag, int32_t *full_cnt,
+                                                PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     const int i = b.start + threadIdx.x;
@@ -302,48 +357,84 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
             dist[gi] = INFINITY;
         } else {
             float q[FD];
-#pragma unroll
-            for (int c = 0; c < FD; ++c) q[c] = F[gi * FD + c];
+            load_row(F, gi, q);
             float best = INFINITY;
             int32_t bj = -1;
             float a2 = -INFINITY;
             for (int g = 0; g < 4; ++g) {
-                int32_t ch = c1[gi * 4 + g];
+                int32_t tl = c1[gi * 4 + g];
                 a2 = fmaxf(a2, v2[gi * 4 + g]);
-                if (ch < 0) continue;
-                for (int t = 0; t < CH; ++t)
-                    for (int e = 0; e < 4; ++e) {
-                        int32_t j = ch * CROWS + t * 16 + 4 * g + e;
-                        if (j >= Fc.n || !valid[Fc.off + j]) continue;
-                        float x[FD];
-                        const float *xr = F + (Fc.off + j) * FD;
-#pragma unroll
-                        for (int c = 0; c < FD; ++c) x[c] = xr[c];
-                        float d = d2_row(q, x);
-                        if (d < best || (d == best && j < bj)) { best = d; bj = j; }
-                    }
+                if (tl < 0) continue;
+                for (int e = 0; e < 4; ++e) {
+                    int32_t j = tl * 16 + 4 * g + e;
+                    if (j >= Fc.n || !valid[Fc.off + j]) continue;
+                    float x[FD];
+                    load_row(F, Fc.off + j, x);
+                    float d = d2_row(q, x);
+                    if (d < best || (d == best && j < bj)) { best = d; bj = j; }
+                }
             }
             float ny2 = yn2[Fq.pk_off + i];
-            float yi = sqrtf(ny2);
-            float R = (yi + sqrtf(best)) * 1.0001f + 1e-6f;       // competitors satisfy |y_j| <= R
-            float E = 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;   // 2^-15 (|y_i| R + R^2/2)
-            float L = ny2 - 2.0f * (a2 + E);
-            bool cert = bj >= 0 && (best * (1.0f + 3e-6f) + 1e-7f < L);
-            if (a2 == -INFINITY) cert = true;                  // every row was re-ranked (bj may be -1: none valid)
+            float E = screen_err(ny2, best);
+            bool cert = a2 == -INFINITY || (bj >= 0 && best + slack(best) < ny2 - 2.0f * (a2 + E));
             if (cert) {
                 nn[gi] = bj;
                 dist[gi] = best;
             } else {
                 fb = true;
-                int k = atomicAdd(fb_count, 1);
-                fb_row[k] = i;
-                fb_frag[k] = b.frag;
+                int k = atomicAdd(&fb_cnt[b.frag], 1);
+                fb_row[Fq.off + k] = i;
+                thr[Fq.off + k] = bj >= 0 ? 0.5f * (ny2 - best - slack(best)) - E : -INFINITY;
+                if (k >= lst_cap(Fq) || bj < 0) {               // no list slot: rescan in float32
+                    int r = atomicAdd(full_cnt, 1);
+                    full_row[r] = i;
+                    full_frag[r] = b.frag;
+                }
             }
         }
     }
     unsigned long long bal = __ballot(fb);
     if ((threadIdx.x & 63) == 0 && bal && ps && Fq.pair >= 0)
         atomicAdd(&ps[Fq.pair].n_fallback, (unsigned long long)__popcll(bal));
+}
+
+// Exact re-rank of the collected candidates of each uncertified row.
+__global__ void __launch_bounds__(256) k_rerank_list(const Frag *frag, const Blk *blk, const float *F,
+                                                     const int32_t *valid, const int32_t *fb_row,
+                                                     const int32_t *fb_cnt, const float *thr, const int32_t *lst,
+                                                     const int32_t *lst_cnt, int32_t *nn, float *dist,
+                                                     int32_t *full_row, int32_t *full_frag, int32_t *full_cnt) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fq = frag[b.frag];
+    if (Fq.partner < 0) return;
+    const int slot = b.start + threadIdx.x;
+    const int nq = min(fb_cnt[b.frag], lst_cap(Fq));
+    if (slot >= nq) return;
+    const int32_t i = fb_row[Fq.off + slot];
+    if (!(thr[Fq.off + slot] > -INFINITY)) return;              // already on the float32 rescan list
+    const Frag &Fc = frag[Fq.partner];
+    const int64_t ls = lst_base(Fq, b.frag) + slot;
+    const int cnt = lst_cnt[ls];
+    if (cnt > LCAP || cnt == 0) {
+        int r = atomicAdd(full_cnt, 1);
+        full_row[r] = i;
+        full_frag[r] = b.frag;
+        return;
+    }
+    float q[FD];
+    load_row(F, Fq.off + i, q);
+    float best = INFINITY;
+    int32_t bj = -1;
+    for (int k = 0; k < cnt; ++k) {
+        int32_t j = lst[ls * LCAP + k];
+        if (j >= Fc.n || !valid[Fc.off + j]) continue;
+        float x[FD];
+        load_row(F, Fc.off + j, x);
+        float d = d2_row(q, x);
+        if (d < best || (d == best && j < bj)) { best = d; bj = j; }
+    }
+    nn[Fq.off + i] = bj;
+    dist[Fq.off + i] = best;
 }
 
 // Exact float32 rescan of the listed rows (grid-stride over the list).
@@ -358,17 +449,13 @@ __global__ void __launch_bounds__(256) k_fallback(const Frag *frag, const float 
         const Frag &Fc = frag[Fq.partner];
         const int32_t i = rows[r];
         float q[FD];
-        const float *src = F + (Fq.off + i) * FD;
-#pragma unroll
-        for (int c = 0; c < FD; ++c) q[c] = src[c];
+        load_row(F, Fq.off + i, q);
         float best = INFINITY;
         int32_t bj = -1;
         for (int j = threadIdx.x; j < Fc.n; j += 256) {
             if (!valid[Fc.off + j]) continue;
             float x[FD];
-            const float *cr = F + (Fc.off + j) * FD;
-#pragma unroll
-            for (int c = 0; c < FD; ++c) x[c] = cr[c];
+            load_row(F, Fc.off + j, x);
             float d = d2_row(q, x);
             if (d < best) { best = d; bj = j; }
         }
@@ -396,28 +483,38 @@ __global__ void __launch_bounds__(256) k_fallback(const Frag *frag, const float 
 hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch,
                              hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
-    ScreenScratch S = carve(scratch, g, g.pk_rows);
+    ScreenScratch S = carve(scratch, g, nullptr);
     hipError_t e;
-    if ((e = fill<int32_t>(S.fb_count, 0, 1, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_desc_partials, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, S.part);
-    float *mean = S.mean;
+    if ((e = fill<int32_t>(S.fb_cnt, 0, g.nfrag, s)) != hipSuccess) return e;
+    if ((e = fill<int32_t>(S.full_cnt, 0, 1, s)) != hipSuccess) return e;
+    if ((e = fill<int32_t>(S.lst_cnt, 0, lst_slots(g), s)) != hipSuccess) return e;
     int npair = (g.nfrag + 1) / 2;
-    hipLaunchKernelGGL(k_desc_mean, dim3((npair + 63) / 64), dim3(64), 0, s, (const Frag *)g.frag, g.nfrag,
-                       (const float *)S.part, ps, mean);
+    hipLaunchKernelGGL(k_desc_mean, dim3(npair), dim3(256), 0, s, (const Frag *)g.frag, g.nfrag, (const float *)d.F,
+                       (const int32_t *)d.valid, S.mean);
     hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)mean, d.pk, S.yn2);
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, d.pk, S.yn2);
     tmark("pack", s);
-    hipLaunchKernelGGL(k_screen, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const uint16_t *)d.pk, S.c1, S.v2);
+    hipLaunchKernelGGL(k_screen<false>, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
+                       (const Blk *)g.blk256, (const uint16_t *)d.pk, S.c1, S.v2, nullptr, nullptr, nullptr, nullptr,
+                       nullptr);
     tmark("screen", s);
     hipLaunchKernelGGL(k_rerank, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.yn2, (const int32_t *)S.c1, (const float *)S.v2, m.nn, m.dist, S.fb_row, S.fb_frag, S.fb_count, ps);
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.yn2, (const int32_t *)S.c1,
+                       (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
+                       S.full_cnt, ps);
     tmark("rerank", s);
+    hipLaunchKernelGGL(k_screen<true>, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
+                       (const Blk *)g.blk256, (const uint16_t *)d.pk, nullptr, nullptr, (const int32_t *)S.fb_row,
+                       (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst, S.lst_cnt);
+    hipLaunchKernelGGL(k_rerank_list, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const float *)d.F, (const int32_t *)d.valid, (const int32_t *)S.fb_row,
+                       (const int32_t *)S.fb_cnt, (const float *)S.thr, (const int32_t *)S.lst,
+                       (const int32_t *)S.lst_cnt, m.nn, m.dist, S.full_row, S.full_frag, S.full_cnt);
+    tmark("collect", s);
     unsigned grid = (unsigned)std::min<int64_t>(g.ntot, 2048);
     hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(256), 0, s, (const Frag *)g.frag, (const float *)d.F,
-                       (const int32_t *)d.valid, (const int32_t *)S.fb_row, (const int32_t *)S.fb_frag,
-                       (const int32_t *)S.fb_count, m.nn, m.dist);
+                       (const int32_t *)d.valid, (const int32_t *)S.full_row, (const int32_t *)S.full_frag,
+                       (const int32_t *)S.full_cnt, m.nn, m.dist);
     return hipGetLastError();
 }
 
