@@ -14,6 +14,8 @@
 // scaled to unit sum.  Pair features are computed in FP64 so that bin and
 // source decisions agree with an FP64 evaluation except within rounding of a
 // boundary.
+#include <cmath>
+
 #include "lsr_internal.h"
 
 namespace lsr {
@@ -163,6 +165,62 @@ hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, Desc
 
 // ---------------------------------------------------------------- SPFH
 
+// A lane's walk over the nine stencil runs of its query; next() advances to
+// the next point within the radius (excluding the query's own position).
+struct StencilCursor {
+    int run, x0, x1, cx, cy, cz;
+    int32_t k, kend;
+    __device__ void init(const Frag &F, double px, double py, double pz, bool active) {
+        cell_of(F, px, py, pz, cx, cy, cz);
+        x0 = max(cx - 1, 0);
+        x1 = min(cx + 1, F.gx - 1);
+        run = (active && x0 <= x1) ? 0 : 9;
+        k = 0;
+        kend = 0;
+    }
+    // returns the next in-radius candidate (sorted index) or -1 when exhausted
+    __device__ __forceinline__ int32_t next(const Frag &F, const GridView &g, double px, double py, double pz,
+                                            double r2, double &d2out) {
+        while (run < 9) {
+            if (k >= kend) {
+                int z = cz - 1 + run / 3, y = cy - 1 + run % 3;
+                ++run;
+                if (z < 0 || z >= F.gz || y < 0 || y >= F.gy) continue;
+                int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
+                k = g.cstart[row + x0];
+                kend = g.cstart[row + x1] + g.ccount[row + x1];
+                continue;
+            }
+            int32_t j = k++;
+            double d2 = pdist2(px, py, pz, (double)g.sx[j], (double)g.sy[j], (double)g.sz[j]);
+            if (d2 > 0.0 && d2 <= r2) { d2out = d2; return j; }
+        }
+        return -1;
+    }
+};
+
+// 1/sqrt(x) and 1/x in double: hardware estimate plus two Newton steps
+// (relative error ~1e-16, far inside the bin-decision margins).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    e = fma(-x * r, r, 1.0);
+    return fma(0.5 * r, e, r);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// theta's bin edges theta_k = -pi + 2 pi k / 11 as values of the pseudo-angle
+// pa(x, y) = 1 - x / (|x| + |y|) for y >= +0 and x / (|x| + |y|) - 1 for y < 0
+// (sign bit), which increases with atan2(y, x) on (-pi, pi].
+struct ThetaEdges { double e[NB - 1]; };
+
 __device__ __forceinline__ int bin11(double x) {       // x in bin units
     double f = floor(x);
     f = fmin(fmax(f, 0.0), (double)(NB - 1));
@@ -171,51 +229,68 @@ __device__ __forceinline__ int bin11(double x) {       // x in bin units
 
 constexpr int SPFH_T = 256;
 
+// For each neighbour pair the Darboux frame u = n_s, v = (u x e)/|u x e|,
+// w = u x v with the source the endpoint whose normal makes the smaller angle
+// with the connecting line (n_i.e >= -(n_j.e): source i).  With the
+// unnormalised line d = p_j - p_i every feature follows without dividing by
+// |d| more than once: the source test is (n_i + n_j).d >= 0; with
+// c = u x d_s and l2 = |c|^2: alpha = (c.n_t) / sqrt(l2), phi = (u.d_s)/|d|,
+// theta = atan2(w.n_t, u.n_t) with w.n_t = ((u.d_s)(u.n_t) - (d_s.n_t)(u.u)) / sqrt(l2).
 __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, GridView g, const double *nxa,
-                                                 const double *nya, const double *nza, double r2, float *spfh,
-                                                 int32_t *knb) {
+                                                 const double *nya, const double *nza, double r2, ThetaEdges te,
+                                                 float *spfh, int32_t *knb) {
     __shared__ uint32_t hist[SPFH_T * FD];
     uint32_t *h = hist + threadIdx.x * FD;
 #pragma unroll
     for (int c = 0; c < FD; ++c) h[c] = 0;
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
-    int i = b.start + threadIdx.x;
-    if (i >= F.n) return;                       // no block-wide barrier follows
-    int64_t s = F.off + i;
+    const int i = b.start + threadIdx.x;
+    const bool act = i < F.n;
+    const int64_t s = F.off + (act ? i : 0);
     const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
     const double ax = nxa[s], ay = nya[s], az = nza[s];
+    StencilCursor cur;
+    cur.init(F, px, py, pz, act);
     int k = 0, kp = 0;
-    const double PI = 3.14159265358979323846;
-    for_stencil(F, g, px, py, pz, [&](int32_t j) {
-        double qx = g.sx[j], qy = g.sy[j], qz = g.sz[j];
-        double d2 = pdist2(px, py, pz, qx, qy, qz);
-        if (!(d2 > 0.0 && d2 <= r2)) return;
+    for (;;) {
+        double d2 = 0;
+        int32_t j = cur.next(F, g, px, py, pz, r2, d2);
+        if (!__any(j >= 0)) break;                      // every lane has walked its stencil
+        if (j < 0) continue;
         ++k;
-        double inv = 1.0 / sqrt(d2);
-        double ex = (qx - px) * inv, ey = (qy - py) * inv, ez = (qz - pz) * inv;
+        double dx = (double)g.sx[j] - px, dy = (double)g.sy[j] - py, dz = (double)g.sz[j] - pz;
         double bx = nxa[j], by = nya[j], bz = nza[j];
-        double ci = ax * ex + ay * ey + az * ez;
-        double cj = bx * ex + by * ey + bz * ez;
-        // source = i when n_i.e >= -(n_j.e): then u = n_i, target normal n_j, line e
-        bool src_i = ci >= -cj;
+        bool src_i = (ax + bx) * dx + (ay + by) * dy + (az + bz) * dz >= 0.0;
         double ux = src_i ? ax : bx, uy = src_i ? ay : by, uz = src_i ? az : bz;
         double tx = src_i ? bx : ax, ty = src_i ? by : ay, tz = src_i ? bz : az;
-        double sg = src_i ? 1.0 : -1.0;
-        ex *= sg; ey *= sg; ez *= sg;
-        double vx = uy * ez - uz * ey, vy = uz * ex - ux * ez, vz = ux * ey - uy * ex;
-        double vn = sqrt(vx * vx + vy * vy + vz * vz);
-        if (vn <= 1e-12) return;
-        vx /= vn; vy /= vn; vz /= vn;
-        double wx = uy * vz - uz * vy, wy = uz * vx - ux * vz, wz = ux * vy - uy * vx;
-        double alpha = vx * tx + vy * ty + vz * tz;
-        double phi = ux * ex + uy * ey + uz * ez;
-        double theta = atan2(wx * tx + wy * ty + wz * tz, ux * tx + uy * ty + uz * tz);
+        if (!src_i) { dx = -dx; dy = -dy; dz = -dz; }
+        double cx = uy * dz - uz * dy, cy = uz * dx - ux * dz, cz = ux * dy - uy * dx;
+        double l2 = cx * cx + cy * cy + cz * cz;
+        if (!(l2 > 1e-24 * d2)) continue;              // |u x e| <= 1e-12: degenerate frame, pair skipped
+        double il = rsqrt_nr(l2);
+        double ud = ux * dx + uy * dy + uz * dz;
+        double ut = ux * tx + uy * ty + uz * tz;
+        double dt = dx * tx + dy * ty + dz * tz;
+        double uu = ux * ux + uy * uy + uz * uz;
+        double alpha = (cx * tx + cy * ty + cz * tz) * il;
+        double phi = ud * rsqrt_nr(d2);
+        double ty_ = (ud * ut - dt * uu) * il;           // w . n_t
+        double sa = fabs(ut) + fabs(ty_);
+        double pa = 0.0;
+        if (sa > 0.0) {
+            double q = ut * rcp_nr(sa);
+            pa = signbit(ty_) ? q - 1.0 : 1.0 - q;
+        }
+        int bt = 0;
+#pragma unroll
+        for (int e = 0; e < NB - 1; ++e) bt += pa >= te.e[e];
         ++kp;
         h[bin11(NB * (alpha + 1.0) / 2.0)] += 1;
         h[NB + bin11(NB * (phi + 1.0) / 2.0)] += 1;
-        h[2 * NB + bin11(NB * (theta + PI) / (2.0 * PI))] += 1;
-    });
+        h[2 * NB + bt] += 1;
+    }
+    if (!act) return;
     float sc = kp > 0 ? 1.0f / (float)kp : 0.0f;
     float *o = spfh + s * FD;
 #pragma unroll
@@ -227,8 +302,14 @@ hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStrea
     if (g.ntot == 0) return hipSuccess;
     GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
     double r2 = (double)r_feature * (double)r_feature;
+    ThetaEdges te;
+    const double PI = 3.14159265358979323846;
+    for (int k = 1; k < NB; ++k) {
+        double t = -PI + 2.0 * PI * k / NB, x = std::cos(t), y = std::sin(t), sa = std::fabs(x) + std::fabs(y);
+        te.e[k - 1] = std::signbit(y) ? x / sa - 1.0 : 1.0 - x / sa;
+    }
     hipLaunchKernelGGL(k_spfh, dim3(g.nblk256), dim3(SPFH_T), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
-                       (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, r2, d.spfh, d.knb);
+                       (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, r2, te, d.spfh, d.knb);
     return hipGetLastError();
 }
 
@@ -239,22 +320,27 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
                                               int32_t *valid, PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
-    int i = b.start + threadIdx.x;
+    const int i = b.start + threadIdx.x;
+    const bool act = i < F.n;
+    const int64_t s = F.off + (act ? i : 0);
+    const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+    float acc[FD];
+#pragma unroll
+    for (int c = 0; c < FD; ++c) acc[c] = 0.f;
+    StencilCursor cur;
+    cur.init(F, px, py, pz, act);
+    for (;;) {
+        double d2 = 0;
+        int32_t j = cur.next(F, g, px, py, pz, r2, d2);
+        if (!__any(j >= 0)) break;
+        if (j < 0) continue;
+        float w = (float)rsqrt_nr(d2);
+        const float *sj = spfh + (int64_t)j * FD;
+#pragma unroll
+        for (int c = 0; c < FD; ++c) acc[c] = fmaf(sj[c], w, acc[c]);
+    }
     bool ok = false;
-    if (i < F.n) {
-        int64_t s = F.off + i;
-        const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
-        float acc[FD];
-#pragma unroll
-        for (int c = 0; c < FD; ++c) acc[c] = 0.f;
-        for_stencil(F, g, px, py, pz, [&](int32_t j) {
-            double d2 = pdist2(px, py, pz, (double)g.sx[j], (double)g.sy[j], (double)g.sz[j]);
-            if (!(d2 > 0.0 && d2 <= r2)) return;
-            float w = (float)(1.0 / sqrt(d2));
-            const float *sj = spfh + (int64_t)j * FD;
-#pragma unroll
-            for (int c = 0; c < FD; ++c) acc[c] = fmaf(sj[c], w, acc[c]);
-        });
+    if (act) {
         int k = knb[s];
         float ik = k > 0 ? 1.0f / (float)k : 0.0f;
         const float *si = spfh + s * FD;

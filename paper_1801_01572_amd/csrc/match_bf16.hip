@@ -265,6 +265,33 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[threadIdx.x + u * SW * 64] = r[u];
     __syncthreads();
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    // Software pipeline: the MFMAs of tile t are issued before the epilogue of
+    // tile t-1, so the matrix cores never wait on the vector ALU.
+    f32x4 prev[SQB];
+    int prev_tile = -1;
+    auto epilogue = [&](const f32x4 *accs, int tile) {
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) {
+            const f32x4 acc = accs[k];
+            if (!COLLECT) {
+                float tm = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+                v2[k] = fmaxf(v2[k], fminf(v1[k], tm));
+                c1[k] = tm > v1[k] ? tile : c1[k];
+                v1[k] = fmaxf(v1[k], tm);
+            } else {
+                bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
+                if (hit) {                                 // rare: near-ties of uncertified rows
+                    int64_t slot = lst_base(Fq, b.frag) + qw + 16 * k + col;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (acc[e] >= th[k]) {
+                            int pos = atomicAdd(&lst_cnt[slot], 1);
+                            if (pos < LCAP) lst[slot * LCAP + pos] = tile * 16 + 4 * grp + e;
+                        }
+                }
+            }
+        }
+    };
     for (int ch = 0; ch < nch; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nch) {
@@ -278,30 +305,19 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             const uint16_t *rowp = L + (t * 16 + col) * PK + 8 * grp;
             bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4 *)rowp);
             bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4 *)(rowp + 32));
-            const int tile = ch * CH + t;
+            // three chained products per query block, the four blocks interleaved so
+            // that each chain step has three independent MFMAs between it and its input
+            f32x4 accs[SQB];
 #pragma unroll
-            for (int k = 0; k < SQB; ++k) {
-                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bl[k], acc, 0, 0, 0);
-                if (!COLLECT) {
-                    float tm = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-                    v2[k] = fmaxf(v2[k], fminf(v1[k], tm));
-                    c1[k] = tm > v1[k] ? tile : c1[k];
-                    v1[k] = fmaxf(v1[k], tm);
-                } else {
-                    bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
-                    if (hit) {                                 // rare: near-ties of uncertified rows
-                        int64_t slot = lst_base(Fq, b.frag) + qw + 16 * k + col;
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (acc[e] >= th[k]) {
-                                int pos = atomicAdd(&lst_cnt[slot], 1);
-                                if (pos < LCAP) lst[slot * LCAP + pos] = tile * 16 + 4 * grp + e;
-                            }
-                    }
-                }
-            }
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bl[k], accs[k], 0, 0, 0);
+            if (prev_tile >= 0) epilogue(prev, prev_tile);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
+            prev_tile = ch * CH + t;
         }
         if (ch + 1 < nch) {
 #pragma unroll
@@ -309,6 +325,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
         }
         __syncthreads();
     }
+    if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
 #pragma unroll
         for (int k = 0; k < SQB; ++k) {
