@@ -171,6 +171,11 @@ int lsr_stage_normals(lsr_ctx *ctx, const lsr_cloud *c, float r_normal, double *
 int lsr_stage_fpfh(lsr_ctx *ctx, const lsr_cloud *c, const double *d_nrm, float r_feature,
                    float *d_F, int32_t *d_valid, void *stream);
 
+/* SPFH (n x 33 floats, device, original order) and neighbour counts k_i
+ * within r_feature (n int32) of one cloud given its normals. */
+int lsr_stage_spfh(lsr_ctx *ctx, const lsr_cloud *c, const double *d_nrm, float r_feature,
+                   float *d_spfh, int32_t *d_k, void *stream);
+
 /* Nearest neighbours in descriptor space, both directions: d_nnQ[i] (nP int32)
  * is the index of the closest valid G row to F row i (-1 if F_i is invalid),
  * d_dQ[i] its float32 squared distance; d_nnP / d_dP likewise for G rows.

@@ -366,6 +366,14 @@ static int features_from(const double *u, const double *nt, const double es[3], 
     double m = bin_margin(xa);
     if (bin_margin(xp) < m) m = bin_margin(xp);
     if (theta_margin(xt) < m) m = theta_margin(xt);
+    /* conditioning: v = u x e / |u x e| and theta = atan2(y, x) turn rounding
+     * of order 1e-16 into errors of 1e-16 / vn and 1e-16 / |(x, y)|; below 1e-6
+     * the bins are not decided by the inputs */
+    double tx = u[0] * nt[0] + u[1] * nt[1] + u[2] * nt[2];
+    double ty = w[0] * nt[0] + w[1] * nt[1] + w[2] * nt[2];
+    double rt = sqrt(tx * tx + ty * ty);
+    if (vn < 1e-6 && vn < m) m = vn;
+    if (rt < 1e-6 && rt < m) m = rt;
     *mb = m;
     return 1;
 }

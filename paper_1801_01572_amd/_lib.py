@@ -65,6 +65,7 @@ def lib():
         L.lsr_align_loss_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.lsr_stage_normals.argtypes = [vp, C.POINTER(Cloud), C.c_float, vp, vp]
         L.lsr_stage_fpfh.argtypes = [vp, C.POINTER(Cloud), vp, C.c_float, vp, vp, vp]
+        L.lsr_stage_spfh.argtypes = [vp, C.POINTER(Cloud), vp, C.c_float, vp, vp, vp]
         L.lsr_stage_match.argtypes = [vp, vp, vp, i64, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp]
         L.lsr_stage_consistency.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i64, C.c_float,
                                             C.c_uint64, vp, vp, vp]
@@ -74,7 +75,7 @@ def lib():
         L.lsr_set_timing.argtypes = [vp, C.c_int]
         L.lsr_get_timing.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
         for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch", "lsr_align_loss",
-                  "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_match",
+                  "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_stage_match",
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify"):
             getattr(L, f).restype = C.c_int
         _LIB = L
@@ -255,6 +256,17 @@ def stage_fpfh(xyz, nrm, r_feature, ctx=None):
     ctx.check(lib().lsr_stage_fpfh(ctx.h, C.byref(c), _ptr(nrm.contiguous()), C.c_float(r_feature), _ptr(F),
                                    _ptr(v), _stream()))
     return F, v
+
+
+def stage_spfh(xyz, nrm, r_feature, ctx=None):
+    ctx = ctx or get_context(xyz.device.index)
+    n = xyz.shape[1]
+    S = torch.empty((n, 33), dtype=torch.float32, device=xyz.device)
+    k = torch.empty(n, dtype=torch.int32, device=xyz.device)
+    c = _cloud(xyz[:3].contiguous() if xyz.shape[0] == 6 else xyz, normals=False)
+    ctx.check(lib().lsr_stage_spfh(ctx.h, C.byref(c), _ptr(nrm.contiguous()), C.c_float(r_feature), _ptr(S),
+                                   _ptr(k), _stream()))
+    return S, k
 
 
 def stage_match(F, vF, G, vG, precision=FP32, ctx=None):

@@ -575,6 +575,27 @@ int lsr_stage_fpfh(lsr_ctx *ctx, const lsr_cloud *c, const double *d_nrm, float 
     return LSR_OK;
 }
 
+int lsr_stage_spfh(lsr_ctx *ctx, const lsr_cloud *c, const double *d_nrm, float r_feature, float *d_spfh,
+                   int32_t *d_k, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_cloud(ctx, c, "cloud", false))) return rc;
+    if (!d_nrm || !d_spfh || !d_k || !(r_feature > 0)) return fail(ctx, LSR_EINVAL, "bad spfh arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FragIn> fr = {frag_of(c, 0, c->n)};
+    std::vector<char> key;
+    put(key, (int)K_FPFH + 1000);
+    put(key, fr[0]);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, false, nullptr, key, s, &pl))) return rc;
+    HIPCHK(ctx, build_grids(pl->g, r_feature, s));
+    HIPCHK(ctx, launch_normals_inject(pl->g, d_nrm, pl->d, s));
+    HIPCHK(ctx, launch_spfh(pl->g, r_feature, pl->d, s));
+    HIPCHK(ctx, launch_spfh_out(pl->g, pl->d, d_spfh, d_k, s));
+    return LSR_OK;
+}
+
 int lsr_stage_match(lsr_ctx *ctx, const float *d_F, const int32_t *d_vF, int64_t nP, const float *d_G,
                     const int32_t *d_vG, int64_t nQ, int32_t precision, int32_t *d_nnQ, float *d_dQ,
                     int32_t *d_nnP, float *d_dP, int64_t *d_fallback, void *stream) {

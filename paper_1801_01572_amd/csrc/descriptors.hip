@@ -181,7 +181,7 @@ struct StencilCursor {
     // returns the next in-radius candidate (sorted index) or -1 when exhausted
     __device__ __forceinline__ int32_t next(const Frag &F, const GridView &g, double px, double py, double pz,
                                             double r2, double &d2out) {
-        while (run < 9) {
+        while (k < kend || run < 9) {                  // run counts runs already opened
             if (k >= kend) {
                 int z = cz - 1 + run / 3, y = cy - 1 + run % 3;
                 ++run;
@@ -256,8 +256,7 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
     for (;;) {
         double d2 = 0;
         int32_t j = cur.next(F, g, px, py, pz, r2, d2);
-        if (!__any(j >= 0)) break;                      // every lane has walked its stencil
-        if (j < 0) continue;
+        if (j < 0) break;                               // this lane has walked its stencil
         ++k;
         double dx = (double)g.sx[j] - px, dy = (double)g.sy[j] - py, dz = (double)g.sz[j] - pz;
         double bx = nxa[j], by = nya[j], bz = nza[j];
@@ -313,6 +312,25 @@ hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStrea
     return hipGetLastError();
 }
 
+// SPFH and neighbour count in original order (stage output).
+__global__ void __launch_bounds__(256) k_spfh_out(const Frag *frag, const Blk *blk, const int32_t *sorig,
+                                                  const float *spfh, const int32_t *knb, float *out, int32_t *kout) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    if (i >= F.n) return;
+    int64_t s = F.off + i, o = F.off + sorig[s];
+    for (int c = 0; c < FD; ++c) out[o * FD + c] = spfh[s * FD + c];
+    kout[o] = knb[s];
+}
+
+hipError_t launch_spfh_out(const GridBufs &g, const DescBufs &d, float *out, int32_t *kout, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spfh_out, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)g.sorig, (const float *)d.spfh, (const int32_t *)d.knb, out, kout);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- FPFH
 
 __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, GridView g, const int32_t *sorig,
@@ -332,8 +350,7 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
     for (;;) {
         double d2 = 0;
         int32_t j = cur.next(F, g, px, py, pz, r2, d2);
-        if (!__any(j >= 0)) break;
-        if (j < 0) continue;
+        if (j < 0) break;
         float w = (float)rsqrt_nr(d2);
         const float *sj = spfh + (int64_t)j * FD;
 #pragma unroll

@@ -140,6 +140,7 @@ hipError_t build_grids(GridBufs &g, float r_cell, hipStream_t s);
 hipError_t launch_normals(const GridBufs &g, float r_normal, DescBufs &d, double *nrm_orig, hipStream_t s);
 hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, DescBufs &d, hipStream_t s);
 hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStream_t s);
+hipError_t launch_spfh_out(const GridBufs &g, const DescBufs &d, float *out, int32_t *kout, hipStream_t s);
 hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairState *ps, hipStream_t s);
 hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s);
 hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s);

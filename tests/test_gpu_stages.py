@@ -37,6 +37,22 @@ def test_normals_parity(L, orc, cfg, idx, n):
 
 
 @pytest.mark.parametrize("cfg,idx,n", CASES)
+def test_spfh_parity(L, orc, cfg, idx, n):
+    """Neighbour counts exact; histograms equal except at points with a
+    decision within the margin of its boundary."""
+    pr = pair(cfg, idx, n)
+    for cloud in (pr.P, pr.Q):
+        nrm, *_ = orc.normals(cloud, 0.025)
+        S, k, kp, mg = orc.spfh(cloud[:3], nrm, 0.05)
+        Sg, kg = L.stage_spfh(dev(cloud[:3]), dev(nrm), 0.05)
+        Sg, kg = Sg.cpu().numpy(), kg.cpu().numpy()
+        assert np.array_equal(kg, k)
+        keep = mg >= MARGIN
+        assert keep.mean() > (0.99 if cfg == 0 else 0.9999)
+        assert np.abs(Sg[keep] - S[keep]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("cfg,idx,n", CASES)
 def test_fpfh_parity(L, orc, cfg, idx, n):
     pr = pair(cfg, idx, n)
     print(f"fpfh cfg={cfg} idx={idx} n={pr.P.shape[1]}", flush=True)
