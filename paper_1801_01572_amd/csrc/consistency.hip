@@ -12,6 +12,8 @@
 // FP64); the correspondences of a passing trial are flagged.
 // Compaction: flagged correspondences in ascending P index, as float xyz of p
 // and q, the input of the pose solve.
+#include <algorithm>
+
 #include "lsr_internal.h"
 
 namespace lsr {
@@ -77,23 +79,41 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
 
 constexpr int CT = 256;      // threads per block
 constexpr int CPT = 32;      // trials per thread
-constexpr int MB_LDS = 8192; // bitmap words staged in LDS (fragments up to 524,288 points)
+constexpr int MB_LDS = 8192; // largest bitmap staged in LDS (words): fragments up to 524,288 points
 
-__global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const int32_t *nn,
-                                                    const uint64_t *mbits, int32_t *flag, double t2, uint64_t seed,
-                                                    PairState *ps) {
-    __shared__ uint64_t bm[MB_LDS];
+// Coordinates of each reciprocal correspondence, packed so that one trial
+// slot reads 32 contiguous bytes: (p_i, q_nnQ(i)).
+__global__ void __launch_bounds__(256) k_corr_pack(const Frag *frag, const Blk *blk, const int32_t *nn,
+                                                   const uint8_t *mutual, uint64_t *mbits, float4 *cpack) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &P = frag[b.frag];
+    if ((b.frag & 1) || P.partner < 0) return;
+    const Frag &Q = frag[P.partner];
+    int i = b.start + threadIdx.x;
+    if (i >= P.n || !mutual[P.off + i]) return;
+    int32_t j = nn[P.off + i];
+    if (j < 0 || j >= Q.n) {                      // not a usable correspondence: never drawn
+        atomicAnd((unsigned long long *)&mbits[mbits_base(P, b.frag) + i / 64], ~(1ull << (i & 63)));
+        return;
+    }
+    cpack[2 * (P.off + i)] = make_float4(P.src[0][i], P.src[1][i], P.src[2][i], Q.src[0][j]);
+    cpack[2 * (P.off + i) + 1] = make_float4(Q.src[1][j], Q.src[2][j], 0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const uint64_t *mbits,
+                                                    const float4 *cpack, int32_t *flag, double t2, uint64_t seed,
+                                                    int use_lds, PairState *ps) {
+    extern __shared__ uint64_t bm[];
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
-    const Frag &Q = frag[2 * b.pair + 1];
     const uint64_t nP = (uint64_t)P.n;
     const int nw = (P.n + 63) / 64;
     const uint64_t *gbits = mbits + mbits_base(P, 2 * b.pair);
-    const bool in_lds = nw <= MB_LDS;
-    if (in_lds)
+    if (use_lds)
         for (int k = threadIdx.x; k < nw; k += CT) bm[k] = gbits[k];
     __syncthreads();
-    const uint64_t *bits = in_lds ? bm : gbits;
+    const uint64_t *bits = use_lds ? bm : gbits;
+    const float4 *cp = cpack + 2 * P.off;
     int passed = 0;
     for (int r = 0; r < CPT; ++r) {
         int64_t t = b.first + (int64_t)r * CT + threadIdx.x;
@@ -116,14 +136,14 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
             ok = found;
         }
         if (!ok) continue;
-        const float *px = P.src[0], *py = P.src[1], *pz = P.src[2];
-        const float *qx = Q.src[0], *qy = Q.src[1], *qz = Q.src[2];
-        for (int k = 0; k < 4 && ok; ++k) {
-            int32_t i0 = id[k], i1 = id[(k + 1) & 3];
-            int32_t j0 = nn[P.off + i0], j1 = nn[P.off + i1];
-            if (j0 < 0 || j0 >= Q.n || j1 < 0 || j1 >= Q.n) { ok = false; break; }
-            double a = pdist2(px[i0], py[i0], pz[i0], px[i1], py[i1], pz[i1]);
-            double c = pdist2(qx[j0], qy[j0], qz[j0], qx[j1], qy[j1], qz[j1]);
+        float4 a0[4], a1[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { a0[k] = cp[2 * id[k]]; a1[k] = cp[2 * id[k] + 1]; }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int k1 = (k + 1) & 3;
+            double a = pdist2(a0[k].x, a0[k].y, a0[k].z, a0[k1].x, a0[k1].y, a0[k1].z);
+            double c = pdist2(a0[k].w, a1[k].x, a1[k].y, a0[k1].w, a1[k1].x, a1[k1].y);
             if (a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a) ok = false;
         }
         if (!ok) continue;
@@ -136,13 +156,18 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
     if ((threadIdx.x & 63) == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
 }
 
-hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb, float tau,
-                              uint64_t seed, hipStream_t s) {
+hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb, int max_nP,
+                              float tau, uint64_t seed, hipStream_t s) {
     hipError_t e = fill<int32_t>(m.flag, 0, g.ntot, s);
-    if (e != hipSuccess || ntb == 0) return e;
+    if (e != hipSuccess || ntb == 0 || g.ntot == 0) return e;
+    hipLaunchKernelGGL(k_corr_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)m.nn, (const uint8_t *)m.mutual, m.mbits, m.cpack);
     double t2 = (double)tau * (double)tau;
-    hipLaunchKernelGGL(k_consistency, dim3(ntb), dim3(CT), 0, s, (const Frag *)g.frag, tb, (const int32_t *)m.nn,
-                       (const uint64_t *)m.mbits, m.flag, t2, seed, ps);
+    int words = (max_nP + 63) / 64;
+    int use_lds = words <= MB_LDS ? 1 : 0;
+    size_t shm = use_lds ? sizeof(uint64_t) * (size_t)std::max(words, 1) : 0;
+    hipLaunchKernelGGL(k_consistency, dim3(ntb), dim3(CT), shm, s, (const Frag *)g.frag, tb,
+                       (const uint64_t *)m.mbits, (const float4 *)m.cpack, m.flag, t2, seed, use_lds, ps);
     return hipGetLastError();
 }
 

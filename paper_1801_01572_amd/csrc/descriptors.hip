@@ -165,40 +165,6 @@ hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, Desc
 
 // ---------------------------------------------------------------- SPFH
 
-// A lane's walk over the nine stencil runs of its query; next() advances to
-// the next point within the radius (excluding the query's own position).
-struct StencilCursor {
-    int run, x0, x1, cx, cy, cz;
-    int32_t k, kend;
-    __device__ void init(const Frag &F, double px, double py, double pz, bool active) {
-        cell_of(F, px, py, pz, cx, cy, cz);
-        x0 = max(cx - 1, 0);
-        x1 = min(cx + 1, F.gx - 1);
-        run = (active && x0 <= x1) ? 0 : 9;
-        k = 0;
-        kend = 0;
-    }
-    // returns the next in-radius candidate (sorted index) or -1 when exhausted
-    __device__ __forceinline__ int32_t next(const Frag &F, const GridView &g, double px, double py, double pz,
-                                            double r2, double &d2out) {
-        while (k < kend || run < 9) {                  // run counts runs already opened
-            if (k >= kend) {
-                int z = cz - 1 + run / 3, y = cy - 1 + run % 3;
-                ++run;
-                if (z < 0 || z >= F.gz || y < 0 || y >= F.gy) continue;
-                int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
-                k = g.cstart[row + x0];
-                kend = g.cstart[row + x1] + g.ccount[row + x1];
-                continue;
-            }
-            int32_t j = k++;
-            double d2 = pdist2(px, py, pz, (double)g.sx[j], (double)g.sy[j], (double)g.sz[j]);
-            if (d2 > 0.0 && d2 <= r2) { d2out = d2; return j; }
-        }
-        return -1;
-    }
-};
-
 // 1/sqrt(x) and 1/x in double: hardware estimate plus two Newton steps
 // (relative error ~1e-16, far inside the bin-decision margins).
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -246,19 +212,16 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     const int i = b.start + threadIdx.x;
-    const bool act = i < F.n;
-    const int64_t s = F.off + (act ? i : 0);
+    if (i >= F.n) return;                       // no block-wide barrier follows
+    const int64_t s = F.off + i;
     const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
     const double ax = nxa[s], ay = nya[s], az = nza[s];
-    StencilCursor cur;
-    cur.init(F, px, py, pz, act);
     int k = 0, kp = 0;
-    for (;;) {
-        double d2 = 0;
-        int32_t j = cur.next(F, g, px, py, pz, r2, d2);
-        if (j < 0) break;                               // this lane has walked its stencil
-        ++k;
+    for_stencil(F, g, px, py, pz, [&](int32_t j) {
         double dx = (double)g.sx[j] - px, dy = (double)g.sy[j] - py, dz = (double)g.sz[j] - pz;
+        double d2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+        if (!(d2 > 0.0 && d2 <= r2)) return;
+        ++k;
         double bx = nxa[j], by = nya[j], bz = nza[j];
         bool src_i = (ax + bx) * dx + (ay + by) * dy + (az + bz) * dz >= 0.0;
         double ux = src_i ? ax : bx, uy = src_i ? ay : by, uz = src_i ? az : bz;
@@ -266,7 +229,7 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
         if (!src_i) { dx = -dx; dy = -dy; dz = -dz; }
         double cx = uy * dz - uz * dy, cy = uz * dx - ux * dz, cz = ux * dy - uy * dx;
         double l2 = cx * cx + cy * cy + cz * cz;
-        if (!(l2 > 1e-24 * d2)) continue;              // |u x e| <= 1e-12: degenerate frame, pair skipped
+        if (!(l2 > 1e-24 * d2)) return;               // |u x e| <= 1e-12: degenerate frame, pair skipped
         double il = rsqrt_nr(l2);
         double ud = ux * dx + uy * dy + uz * dz;
         double ut = ux * tx + uy * ty + uz * tz;
@@ -274,12 +237,12 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
         double uu = ux * ux + uy * uy + uz * uz;
         double alpha = (cx * tx + cy * ty + cz * tz) * il;
         double phi = ud * rsqrt_nr(d2);
-        double ty_ = (ud * ut - dt * uu) * il;           // w . n_t
-        double sa = fabs(ut) + fabs(ty_);
+        double wt = (ud * ut - dt * uu) * il;             // w . n_t
+        double sa = fabs(ut) + fabs(wt);
         double pa = 0.0;
         if (sa > 0.0) {
             double q = ut * rcp_nr(sa);
-            pa = signbit(ty_) ? q - 1.0 : 1.0 - q;
+            pa = signbit(wt) ? q - 1.0 : 1.0 - q;
         }
         int bt = 0;
 #pragma unroll
@@ -288,8 +251,7 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
         h[bin11(NB * (alpha + 1.0) / 2.0)] += 1;
         h[NB + bin11(NB * (phi + 1.0) / 2.0)] += 1;
         h[2 * NB + bt] += 1;
-    }
-    if (!act) return;
+    });
     float sc = kp > 0 ? 1.0f / (float)kp : 0.0f;
     float *o = spfh + s * FD;
 #pragma unroll
@@ -338,26 +300,22 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
                                               int32_t *valid, PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
-    const int i = b.start + threadIdx.x;
-    const bool act = i < F.n;
-    const int64_t s = F.off + (act ? i : 0);
-    const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
-    float acc[FD];
-#pragma unroll
-    for (int c = 0; c < FD; ++c) acc[c] = 0.f;
-    StencilCursor cur;
-    cur.init(F, px, py, pz, act);
-    for (;;) {
-        double d2 = 0;
-        int32_t j = cur.next(F, g, px, py, pz, r2, d2);
-        if (j < 0) break;
-        float w = (float)rsqrt_nr(d2);
-        const float *sj = spfh + (int64_t)j * FD;
-#pragma unroll
-        for (int c = 0; c < FD; ++c) acc[c] = fmaf(sj[c], w, acc[c]);
-    }
+    int i = b.start + threadIdx.x;
     bool ok = false;
-    if (act) {
+    if (i < F.n) {
+        int64_t s = F.off + i;
+        const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+        float acc[FD];
+#pragma unroll
+        for (int c = 0; c < FD; ++c) acc[c] = 0.f;
+        for_stencil(F, g, px, py, pz, [&](int32_t j) {
+            double d2 = pdist2(px, py, pz, (double)g.sx[j], (double)g.sy[j], (double)g.sz[j]);
+            if (!(d2 > 0.0 && d2 <= r2)) return;
+            float w = (float)rsqrt_nr(d2);
+            const float *sj = spfh + (int64_t)j * FD;
+#pragma unroll
+            for (int c = 0; c < FD; ++c) acc[c] = fmaf(sj[c], w, acc[c]);
+        });
         int k = knb[s];
         float ik = k > 0 ? 1.0f / (float)k : 0.0f;
         const float *si = spfh + s * FD;

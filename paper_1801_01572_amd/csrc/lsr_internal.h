@@ -121,6 +121,7 @@ struct MatchBufs {
     float *dist;
     uint8_t *mutual;           // original order
     uint64_t *mbits;           // the same flags as a bitmap, per fragment from word off/64 + f
+    float4 *cpack;             // per P point with a reciprocal match: (px, py, pz, qx), (qy, qz, 0, 0)
     int32_t *flag;             // consistency flags, original order (int32 for the scan)
     int32_t *kpos;             // exclusive scan of flags over the batch
     float *kp, *kq;            // consistent correspondences, compacted: xyz of p and q (3 floats each)
@@ -146,7 +147,7 @@ hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStre
 hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s);
 inline int64_t mbits_words(int64_t ntot, int nfrag) { return ntot / 64 + nfrag + 1; }
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
-                              float tau, uint64_t seed, hipStream_t s);
+                              int max_nP, float tau, uint64_t seed, hipStream_t s);
 hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);
 hipError_t launch_gnc(const GridBufs &g, const MatchBufs &m, PairState *ps, int npairs, const lsr_params &prm,
                       hipStream_t s);
