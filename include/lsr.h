@@ -160,6 +160,19 @@ int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t n
                             float *const dP_xyz[3], float *const dQ_xyz[3], double *d_dxi,
                             void *stream);
 
+/*
+ * Voxel downsampling of one cloud (Algorithm 1's first step, leaf size of
+ * Sec. III): one output point per occupied voxel floor(coord / voxel) - the
+ * mean position and the normalised mean input normal (the first point's
+ * normal when that mean vanishes) - ordered by ascending (kx, ky, kz).
+ * out: six device arrays (x, y, z, nx, ny, nz) with room for c->n points;
+ * *d_count (device) receives the number of voxels, or -1 when a coordinate is
+ * not finite or lies 2^20 voxels or more from the origin (outputs then
+ * unspecified).
+ */
+int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *const out[6],
+                         int64_t *d_count, void *stream);
+
 /* ---- stage entry points: one stage on injected inputs (parity checks) ---- */
 
 /* Normals (n x 3 doubles, row-major, device) of one cloud; PCA over the

@@ -65,6 +65,7 @@ def lib():
         L.lsr_align_loss_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.lsr_stage_normals.argtypes = [vp, C.POINTER(Cloud), C.c_float, vp, vp]
         L.lsr_stage_fpfh.argtypes = [vp, C.POINTER(Cloud), vp, C.c_float, vp, vp, vp]
+        L.lsr_voxel_downsample.argtypes = [vp, C.POINTER(Cloud), C.c_float, vp, vp, vp]
         L.lsr_stage_spfh.argtypes = [vp, C.POINTER(Cloud), vp, C.c_float, vp, vp, vp]
         L.lsr_stage_match.argtypes = [vp, vp, vp, i64, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp]
         L.lsr_stage_consistency.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i64, C.c_float,
@@ -75,7 +76,7 @@ def lib():
         L.lsr_set_timing.argtypes = [vp, C.c_int]
         L.lsr_get_timing.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
         for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch", "lsr_align_loss",
-                  "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_stage_match",
+                  "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_voxel_downsample", "lsr_stage_match",
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify"):
             getattr(L, f).restype = C.c_int
         _LIB = L
@@ -183,6 +184,21 @@ def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params:
     ctx.check(lib().lsr_register_batch(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
                                        offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), _ptr(out), _stream()))
     return _parse_results(out, n) if sync else out
+
+
+def voxel_downsample(cloud: torch.Tensor, voxel: float, ctx: Context | None = None):
+    """(6, M) float32 CUDA tensor of voxel means (ordered by voxel index)."""
+    ctx = ctx or get_context(cloud.device.index)
+    n = cloud.shape[1]
+    out = torch.empty((6, max(n, 1)), dtype=torch.float32, device=cloud.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=cloud.device)
+    c = _cloud(cloud)
+    ptrs = (C.c_void_p * 6)(*[out[k].data_ptr() for k in range(6)])
+    ctx.check(lib().lsr_voxel_downsample(ctx.h, C.byref(c), C.c_float(voxel), ptrs, _ptr(cnt), _stream()))
+    m = int(cnt.cpu()[0])
+    if m < 0:
+        raise LsrError("voxel downsample: non-finite coordinate or voxel index out of range")
+    return out[:, :m]
 
 
 def _xyz_ptrs(t):

@@ -28,6 +28,10 @@ hipError_t launch_align(bool bwd, const float *const P[3], int64_t nP, const flo
                         float *const dQ[3], hipStream_t s);
 hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch,
                              hipStream_t s);
+size_t voxel_sort_bytes(int64_t n);
+size_t voxel_ws_bytes(int64_t n);
+hipError_t launch_voxel(const float *const *src_dev, const float *const src[6], int64_t n, float v,
+                        float *const *out_dev, int64_t *count, char *ws, size_t sort_bytes, hipStream_t s);
 size_t match_bf16_scratch(const GridBufs &g, int64_t pk_rows);
 }  // namespace lsr
 
@@ -35,7 +39,7 @@ using namespace lsr;
 
 namespace {
 
-enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN };
+enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN, K_VOXEL };
 
 struct FragIn {
     const float *src[6];
@@ -733,6 +737,46 @@ int lsr_stage_verify(lsr_ctx *ctx, const lsr_cloud *P, const double *d_nrmP, con
     hipLaunchKernelGGL(k_verify_info, dim3(1), dim3(1), 0, s, (const PairState *)pl->ps, (const Frag *)pl->g.frag,
                        (double)delta * (double)delta, d_info);
     HIPCHK(ctx, hipGetLastError());
+    return LSR_OK;
+}
+
+int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *const out[6], int64_t *d_count,
+                         void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_cloud(ctx, c, "cloud", true))) return rc;
+    if (!(voxel > 0) || !(voxel < 1e30f) || !out || !d_count) return fail(ctx, LSR_EINVAL, "bad voxel arguments");
+    for (int a = 0; a < 6; ++a)
+        if (!out[a] && c->n > 0) return fail(ctx, LSR_EINVAL, "NULL output array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n == 0) {
+        HIPCHK(ctx, fill<int64_t>(d_count, 0, 1, s));
+        return LSR_OK;
+    }
+    std::vector<char> key;
+    put(key, (int)K_VOXEL);
+    put(key, c->n);
+    const float *src[6] = {c->x, c->y, c->z, c->nx, c->ny, c->nz};
+    for (int a = 0; a < 6; ++a) put(key, src[a]);
+    for (int a = 0; a < 6; ++a) put(key, out[a]);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl) {
+        auto P = std::make_unique<Plan>();
+        P->key = key;
+        size_t ws = voxel_ws_bytes(c->n);
+        if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
+        HIPCHK(ctx, hipMalloc((void **)&P->dmem, ws + 256));
+        HIPCHK(ctx, hipHostMalloc((void **)&P->hmem, 256, hipHostMallocDefault));
+        P->dbytes = ws;
+        std::memcpy(P->hmem, src, sizeof(src));
+        std::memcpy(P->hmem + 64, out, 6 * sizeof(float *));
+        HIPCHK(ctx, hipMemcpyAsync(P->dmem + ws, P->hmem, 128, hipMemcpyHostToDevice, s));
+        if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
+    }
+    const float *const *src_dev = (const float *const *)(pl->dmem + pl->dbytes);
+    float *const *out_dev = (float *const *)(pl->dmem + pl->dbytes + 64);
+    HIPCHK(ctx, launch_voxel(src_dev, src, c->n, voxel, out_dev, d_count, pl->dmem, voxel_sort_bytes(c->n), s));
     return LSR_OK;
 }
 

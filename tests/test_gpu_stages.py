@@ -201,3 +201,39 @@ def test_verify_parity(L, orc, normal_check):
                               normal_check).cpu().numpy()
         assert abs(info[0] - ni) <= 2                 # decisions at |Tp - q| = delta within rounding
         assert abs(info[2] - fit) <= 1e-6 * (1 + fit)
+
+
+@pytest.mark.parametrize("cfg,idx,n,v", [(0, 0, None, 0.01), (5, 0, 60000, 0.02), (1, 1, 9000, 0.05)])
+def test_voxel_parity(L, orc, cfg, idx, n, v):
+    """Voxel means and normals bit-identical to the oracle, same voxel order."""
+    pr = pair(cfg, idx, n)
+    print(f"voxel cfg={cfg} idx={idx} n={pr.P.shape[1]} v={v}", flush=True)
+    for cloud in (pr.P, pr.Q):
+        want = orc.voxel(cloud, v)
+        for _ in range(2):                                   # second call reuses the cached plan
+            got = L.voxel_downsample(dev(cloud), v).cpu().numpy()
+            assert got.shape == want.shape
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_voxel_edge_cases(L, orc):
+    rng = np.random.default_rng(7)
+    # duplicates, opposite normals in one voxel (zero mean normal), negative coordinates, ragged size
+    n = 4099
+    c = rng.normal(size=(6, n)).astype(np.float32)
+    c[:3] = np.round(c[:3] * 4) / 4 - 0.125
+    c[3:, 1::2] = -c[3:, 0:-1:2]
+    c[:3, 1::2] = c[:3, 0:-1:2]
+    for v in (0.25, 0.5, 3.0):
+        want = orc.voxel(c, v)
+        got = L.voxel_downsample(dev(c), v).cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    one = c[:, :1].copy()
+    assert np.array_equal(L.voxel_downsample(dev(one), 0.1).cpu().numpy(), orc.voxel(one, 0.1))
+    assert L.voxel_downsample(dev(c[:, :0].copy()), 0.1).shape == (6, 0)
+    far = c.copy()
+    far[0, 17] = 1e9
+    with pytest.raises(L.LsrError):
+        L.voxel_downsample(dev(far), 0.01)
+    with pytest.raises(L.LsrError):
+        L.voxel_downsample(dev(c), 0.0)
