@@ -70,15 +70,21 @@ hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s) {
     return hipGetLastError();
 }
 
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
-    uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+// SplitMix64 (Steele, Lea and Flood 2014): the n-th output for a seed is the
+// finaliser applied to the state seed + (n + 1) * golden-gamma.  Consecutive
+// draws of one slot only add the gamma to the state; only the upper 32 bits
+// of the output are used (the index draw below).
+constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint32_t splitmix64_hi(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
+    return (uint32_t)((z ^ (z >> 31)) >> 32);
 }
 
 constexpr int CT = 256;      // threads per block
-constexpr int CPT = 32;      // trials per thread
+constexpr int CPT = 32;      // trials per thread (on average)
+constexpr int QCAP = 128;    // per-wavefront ring of drawn quadruples awaiting the edge test
 constexpr int MB_LDS = 8192; // largest bitmap staged in LDS (words): fragments up to 524,288 points
 
 // Coordinates of each reciprocal correspondence, packed so that one trial
@@ -100,60 +106,122 @@ __global__ void __launch_bounds__(256) k_corr_pack(const Frag *frag, const Blk *
     cpack[2 * (P.off + i) + 1] = make_float4(Q.src[1][j], Q.src[2][j], 0.f, 0.f);
 }
 
+// Edge test of one drawn quadruple; flags its correspondences when it passes.
+__device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, int32_t *flag) {
+    const int id[4] = {e.x, e.y, e.z, e.w};
+    float4 a0[4], a1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { a0[k] = cp[2 * id[k]]; a1[k] = cp[2 * id[k] + 1]; }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int k1 = (k + 1) & 3;
+        double a = pdist2(a0[k].x, a0[k].y, a0[k].z, a0[k1].x, a0[k1].y, a0[k1].z);
+        double c = pdist2(a0[k].w, a1[k].x, a1[k].y, a0[k1].w, a1[k1].x, a1[k1].y);
+        if (a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a) ok = false;
+    }
+    if (!ok) return 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) flag[id[k]] = 1;
+    return 1;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Each wavefront owns a contiguous range of 64 * CPT trials of one pair and
+// hands them to its lanes on demand: a lane draws one index per iteration,
+// takes the next unclaimed trial when its current one completes or fails, and
+// parks a complete quadruple in a wavefront ring; 64 parked quadruples are
+// tested together.  Which lane runs which trial changes neither the draws
+// (they depend only on the trial index) nor the result (flags are set, counts
+// summed).
 __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const uint64_t *mbits,
                                                     const float4 *cpack, int32_t *flag, double t2, uint64_t seed,
                                                     int use_lds, PairState *ps) {
     extern __shared__ uint64_t bm[];
+    __shared__ int4 ring[CT / 64][QCAP];
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
-    const uint64_t nP = (uint64_t)P.n;
+    const uint32_t nP = (uint32_t)P.n;
     const int nw = (P.n + 63) / 64;
     const uint64_t *gbits = mbits + mbits_base(P, 2 * b.pair);
     if (use_lds)
         for (int k = threadIdx.x; k < nw; k += CT) bm[k] = gbits[k];
     __syncthreads();
-    const uint64_t *bits = use_lds ? bm : gbits;
+    const uint32_t *bits = (const uint32_t *)(use_lds ? bm : gbits);
     const float4 *cp = cpack + 2 * P.off;
-    int passed = 0;
-    for (int r = 0; r < CPT; ++r) {
-        int64_t t = b.first + (int64_t)r * CT + threadIdx.x;
-        if (t >= b.count || nP == 0) break;
-        int32_t id[4];
-        bool ok = true;
-        for (int sl = 0; sl < 4 && ok; ++sl) {
-            bool found = false;
-            for (int a = 0; a < 64; ++a) {
-                uint64_t rr = splitmix64_at(seed, ((uint64_t)t << 8) | ((uint64_t)sl << 6) | (uint64_t)a);
-                int32_t i = (int32_t)(((rr >> 32) * nP) >> 32);
-                if (!((bits[i >> 6] >> (i & 63)) & 1ull)) continue;
-                bool dup = false;
-                for (int u = 0; u < sl; ++u) dup |= id[u] == i;
-                if (dup) continue;
-                id[sl] = i;
-                found = true;
-                break;
+    int32_t *fl = flag + P.off;
+    const int lane = threadIdx.x & 63;
+    int4 *q = ring[threadIdx.x >> 6];
+    const int64_t wbeg = b.first + (int64_t)(threadIdx.x >> 6) * (64 * CPT);
+    const int64_t wend = nP ? min(b.count, wbeg + 64 * CPT) : wbeg;
+    int64_t next = wbeg;                       // next unclaimed trial (uniform)
+    uint32_t qhead = 0, qtail = 0;             // ring cursors (uniform)
+    bool live = false;
+    uint64_t zslot = 0, z = 0;                 // SplitMix64 state at the slot's first draw, at the current draw
+    int sl = 0, a = 0, id0 = 0, id1 = 0, id2 = 0, passed = 0;
+    for (;;) {
+        const uint64_t need = __ballot(!live);
+        if (!live) {
+            const int64_t t = next + lanes_below(need);
+            if (t < wend) {
+                live = true;
+                sl = 0;
+                a = 0;
+                zslot = z = seed + (((uint64_t)t << 8) + 1ull) * GAMMA;
             }
-            ok = found;
         }
-        if (!ok) continue;
-        float4 a0[4], a1[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { a0[k] = cp[2 * id[k]]; a1[k] = cp[2 * id[k] + 1]; }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int k1 = (k + 1) & 3;
-            double a = pdist2(a0[k].x, a0[k].y, a0[k].z, a0[k1].x, a0[k1].y, a0[k1].z);
-            double c = pdist2(a0[k].w, a1[k].x, a1[k].y, a0[k1].w, a1[k1].x, a1[k1].y);
-            if (a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a) ok = false;
+        next += __popcll(need);
+        if (!__ballot(live)) break;
+        int4 quad;
+        bool push = false;
+        if (live) {
+            const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z) * nP) >> 32);
+            bool hit = (bits[i >> 5] >> (i & 31)) & 1u;
+            hit = hit && !(sl > 0 && (int)i == id0) && !(sl > 1 && (int)i == id1) && !(sl > 2 && (int)i == id2);
+            if (hit) {
+                if (sl == 3) {
+                    quad = make_int4(id0, id1, id2, (int)i);
+                    push = true;
+                    live = false;
+                } else {
+                    id0 = sl == 0 ? (int)i : id0;
+                    id1 = sl == 1 ? (int)i : id1;
+                    id2 = sl == 2 ? (int)i : id2;
+                    ++sl;
+                    a = 0;
+                    zslot += 64ull * GAMMA;   // n advances by one slot (1 << 6)
+                    z = zslot;
+                }
+            } else if (++a == 64) {
+                live = false;                  // slot exhausted: the trial fails
+            } else {
+                z += GAMMA;
+            }
         }
-        if (!ok) continue;
-        ++passed;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) flag[P.off + id[k]] = 1;
+        const uint64_t pm = __ballot(push);
+        if (push) q[(qtail + lanes_below(pm)) & (QCAP - 1)] = quad;
+        qtail += __popcll(pm);
+        if (qtail - qhead >= 64) {
+            wave_lds_sync();
+            passed += quad_test(cp, q[(qhead + lane) & (QCAP - 1)], t2, fl);
+            qhead += 64;
+            wave_lds_sync();
+        }
     }
+    wave_lds_sync();
+    if ((uint32_t)lane < qtail - qhead) passed += quad_test(cp, q[(qhead + lane) & (QCAP - 1)], t2, fl);
     // passing-trial count per pair (integer, order independent)
     for (int o = 32; o > 0; o >>= 1) passed += __shfl_xor(passed, o, 64);
-    if ((threadIdx.x & 63) == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
+    if (lane == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
 }
 
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb, int max_nP,
