@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=2)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -115,6 +117,17 @@ def main():
             traffic = tr.get("bytes_per_launch")
     log(f"screen kernel {scr:.3f} ms/launch -> {achieved:.1f} TFLOP/s algorithmic")
     log("stages (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in stage_ms.items()))
+
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: reads and writes calib_copy_mib MiB once
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del a, c
 
     # plain float32 per-pair baseline (host loop, no graph)
     base = None

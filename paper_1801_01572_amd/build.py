@@ -28,7 +28,7 @@ def _hipcc():
 
 
 # the matrix-core screen only compares finite scores: no NaN canonicalisation
-EXTRA = {"match_bf16.hip": ["-fno-honor-nans"]}
+EXTRA = {"match_bf16.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src, verbose):

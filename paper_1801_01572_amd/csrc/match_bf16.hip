@@ -206,6 +206,15 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
 
 // ---------------------------------------------------------------- screen
 
+// A staged row is 8 chunks of 16 bytes (hi 0-3, lo 4-7).  Chunk q of row r
+// sits at position q ^ lds_swz(r): the 16 lanes that read chunk g of 16
+// consecutive rows then touch every bank once (and any 8 of them distinct
+// banks), where the plain layout (128-byte rows) put 8 lanes on one bank.
+__device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+__device__ __forceinline__ int lds_slot(int idx) {            // uint4 index of chunk idx & 7 of row idx >> 3
+    return (idx & ~7) | ((idx & 7) ^ lds_swz(idx >> 3));
+}
+
 // COLLECT = false: every row of the fragment is a query; write the best tile
 // and second-best tile maximum per lane group.
 // COLLECT = true: the queries are the fragment's uncertified rows (slots
@@ -228,6 +237,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     const Frag &Fc = frag[Fq.partner];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
+    const int swz = lds_swz(col);
 
     // query operands: [y_hi, 1, 1] and [y_lo, 0, 0] of this wave's 4 blocks of 16 queries
     bf16x8 Bh[SQB], Bl[SQB];
@@ -262,7 +272,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 #pragma unroll
     for (int u = 0; u < PER; ++u) r[u] = nch > 0 ? src[threadIdx.x + u * SW * 64] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[threadIdx.x + u * SW * 64] = r[u];
+    for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
     __syncthreads();
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     // Software pipeline: the MFMAs of tile t are issued before the epilogue of
@@ -274,10 +284,11 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
         for (int k = 0; k < SQB; ++k) {
             const f32x4 acc = accs[k];
             if (!COLLECT) {
-                float tm = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-                v2[k] = fmaxf(v2[k], fminf(v1[k], tm));
+                // v2 <= v1 always, so max(v2, min(v1, tm)) is the median of the three
+                float tm = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
+                v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);
                 c1[k] = tm > v1[k] ? tile : c1[k];
-                v1[k] = fmaxf(v1[k], tm);
+                v1[k] = __builtin_fmaxf(v1[k], tm);
             } else {
                 bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
                 if (hit) {                                 // rare: near-ties of uncertified rows
@@ -299,12 +310,12 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 #pragma unroll
             for (int u = 0; u < PER; ++u) r[u] = nx[threadIdx.x + u * SW * 64];
         }
-        const uint16_t *L = lds[buf];
+        const uint4 *L = (const uint4 *)lds[buf];
 #pragma unroll 2
         for (int t = 0; t < CH; ++t) {
-            const uint16_t *rowp = L + (t * 16 + col) * PK + 8 * grp;
-            bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4 *)rowp);
-            bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4 *)(rowp + 32));
+            const uint4 *rowp = L + (t * 16 + col) * 8;
+            bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
+            bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
             // three chained products per query block, the four blocks interleaved so
             // that each chain step has three independent MFMAs between it and its input
             f32x4 accs[SQB];
@@ -321,7 +332,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
         }
         if (ch + 1 < nch) {
 #pragma unroll
-            for (int u = 0; u < PER; ++u) ((uint4 *)lds[buf ^ 1])[threadIdx.x + u * SW * 64] = r[u];
+            for (int u = 0; u < PER; ++u) ((uint4 *)lds[buf ^ 1])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
         }
         __syncthreads();
     }
