@@ -124,7 +124,7 @@ def main():
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         c = torch.empty_like(a)
         torch.cuda.synchronize()
-        c.copy_(a)
+        torch.mul(a, 1.0, out=c)              # an elementwise kernel (a same-type copy_ would be a DMA copy)
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
         del a, c

@@ -7,12 +7,16 @@
 // Helmert contrasts h_k = (x_0 + .. + x_{k-1} - k x_k) / sqrt(k (k+1)),
 // k = 1..10, the 33-vector maps to y (30 numbers) with |F_i - F_j| = |y_i - y_j|.
 // y is centred on the pair's mean descriptor (distances unchanged, smaller
-// magnitudes).  y is split into bf16 hi + lo parts.  A candidate row is
-// [y_hi, c_hi, c_lo | y_lo, 0, 0] with c_hi + c_lo = -|y_j|^2 / 2; a query row
-// is [y_hi, 1, 1 | y_lo, 0, 0].  Three chained 16x16x32 bf16 MFMAs
-// (hi.hi, lo_cand.hi_query, hi_cand.lo_query) give
-//   s_ij = y_i . y_j - |y_j|^2 / 2 = (|y_i|^2 - D_ij) / 2
-// to about 2^-16 relative, so the best candidate maximises s.
+// magnitudes).  y is split into bf16 hi + lo parts (hi + lo within 2^-18 of
+// y).  A candidate row is [y_hi, c_hi, c_lo | y_lo, 0, 0] with
+// c_hi + c_lo = -|y_j|^2 / 2; a query enters rounded once, as [y_hi, 1, 1].
+// Two chained 16x16x32 bf16 MFMAs (hi_cand.hi_query, lo_cand.hi_query) give
+//   t_ij = yh_i . y_j - |y_j|^2 / 2,   yh_i = bf16(y_i),
+// while the exact score is s_ij = y_i . y_j - |y_j|^2 / 2 = (|y_i|^2 - D_ij) / 2.
+// With d_i = y_i - yh_i, s_ij - t_ij = d_i . y_j = c_i + d_i . (y_j - y_i),
+// c_i = d_i . y_i: a per-query constant (no effect on the ranking) plus a
+// term bounded by |d_i| sqrt(D_ij), small exactly for the candidates that
+// compete for the minimum.
 //
 // Screen.  A wave owns 4 blocks of 16 queries and sweeps the partner's rows
 // 16 at a time from LDS (chunks of 128 rows, double buffered).  Lane l sees
@@ -22,16 +26,17 @@
 //
 // Certification.  The 16 rows of the four groups' best tiles are re-ranked
 // with the exact float32 distance d2_row, giving D*.  A row j outside them has
-// a screened score <= A2, the largest second-best tile maximum.  Only rows
-// with D_ij <= D* can matter, and those have |y_j| <= |y_i| + sqrt(D*) = R,
-// so their screen error is at most E = 2^-15 (|y_i| R + R^2 / 2) (bf16 split
-// rounding and float32 accumulation, with margin).  If
-// D* + slack < |y_i|^2 - 2 (A2 + E) no outside row can win and D* with its
-// index is the float32 scan's answer.  Otherwise the row goes to a second
-// screen that collects every candidate whose score reaches
-// theta = (|y_i|^2 - D* - slack) / 2 - E (a superset of all rows that can tie
-// or beat D*), and those are re-ranked exactly.  Only a row with more than
-// LCAP such candidates is rescanned in float32.
+// a screened score t_ij <= A2, the largest second-best tile maximum.  Only
+// rows with D_ij <= D* + slack can matter; those have
+// |y_j| <= |y_i| + sqrt(D* + slack) = R and s_ij <= t_ij + c_i + E with
+// E = |d_i| sqrt(D* + slack) + 2^-15 (|y_i| R + R^2 / 2) (the second term
+// covers the candidate split, the norm slots and float32 accumulation, with
+// margin).  If D* + slack < |y_i|^2 - 2 (A2 + c_i + E) no outside row can win
+// and D* with its index is the float32 scan's answer.  Otherwise the row goes
+// to a second screen that collects every candidate whose screened score
+// reaches theta = (|y_i|^2 - D* - slack) / 2 - c_i - E (a superset of all rows
+// that can tie or beat D*), and those are re-ranked exactly.  Only a row with
+// more than LCAP such candidates is rescanned in float32.
 #include "match_common.h"
 
 namespace lsr {
@@ -43,7 +48,7 @@ constexpr int SW = 4;              // waves per block
 constexpr int SQB = 4;             // 16-query blocks per wave (64 queries per wave, 256 per block)
 constexpr int CH = 8;              // 16-row tiles per LDS chunk
 constexpr int CROWS = CH * 16;     // rows per chunk (128); fragments are padded to this
-constexpr int LCAP = 64;           // candidates collected per uncertified row
+constexpr int LCAP = 32;           // candidates collected per uncertified row
 
 __device__ __forceinline__ uint16_t f2bf(float f) {     // round to nearest even
     uint32_t u = __float_as_uint(f);
@@ -54,7 +59,7 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 struct ScreenScratch {
     float *mean;          // (nfrag/2 + 1) x 32: projected centring vector per pair
-    float *yn2;           // pk_rows: |y|^2
+    float4 *yq;           // pk_rows: (|y|^2, c = d . y, |d|, 0) with d = y - bf16(y)
     int32_t *c1;          // ntot x 4: best tile per lane group
     float *v2;            // ntot x 4: second-best tile maximum per lane group
     int32_t *fb_row;      // ntot: uncertified rows, per fragment from Frag::off
@@ -65,10 +70,10 @@ struct ScreenScratch {
     int32_t *full_row, *full_frag, *full_cnt;
 };
 
-// list slots of fragment f: [off/16 + 64 f, ... + n/16 + 64)
-__device__ __forceinline__ int64_t lst_base(const Frag &F, int f) { return F.off / 16 + 64 * (int64_t)f; }
-__device__ __forceinline__ int32_t lst_cap(const Frag &F) { return F.n / 16 + 64; }
-static int64_t lst_slots(const GridBufs &g) { return g.ntot / 16 + 64 * (int64_t)g.nfrag + 64; }
+// list slots of fragment f: [off/4 + 64 f, ... + n/4 + 64)
+__device__ __forceinline__ int64_t lst_base(const Frag &F, int f) { return F.off / 4 + 64 * (int64_t)f; }
+__device__ __forceinline__ int32_t lst_cap(const Frag &F) { return F.n / 4 + 64; }
+static int64_t lst_slots(const GridBufs &g) { return g.ntot / 4 + 64 * (int64_t)g.nfrag + 64; }
 
 static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     char *p = (char *)base;
@@ -77,7 +82,7 @@ static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     const size_t n1 = (size_t)std::max<int64_t>(g.ntot, 1);
     ScreenScratch s;
     s.mean = (float *)take(sizeof(float) * 32 * (size_t)(g.nfrag / 2 + 1));
-    s.yn2 = (float *)take(sizeof(float) * (size_t)std::max<int64_t>(g.pk_rows, 1));
+    s.yq = (float4 *)take(sizeof(float4) * (size_t)std::max<int64_t>(g.pk_rows, 1));
     s.c1 = (int32_t *)take(sizeof(int32_t) * 4 * n1);
     s.v2 = (float *)take(sizeof(float) * 4 * n1);
     s.fb_row = (int32_t *)take(sizeof(int32_t) * n1);
@@ -153,7 +158,7 @@ __global__ void __launch_bounds__(256) k_desc_mean(const Frag *frag, int nfrag, 
 }
 
 __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                              const float *mean, uint16_t *pk, float *yn2) {
+                                              const float *mean, uint16_t *pk, float4 *yq) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
     int i = b.start + threadIdx.x;
@@ -161,7 +166,8 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
     if (i >= npad) return;
     int64_t row = Fr.pk_off + i;
     uint16_t hi[32], lo[32];
-    float n2 = 0.f;
+    float n2 = 0.f, dd = 0.f;
+    double dy = 0.0;
     bool v = i < Fr.n && valid[Fr.off + i];
     if (v) {
         const float *x = F + (Fr.off + i) * FD;
@@ -177,7 +183,10 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
             h[c] -= m[c];
             n2 = fmaf(h[c], h[c], n2);
             hi[c] = f2bf(h[c]);
-            lo[c] = f2bf(h[c] - bf2f(hi[c]));
+            const float d = h[c] - bf2f(hi[c]);              // exact
+            lo[c] = f2bf(d);
+            dd = fmaf(d, d, dd);
+            dy += (double)d * (double)h[c];
         }
         float cc = -0.5f * n2;
         hi[30] = f2bf(cc);
@@ -201,7 +210,7 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
         w.w = o[6] | ((uint32_t)o[7] << 16);
         dst[q] = w;
     }
-    yn2[row] = n2;
+    yq[row] = make_float4(n2, (float)dy, sqrtf(dd) * 1.0001f, 0.f);
 }
 
 // ---------------------------------------------------------------- screen
@@ -239,25 +248,23 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     const int col = lane & 15, grp = lane >> 4;
     const int swz = lds_swz(col);
 
-    // query operands: [y_hi, 1, 1] and [y_lo, 0, 0] of this wave's 4 blocks of 16 queries
-    bf16x8 Bh[SQB], Bl[SQB];
+    // query operands: [y_hi, 1, 1] of this wave's 4 blocks of 16 queries
+    bf16x8 Bh[SQB];
     float th[SQB];
     const int qw = b.start + wv * SQB * 16;
 #pragma unroll
     for (int k = 0; k < SQB; ++k) {
         int slot = qw + 16 * k + col;
-        uint4 wh = make_uint4(0, 0, 0, 0), wl = wh;
+        uint4 wh = make_uint4(0, 0, 0, 0);
         th[k] = INFINITY;
         if (slot < nq) {
             int q = COLLECT ? fb_row[Fq.off + slot] : slot;
             const uint16_t *r = pk + (Fq.pk_off + q) * PK;
             wh = *(const uint4 *)(r + 8 * grp);
-            wl = *(const uint4 *)(r + 32 + 8 * grp);
             if (COLLECT) th[k] = thr[Fq.off + slot];
         }
         if (grp == 3) wh.w = 0x3f803f80u;                     // slots 30, 31 = 1.0
         Bh[k] = __builtin_bit_cast(bf16x8, wh);
-        Bl[k] = __builtin_bit_cast(bf16x8, wl);
     }
     float v1[SQB], v2[SQB];
     int32_t c1[SQB];
@@ -316,15 +323,13 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             const uint4 *rowp = L + (t * 16 + col) * 8;
             bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
             bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
-            // three chained products per query block, the four blocks interleaved so
+            // two chained products per query block, the four blocks interleaved so
             // that each chain step has three independent MFMAs between it and its input
             f32x4 accs[SQB];
 #pragma unroll
             for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
-#pragma unroll
-            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bl[k], accs[k], 0, 0, 0);
             if (prev_tile >= 0) epilogue(prev, prev_tile);
 #pragma unroll
             for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
@@ -361,15 +366,16 @@ __device__ __forceinline__ void load_row(const float *F, int64_t r, float *x) {
 
 // Error bound of the screen for competitors of a row with |y_i|^2 = ny2 and
 // current best D (see the file header).
-__device__ __forceinline__ float screen_err(float ny2, float best) {
-    float yi = sqrtf(ny2);
-    float R = (yi + sqrtf(best)) * 1.0001f + 1e-6f;
-    return 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;      // 2^-15 (|y_i| R + R^2 / 2)
-}
 __device__ __forceinline__ float slack(float best) { return best * 3e-6f + 1e-7f; }
+__device__ __forceinline__ float screen_err(float4 q, float best) {
+    const float yi = sqrtf(q.x);
+    const float Rp = sqrtf(best + slack(best)) * 1.0001f + 1e-6f;     // bound on |y_j - y_i| of competitors
+    const float R = yi * 1.0001f + Rp;                                 // bound on |y_j|
+    return q.z * Rp + 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;   // |d_i| Rp + 2^-15 (|y_i| R + R^2 / 2)
+}
 
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                                const float *yn2, const int32_t *c1, const float *v2, int32_t *nn,
+                                                const float4 *yq, const int32_t *c1, const float *v2, int32_t *nn,
                                                 float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
                                                 int32_t *full_row, int32_t *full_frag, int32_t *full_cnt,
                                                 PairState *ps) {
@@ -402,9 +408,10 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                     if (d < best || (d == best && j < bj)) { best = d; bj = j; }
                 }
             }
-            float ny2 = yn2[Fq.pk_off + i];
-            float E = screen_err(ny2, best);
-            bool cert = a2 == -INFINITY || (bj >= 0 && best + slack(best) < ny2 - 2.0f * (a2 + E));
+            const float4 qv = yq[Fq.pk_off + i];
+            const float ny2 = qv.x;
+            float E = screen_err(qv, best);
+            bool cert = a2 == -INFINITY || (bj >= 0 && best + slack(best) < ny2 - 2.0f * (a2 + qv.y + E));
             if (cert) {
                 nn[gi] = bj;
                 dist[gi] = best;
@@ -412,7 +419,7 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                 fb = true;
                 int k = atomicAdd(&fb_cnt[b.frag], 1);
                 fb_row[Fq.off + k] = i;
-                thr[Fq.off + k] = bj >= 0 ? 0.5f * (ny2 - best - slack(best)) - E : -INFINITY;
+                thr[Fq.off + k] = bj >= 0 ? 0.5f * (ny2 - best - slack(best)) - qv.y - E : -INFINITY;
                 if (k >= lst_cap(Fq) || bj < 0) {               // no list slot: rescan in float32
                     int r = atomicAdd(full_cnt, 1);
                     full_row[r] = i;
@@ -520,14 +527,14 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     hipLaunchKernelGGL(k_desc_mean, dim3(npair), dim3(256), 0, s, (const Frag *)g.frag, g.nfrag, (const float *)d.F,
                        (const int32_t *)d.valid, S.mean);
     hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, d.pk, S.yn2);
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, d.pk, S.yq);
     tmark("pack", s);
     hipLaunchKernelGGL(k_screen<false>, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
                        (const Blk *)g.blk256, (const uint16_t *)d.pk, S.c1, S.v2, nullptr, nullptr, nullptr, nullptr,
                        nullptr);
     tmark("screen", s);
     hipLaunchKernelGGL(k_rerank, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.yn2, (const int32_t *)S.c1,
+                       (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
                        (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                        S.full_cnt, ps);
     tmark("rerank", s);
