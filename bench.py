@@ -43,6 +43,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -74,6 +75,13 @@ def main():
 
     prm = lsr.default_params(precision=lsr.BF16_SCREEN)
     out = torch.empty(npairs * lsr._lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    tune = None
+    if not args.no_autotune:                   # setup, like plan creation: outside the timed region
+        ta = time.perf_counter()
+        tune = lsr.autotune(Pd, Qd, offP, offQ, prm, reps=1)
+        log(f"autotune ({time.perf_counter() - ta:.1f}s): screen shape {tune['screen_shape']} "
+            f"{[round(x, 2) for x in tune['screen_ms']]} ms, consistency shape {tune['consistency_shape']} "
+            f"{[round(x, 2) for x in tune['consistency_ms']]} ms")
     for w in range(args.warmup):
         tw = time.perf_counter()
         lsr.register_batch(Pd, Qd, offP, offQ, prm, out=out, sync=False)
@@ -186,6 +194,7 @@ def main():
                      "traffic": traffic, "ms_per_launch": round(scr, 4), "flops_per_launch": flops},
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "autotune": tune,
         "accepted_fraction": round(acc, 4),
         "bf16_fallback_rows": fb,
     }

@@ -173,6 +173,40 @@ int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t n
 int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *const out[6],
                          int64_t *d_count, void *stream);
 
+/* ---- autotuning of the batch driver's launch shapes ---- */
+
+#define LSR_MAX_VARIANTS 8
+
+/* Launch-shape choice of a context (not a parameter of the method: every
+ * variant computes the same bits).  screen_shape picks the bf16 screen's
+ * waves per block, query blocks per wave and rows per LDS chunk;
+ * consistency_shape picks the trial kernel's block width.  screen_ms and
+ * consistency_ms: mean time of each variant in the last lsr_autotune call
+ * (the whole bf16 matching stage, and the consistency stage), in ms. */
+typedef struct {
+    int32_t screen_shape, consistency_shape;
+    int32_t n_screen_shapes, n_consistency_shapes;
+    float screen_ms[LSR_MAX_VARIANTS];
+    float consistency_ms[LSR_MAX_VARIANTS];
+} lsr_tune;
+
+/*
+ * Times every variant of the tuned kernels on the given batch (arguments as
+ * lsr_register_batch, without the output; the screen is tuned with
+ * precision LSR_BF16_SCREEN whatever prm asks) over `reps` runs each and
+ * keeps the fastest in the context.  Cached plans are dropped when the
+ * choice changes, so later calls capture graphs with the chosen kernels.
+ * Allocates scratch and synchronises the stream; not for capture.  *out
+ * (may be NULL) receives the choice and the timings.
+ */
+int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                 const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, int32_t reps,
+                 lsr_tune *out, void *stream);
+/* Current choice (timings zero); set a saved choice (LSR_EINVAL if a
+ * variant index is out of range; drops cached plans when it changes). */
+int lsr_get_tune(lsr_ctx *ctx, lsr_tune *out);
+int lsr_set_tune(lsr_ctx *ctx, const lsr_tune *t);
+
 /* ---- stage entry points: one stage on injected inputs (parity checks) ---- */
 
 /* Normals (n x 3 doubles, row-major, device) of one cloud; PCA over the

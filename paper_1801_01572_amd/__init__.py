@@ -9,7 +9,7 @@ A cloud is a float32 CUDA tensor of shape (6, N): rows x, y, z, nx, ny, nz.
 from ._lib import (  # noqa: F401
     ACCEPTED, REJECTED, DEGENERATE, FP32, BF16_SCREEN,
     Params, Result, LsrError, lib, default_params, Context, get_context,
-    voxel_downsample, register_pair, register_batch, align_loss, align_loss_backward, set_timing, get_timing,
+    voxel_downsample, register_pair, register_batch, autotune, get_tune, set_tune, align_loss, align_loss_backward, set_timing, get_timing,
     stage_normals, stage_spfh, stage_fpfh, stage_match, stage_consistency, stage_gnc, stage_verify,
 )
 from .autograd import AlignLoss  # noqa: F401

@@ -41,6 +41,15 @@ class Result(C.Structure):
     ]
 
 
+MAX_VARIANTS = 8
+
+
+class Tune(C.Structure):
+    _fields_ = [("screen_shape", C.c_int32), ("consistency_shape", C.c_int32),
+                ("n_screen_shapes", C.c_int32), ("n_consistency_shapes", C.c_int32),
+                ("screen_ms", C.c_float * MAX_VARIANTS), ("consistency_ms", C.c_float * MAX_VARIANTS)]
+
+
 class Cloud(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("nx", C.c_void_p), ("ny", C.c_void_p), ("nz", C.c_void_p), ("n", C.c_int64)]
@@ -74,10 +83,15 @@ def lib():
         L.lsr_stage_verify.argtypes = [vp, C.POINTER(Cloud), vp, C.POINTER(Cloud), vp, vp, C.c_float, i32,
                                        C.c_float, vp, vp]
         L.lsr_set_timing.argtypes = [vp, C.c_int]
+        L.lsr_autotune.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32, C.POINTER(Params), i32,
+                                   C.POINTER(Tune), vp]
+        L.lsr_get_tune.argtypes = [vp, C.POINTER(Tune)]
+        L.lsr_set_tune.argtypes = [vp, C.POINTER(Tune)]
         L.lsr_get_timing.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
         for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch", "lsr_align_loss",
                   "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_voxel_downsample", "lsr_stage_match",
-                  "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify"):
+                  "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify", "lsr_autotune", "lsr_get_tune",
+                  "lsr_set_tune"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -184,6 +198,44 @@ def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params:
     ctx.check(lib().lsr_register_batch(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
                                        offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), _ptr(out), _stream()))
     return _parse_results(out, n) if sync else out
+
+
+def _tune_dict(t: Tune) -> dict:
+    return {"screen_shape": t.screen_shape, "consistency_shape": t.consistency_shape,
+            "screen_ms": list(t.screen_ms[:t.n_screen_shapes]),
+            "consistency_ms": list(t.consistency_ms[:t.n_consistency_shapes])}
+
+
+def autotune(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params: Params | None = None, reps: int = 2,
+             ctx: Context | None = None) -> dict:
+    """Time every launch-shape variant on this batch and keep the fastest (lsr_autotune)."""
+    ctx = ctx or get_context(P_all.device.index)
+    prm = params or default_params()
+    offP = np.ascontiguousarray(offP, np.int64)
+    offQ = np.ascontiguousarray(offQ, np.int64)
+    n = len(offP) - 1
+    if len(offQ) != n + 1:
+        raise LsrError("offP and offQ must have the same length")
+    cp, cq = _cloud(P_all), _cloud(Q_all)
+    t = Tune()
+    ctx.check(lib().lsr_autotune(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
+                                 offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), reps, C.byref(t), _stream()))
+    return _tune_dict(t)
+
+
+def get_tune(ctx: Context | None = None) -> dict:
+    ctx = ctx or get_context()
+    t = Tune()
+    ctx.check(lib().lsr_get_tune(ctx.h, C.byref(t)))
+    return {"screen_shape": t.screen_shape, "consistency_shape": t.consistency_shape,
+            "n_screen_shapes": t.n_screen_shapes, "n_consistency_shapes": t.n_consistency_shapes}
+
+
+def set_tune(screen_shape: int, consistency_shape: int, ctx: Context | None = None):
+    ctx = ctx or get_context()
+    t = Tune()
+    t.screen_shape, t.consistency_shape = screen_shape, consistency_shape
+    ctx.check(lib().lsr_set_tune(ctx.h, C.byref(t)))
 
 
 def voxel_downsample(cloud: torch.Tensor, voxel: float, ctx: Context | None = None):

@@ -26,8 +26,10 @@ hipError_t launch_align(bool bwd, const float *const P[3], int64_t nP, const flo
                         const void *dev_tab, int64_t nblocks, const int64_t *dev_pblk, int nprob, const double *T,
                         const double *mu, const double *dE, double *partial, double *out, float *const dP[3],
                         float *const dQ[3], hipStream_t s);
-hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch,
+hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch, int shape,
                              hipStream_t s);
+int screen_shapes();
+int consistency_shapes();
 size_t voxel_sort_bytes(int64_t n);
 size_t voxel_ws_bytes(int64_t n);
 hipError_t launch_voxel(const float *const *src_dev, const float *const src[6], int64_t n, float v,
@@ -118,6 +120,8 @@ void tmark(const char *name, hipStream_t s) {
 
 struct lsr_ctx {
     int device = 0;
+    int tune_screen = 0;           // screen shape variant (autotuned)
+    int tune_cons = 0;             // consistency block-width variant (autotuned)
     std::string err = "no error";
     std::vector<std::unique_ptr<Plan>> plans;   // most recently used last
 };
@@ -357,14 +361,14 @@ int run_pairs(lsr_ctx *c, Plan *P, const lsr_params &prm, lsr_result *d_out, hip
     HIPCHK(c, launch_fpfh(P->g, prm.r_feature, P->d, P->ps, s));
     tmark("fpfh", s);
     if (prm.precision == LSR_BF16_SCREEN) {
-        HIPCHK(c, launch_match_bf16(P->g, P->d, P->m, P->ps, P->mscratch, s));
+        HIPCHK(c, launch_match_bf16(P->g, P->d, P->m, P->ps, P->mscratch, c->tune_screen, s));
         tmark("fallback", s);
     } else {
         HIPCHK(c, launch_match_fp32(P->g, P->d, P->m, s));
         tmark("match_fp32", s);
     }
     HIPCHK(c, launch_mutual(P->g, P->m, P->ps, s));
-    HIPCHK(c, launch_consistency(P->g, P->m, P->ps, P->tb, P->ntb, P->max_nP, prm.tau, prm.seed, s));
+    HIPCHK(c, launch_consistency(P->g, P->m, P->ps, P->tb, P->ntb, P->max_nP, prm.tau, prm.seed, c->tune_cons, s));
     tmark("consistency", s);
     HIPCHK(c, launch_compact(P->g, P->m, P->ps, P->scan_tmp, s));
     HIPCHK(c, launch_gnc(P->g, P->m, P->ps, P->npairs, prm, s));
@@ -497,29 +501,75 @@ int lsr_register_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, cons
     return run_pairs(ctx, pl, *prm, d_out, s);
 }
 
-int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
-                       const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out, void *stream) {
-    if (!ctx) return LSR_EINVAL;
+}  // extern "C"
+
+namespace {
+// Checks a batch call's arguments and lists its fragments (P_b, Q_b per pair).
+int batch_frags(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP, const int64_t *offQ,
+                int32_t n_pairs, const lsr_params *prm, std::vector<FragIn> &fr) {
     int rc;
     if ((rc = check_params(ctx, prm)) || (rc = check_cloud(ctx, P_all, "P_all", true)) ||
         (rc = check_cloud(ctx, Q_all, "Q_all", true)))
         return rc;
     if (n_pairs < 0 || n_pairs > (1 << 20)) return fail(ctx, LSR_EINVAL, "n_pairs %d out of range", n_pairs);
     if (n_pairs == 0) return LSR_OK;
-    if (!offP || !offQ || !d_out) return fail(ctx, LSR_EINVAL, "NULL offsets or output");
+    if (!offP || !offQ) return fail(ctx, LSR_EINVAL, "NULL offsets");
     for (int b = 0; b < n_pairs; ++b) {
         if (offP[b] < 0 || offP[b + 1] < offP[b] || offP[b + 1] > P_all->n || offQ[b] < 0 || offQ[b + 1] < offQ[b] ||
             offQ[b + 1] > Q_all->n)
             return fail(ctx, LSR_EINVAL, "bad offsets at pair %d", b);
     }
-    HIPCHK(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<FragIn> fr;
+    fr.clear();
     fr.reserve(2 * n_pairs);
     for (int b = 0; b < n_pairs; ++b) {
         fr.push_back(frag_of(P_all, offP[b], offP[b + 1] - offP[b]));
         fr.push_back(frag_of(Q_all, offQ[b], offQ[b + 1] - offQ[b]));
     }
+    return LSR_OK;
+}
+
+// Drops every cached plan (their graphs hold the previous kernel variants).
+int drop_plans(lsr_ctx *c) {
+    HIPCHK(c, hipDeviceSynchronize());
+    c->plans.clear();
+    return LSR_OK;
+}
+
+// Mean time of `reps` runs of fn on stream s (one untimed run first).
+template <class Fn>
+int time_ms(lsr_ctx *c, hipStream_t s, int reps, Fn &&fn, float *ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(c, LSR_EHIP, "hipEventCreate"); }
+    int rc = fn();
+    hipError_t e = hipSuccess;
+    if (!rc) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !rc && e == hipSuccess; ++r) rc = fn();
+    if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(c, LSR_EHIP, "timing: %s", hipGetErrorString(e));
+    *ms = t / (float)reps;
+    return LSR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                       const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    std::vector<FragIn> fr;
+    if ((rc = batch_frags(ctx, P_all, Q_all, offP, offQ, n_pairs, prm, fr))) return rc;
+    if (n_pairs == 0) return LSR_OK;
+    if (!d_out) return fail(ctx, LSR_EINVAL, "NULL output");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
     std::vector<char> key;
     put(key, (int)K_PAIRS + 100);
     put(key, *prm);
@@ -539,6 +589,85 @@ int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_
         HIPCHK(ctx, hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0));
     }
     HIPCHK(ctx, hipGraphLaunch(pl->gexec, s));
+    return LSR_OK;
+}
+
+int lsr_get_tune(lsr_ctx *ctx, lsr_tune *out) {
+    if (!ctx || !out) return LSR_EINVAL;
+    std::memset(out, 0, sizeof *out);
+    out->screen_shape = ctx->tune_screen;
+    out->consistency_shape = ctx->tune_cons;
+    out->n_screen_shapes = screen_shapes();
+    out->n_consistency_shapes = consistency_shapes();
+    return LSR_OK;
+}
+
+int lsr_set_tune(lsr_ctx *ctx, const lsr_tune *t) {
+    if (!ctx || !t) return LSR_EINVAL;
+    if (t->screen_shape < 0 || t->screen_shape >= screen_shapes() || t->consistency_shape < 0 ||
+        t->consistency_shape >= consistency_shapes())
+        return fail(ctx, LSR_EINVAL, "tune variant out of range");
+    if (t->screen_shape == ctx->tune_screen && t->consistency_shape == ctx->tune_cons) return LSR_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    int rc;
+    if ((rc = drop_plans(ctx))) return rc;
+    ctx->tune_screen = t->screen_shape;
+    ctx->tune_cons = t->consistency_shape;
+    return LSR_OK;
+}
+
+int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                 const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, int32_t reps, lsr_tune *out,
+                 void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (reps < 1 || reps > 1000) return fail(ctx, LSR_EINVAL, "reps %d out of range", reps);
+    if (screen_shapes() > LSR_MAX_VARIANTS || consistency_shapes() > LSR_MAX_VARIANTS)
+        return fail(ctx, LSR_EINVAL, "too many variants");
+    int rc;
+    std::vector<FragIn> fr;
+    if ((rc = batch_frags(ctx, P_all, Q_all, offP, offQ, n_pairs, prm, fr))) return rc;
+    if (n_pairs == 0) return fail(ctx, LSR_EINVAL, "autotuning needs at least one pair");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return fail(ctx, LSR_EINVAL, "autotuning cannot run under stream capture");
+    lsr_params tp = *prm;
+    tp.precision = LSR_BF16_SCREEN;                 // the screen is one of the tuned kernels
+    const bool timing = g_timing.on;
+    g_timing.on = false;
+    lsr_tune res;
+    std::memset(&res, 0, sizeof res);
+    res.n_screen_shapes = screen_shapes();
+    res.n_consistency_shapes = consistency_shapes();
+    lsr_result *d_out = nullptr;
+    Plan *pl = nullptr;
+    std::vector<char> key;
+    put(key, (int)K_PAIRS + 200);
+    put(key, tp);
+    for (auto &f : fr) { put(key, f.n); for (int a = 0; a < 6; ++a) put(key, f.src[a]); }
+    pl = find_plan(ctx, key);
+    if (!pl) rc = make_batch_plan(ctx, fr, true, &tp, key, s, &pl);
+    if (!rc && hipMalloc((void **)&d_out, sizeof(lsr_result) * (size_t)n_pairs) != hipSuccess)
+        rc = fail(ctx, LSR_ENOMEM, "autotune output");
+    if (!rc) rc = run_pairs(ctx, pl, tp, d_out, s);   // every buffer the tuned stages read
+    for (int v = 0; v < res.n_screen_shapes && !rc; ++v)
+        rc = time_ms(ctx, s, reps, [&]() -> int {
+            HIPCHK(ctx, launch_match_bf16(pl->g, pl->d, pl->m, pl->ps, pl->mscratch, v, s));
+            return LSR_OK;
+        }, &res.screen_ms[v]);
+    for (int v = 0; v < res.n_consistency_shapes && !rc; ++v)
+        rc = time_ms(ctx, s, reps, [&]() -> int {
+            HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, pl->max_nP, tp.tau, tp.seed, v, s));
+            return LSR_OK;
+        }, &res.consistency_ms[v]);
+    g_timing.on = timing;
+    if (d_out) { (void)hipStreamSynchronize(s); (void)hipFree(d_out); }
+    if (rc) return rc;
+    for (int v = 1; v < res.n_screen_shapes; ++v)
+        if (res.screen_ms[v] < res.screen_ms[res.screen_shape]) res.screen_shape = v;
+    for (int v = 1; v < res.n_consistency_shapes; ++v)
+        if (res.consistency_ms[v] < res.consistency_ms[res.consistency_shape]) res.consistency_shape = v;
+    if ((rc = lsr_set_tune(ctx, &res))) return rc;
+    if (out) *out = res;
     return LSR_OK;
 }
 
@@ -633,7 +762,7 @@ int lsr_stage_match(lsr_ctx *ctx, const float *d_F, const int32_t *d_vF, int64_t
     HIPCHK(ctx, copy<int32_t>(pl->d.valid, d_vF, nP, s));
     HIPCHK(ctx, copy<int32_t>(pl->d.valid + nP, d_vG, nQ, s));
     if (precision == LSR_BF16_SCREEN) {
-        HIPCHK(ctx, launch_match_bf16(pl->g, pl->d, pl->m, pl->ps, pl->mscratch, s));
+        HIPCHK(ctx, launch_match_bf16(pl->g, pl->d, pl->m, pl->ps, pl->mscratch, ctx->tune_screen, s));
     } else {
         HIPCHK(ctx, launch_match_fp32(pl->g, pl->d, pl->m, s));
     }
@@ -673,7 +802,7 @@ int lsr_stage_consistency(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, 
     HIPCHK(ctx, copy<int32_t>(pl->m.nn, d_nnQ, P->n, s));
     HIPCHK(ctx, copy<uint8_t>(pl->m.mutual, d_mutual, P->n, s));
     HIPCHK(ctx, launch_mutual_bits(pl->g, pl->m, s));
-    HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, pl->max_nP, tau, seed, s));
+    HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, pl->max_nP, tau, seed, ctx->tune_cons, s));
     if (P->n > 0) {
         hipLaunchKernelGGL(k_flag_out, dim3(nblk(P->n, 256)), dim3(256), 0, s, (const int32_t *)pl->m.flag, P->n, d_flag);
         HIPCHK(ctx, hipGetLastError());

@@ -82,8 +82,9 @@ __device__ __forceinline__ uint32_t splitmix64_hi(uint64_t z) {
     return (uint32_t)((z ^ (z >> 31)) >> 32);
 }
 
-constexpr int CT = 256;      // threads per block
-constexpr int CPT = 32;      // trials per thread (on average)
+constexpr int TPB = 8192;    // trials per block (the trial table's granularity)
+constexpr int CONS_THREADS[] = {256, 128, 512};   // block widths the autotuner picks from
+constexpr int N_CONS_SHAPES = sizeof(CONS_THREADS) / sizeof(CONS_THREADS[0]);
 constexpr int QCAP = 128;    // per-wavefront ring of drawn quadruples awaiting the edge test
 constexpr int MB_LDS = 8192; // largest bitmap staged in LDS (words): fragments up to 524,288 points
 
@@ -136,13 +137,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Each wavefront owns a contiguous range of 64 * CPT trials of one pair and
+// Each wavefront owns a contiguous range of TPB / waves trials of one pair and
 // hands them to its lanes on demand: a lane draws one index per iteration,
 // takes the next unclaimed trial when its current one completes or fails, and
 // parks a complete quadruple in a wavefront ring; 64 parked quadruples are
 // tested together.  Which lane runs which trial changes neither the draws
 // (they depend only on the trial index) nor the result (flags are set, counts
 // summed).
+template <int CT>
 __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const uint64_t *mbits,
                                                     const float4 *cpack, int32_t *flag, double t2, uint64_t seed,
                                                     int use_lds, PairState *ps) {
@@ -161,8 +163,9 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
     int32_t *fl = flag + P.off;
     const int lane = threadIdx.x & 63;
     int4 *q = ring[threadIdx.x >> 6];
-    const int64_t wbeg = b.first + (int64_t)(threadIdx.x >> 6) * (64 * CPT);
-    const int64_t wend = nP ? min(b.count, wbeg + 64 * CPT) : wbeg;
+    constexpr int PER_WAVE = TPB / (CT / 64);
+    const int64_t wbeg = b.first + (int64_t)(threadIdx.x >> 6) * PER_WAVE;
+    const int64_t wend = nP ? min(b.count, wbeg + PER_WAVE) : wbeg;
     int64_t next = wbeg;                       // next unclaimed trial (uniform)
     uint32_t qhead = 0, qtail = 0;             // ring cursors (uniform)
     bool live = false;
@@ -225,7 +228,7 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
 }
 
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb, int max_nP,
-                              float tau, uint64_t seed, hipStream_t s) {
+                              float tau, uint64_t seed, int shape, hipStream_t s) {
     hipError_t e = fill<int32_t>(m.flag, 0, g.ntot, s);
     if (e != hipSuccess || ntb == 0 || g.ntot == 0) return e;
     hipLaunchKernelGGL(k_corr_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
@@ -234,12 +237,23 @@ hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, co
     int words = (max_nP + 63) / 64;
     int use_lds = words <= MB_LDS ? 1 : 0;
     size_t shm = use_lds ? sizeof(uint64_t) * (size_t)std::max(words, 1) : 0;
-    hipLaunchKernelGGL(k_consistency, dim3(ntb), dim3(CT), shm, s, (const Frag *)g.frag, tb,
-                       (const uint64_t *)m.mbits, (const float4 *)m.cpack, m.flag, t2, seed, use_lds, ps);
+    const Frag *fr = (const Frag *)g.frag;
+    const uint64_t *mb = (const uint64_t *)m.mbits;
+    const float4 *cp = (const float4 *)m.cpack;
+    switch (shape) {
+    case 0: hipLaunchKernelGGL(k_consistency<CONS_THREADS[0]>, dim3(ntb), dim3(CONS_THREADS[0]), shm, s, fr, tb, mb, cp,
+                               m.flag, t2, seed, use_lds, ps); break;
+    case 1: hipLaunchKernelGGL(k_consistency<CONS_THREADS[1]>, dim3(ntb), dim3(CONS_THREADS[1]), shm, s, fr, tb, mb, cp,
+                               m.flag, t2, seed, use_lds, ps); break;
+    case 2: hipLaunchKernelGGL(k_consistency<CONS_THREADS[2]>, dim3(ntb), dim3(CONS_THREADS[2]), shm, s, fr, tb, mb, cp,
+                               m.flag, t2, seed, use_lds, ps); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-int trials_per_block() { return CT * CPT; }
+int trials_per_block() { return TPB; }
+int consistency_shapes() { return N_CONS_SHAPES; }
 
 // Flagged correspondences, in ascending P index, gathered into compact xyz
 // arrays; per pair the list starts at kpos[P.off].

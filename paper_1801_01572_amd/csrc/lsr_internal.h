@@ -147,7 +147,7 @@ hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStre
 hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s);
 inline int64_t mbits_words(int64_t ntot, int nfrag) { return ntot / 64 + nfrag + 1; }
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
-                              int max_nP, float tau, uint64_t seed, hipStream_t s);
+                              int max_nP, float tau, uint64_t seed, int shape, hipStream_t s);
 hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);
 hipError_t launch_gnc(const GridBufs &g, const MatchBufs &m, PairState *ps, int npairs, const lsr_params &prm,
                       hipStream_t s);

@@ -44,10 +44,13 @@ namespace lsr {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int SW = 4;              // waves per block
-constexpr int SQB = 4;             // 16-query blocks per wave (64 queries per wave, 256 per block)
-constexpr int CH = 8;              // 16-row tiles per LDS chunk
-constexpr int CROWS = CH * 16;     // rows per chunk (128); fragments are padded to this
+// Screen shapes: SW waves per block x SQB 16-query blocks per wave = 256
+// queries per block (one block per 256 rows of a fragment, any variant);
+// CH 16-row tiles per LDS chunk.  The variant is chosen by the autotuner.
+struct ScreenShape { int sw, sqb, ch; };
+constexpr ScreenShape SCREEN_SHAPES[] = {{4, 4, 8}, {4, 4, 4}, {8, 2, 8}, {8, 2, 4}};
+constexpr int N_SCREEN_SHAPES = sizeof(SCREEN_SHAPES) / sizeof(SCREEN_SHAPES[0]);
+constexpr int PAD_ROWS = 128;      // fragments' packed rows are padded to a multiple of this
 constexpr int LCAP = 32;           // candidates collected per uncertified row
 
 __device__ __forceinline__ uint16_t f2bf(float f) {     // round to nearest even
@@ -162,7 +165,7 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
     int i = b.start + threadIdx.x;
-    int npad = (Fr.n + CROWS - 1) / CROWS * CROWS;
+    int npad = (Fr.n + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS;
     if (i >= npad) return;
     int64_t row = Fr.pk_off + i;
     uint16_t hi[32], lo[32];
@@ -229,12 +232,14 @@ __device__ __forceinline__ int lds_slot(int idx) {            // uint4 index of 
 // COLLECT = true: the queries are the fragment's uncertified rows (slots
 // [start, start + 256) of its list); append every candidate whose score
 // reaches the row's threshold to the row's candidate list.
-template <bool COLLECT>
+template <bool COLLECT, int SW, int SQB, int CH>
 __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, const uint16_t *pk,
                                                     int32_t *c1_out, float *v2_out, const int32_t *fb_row,
                                                     const int32_t *fb_cnt, const float *thr, int32_t *lst,
                                                     int32_t *lst_cnt) {
-    __shared__ __align__(16) uint16_t lds[2][CROWS * PK];     // 2 x 16 KB
+    static_assert(SW * SQB * 16 == 256 && PAD_ROWS % (CH * 16) == 0, "screen shape");
+    constexpr int CROWS = CH * 16;                               // rows per LDS chunk
+    __shared__ __align__(16) uint16_t lds[2][CROWS * PK];
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
@@ -515,7 +520,38 @@ __global__ void __launch_bounds__(256) k_fallback(const Frag *frag, const float 
     }
 }
 
-hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch,
+template <bool COLLECT, int SW, int SQB, int CH>
+static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScratch &S, hipStream_t s) {
+    if (COLLECT)
+        hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
+                           (const Blk *)g.blk256, pk, nullptr, nullptr, (const int32_t *)S.fb_row,
+                           (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst, S.lst_cnt);
+    else
+        hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
+                           (const Blk *)g.blk256, pk, S.c1, S.v2, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+template <bool COLLECT>
+static hipError_t launch_screen_c(int shape, const GridBufs &g, const uint16_t *pk, const ScreenScratch &S,
+                                  hipStream_t s) {
+    switch (shape) {
+    case 0: screen_launch<COLLECT, SCREEN_SHAPES[0].sw, SCREEN_SHAPES[0].sqb, SCREEN_SHAPES[0].ch>(g, pk, S, s); break;
+    case 1: screen_launch<COLLECT, SCREEN_SHAPES[1].sw, SCREEN_SHAPES[1].sqb, SCREEN_SHAPES[1].ch>(g, pk, S, s); break;
+    case 2: screen_launch<COLLECT, SCREEN_SHAPES[2].sw, SCREEN_SHAPES[2].sqb, SCREEN_SHAPES[2].ch>(g, pk, S, s); break;
+    case 3: screen_launch<COLLECT, SCREEN_SHAPES[3].sw, SCREEN_SHAPES[3].sqb, SCREEN_SHAPES[3].ch>(g, pk, S, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_screen(bool collect, int shape, const GridBufs &g, const uint16_t *pk,
+                                const ScreenScratch &S, hipStream_t s) {
+    return collect ? launch_screen_c<true>(shape, g, pk, S, s) : launch_screen_c<false>(shape, g, pk, S, s);
+}
+
+int screen_shapes() { return N_SCREEN_SHAPES; }
+
+hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch, int shape,
                              hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
     ScreenScratch S = carve(scratch, g, nullptr);
@@ -529,18 +565,14 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, d.pk, S.yq);
     tmark("pack", s);
-    hipLaunchKernelGGL(k_screen<false>, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
-                       (const Blk *)g.blk256, (const uint16_t *)d.pk, S.c1, S.v2, nullptr, nullptr, nullptr, nullptr,
-                       nullptr);
+    if ((e = launch_screen(false, shape, g, d.pk, S, s)) != hipSuccess) return e;
     tmark("screen", s);
     hipLaunchKernelGGL(k_rerank, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
                        (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                        S.full_cnt, ps);
     tmark("rerank", s);
-    hipLaunchKernelGGL(k_screen<true>, dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
-                       (const Blk *)g.blk256, (const uint16_t *)d.pk, nullptr, nullptr, (const int32_t *)S.fb_row,
-                       (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst, S.lst_cnt);
+    if ((e = launch_screen(true, shape, g, d.pk, S, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rerank_list, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const float *)d.F, (const int32_t *)d.valid, (const int32_t *)S.fb_row,
                        (const int32_t *)S.fb_cnt, (const float *)S.thr, (const int32_t *)S.lst,

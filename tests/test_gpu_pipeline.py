@@ -175,3 +175,40 @@ def test_autograd_function_fd(L):
         Em = L.align_loss(P.detach(), Q.detach(), dev(C), [0, n], Ts[1], mu).item()
         fd = (Ep - Em) / (2 * h)
         assert abs(fd - xi.grad[0, k].item()) <= 1e-4 * (1 + abs(fd))
+
+
+def test_autotune_variants_agree(L):
+    """Every launch-shape variant computes the same bits; the autotuner picks one and times all."""
+    import paper_1801_01572_amd._lib as lib
+    prs = [pair(2, 10 + k, (int(n1), int(n2))) for k, (n1, n2) in enumerate([(4000, 6000), (9000, 700), (2500, 2500)])]
+    P, Q, offP, offQ = _batch(prs)
+    Pd, Qd = dev(P), dev(Q)
+    prm = L.default_params(precision=L.BF16_SCREEN)
+    info = L.get_tune()
+    ref = None
+    try:
+        for sv in range(info["n_screen_shapes"]):
+            for cv in range(info["n_consistency_shapes"]):
+                print(f"tune screen={sv} consistency={cv}", flush=True)
+                L.set_tune(sv, cv)
+                res = L.register_batch(Pd, Qd, offP, offQ, prm)
+                if ref is None:
+                    ref = res
+                for b in range(len(prs)):
+                    for k in ref[b]:
+                        assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), (sv, cv, b, k)
+        t = L.autotune(Pd, Qd, offP, offQ, prm, reps=1)
+        assert 0 <= t["screen_shape"] < info["n_screen_shapes"]
+        assert 0 <= t["consistency_shape"] < info["n_consistency_shapes"]
+        assert all(ms > 0 for ms in t["screen_ms"] + t["consistency_ms"])
+        assert t["screen_ms"][t["screen_shape"]] == min(t["screen_ms"])
+        g = L.get_tune()
+        assert (g["screen_shape"], g["consistency_shape"]) == (t["screen_shape"], t["consistency_shape"])
+        res = L.register_batch(Pd, Qd, offP, offQ, prm)
+        for b in range(len(prs)):
+            for k in ref[b]:
+                assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), ("tuned", b, k)
+        with pytest.raises(lib.LsrError):
+            L.set_tune(info["n_screen_shapes"], 0)
+    finally:
+        L.set_tune(0, 0)
