@@ -246,12 +246,13 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     size_t n1 = (size_t)std::max<int64_t>(ntot, 1), c1 = (size_t)std::max<int64_t>(ncells, 1);
     size_t o_cellpt = D.add(4 * n1), o_cstart = D.add(4 * (c1 + 1)), o_ccount = D.add(4 * c1),
            o_cursor = D.add(4 * (c1 + scan_tmp_elems(ncells))), o_tmp = D.add(4 * n1);
+    size_t o_sp = D.add(16 * n1);
     size_t o_s[6];
-    for (int a = 0; a < 6; ++a) o_s[a] = D.add(4 * n1);
+    for (int a = 3; a < 6; ++a) o_s[a] = D.add(4 * n1);
     size_t o_sorig = D.add(4 * n1);
     size_t o_n[3];
     for (int a = 0; a < 3; ++a) o_n[a] = D.add(8 * n1);
-    size_t o_spfh = D.add(4 * FD * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
+    size_t o_spfh = D.add(4 * FDP * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
     size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
     size_t o_bits = D.add(8 * (size_t)mbits_words(ntot, nf));
     size_t o_cpack = D.add(32 * n1);
@@ -286,7 +287,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->g.ccount = (int32_t *)(db + o_ccount);
     P->g.cursor = (int32_t *)(db + o_cursor);
     P->g.tmp = (int32_t *)(db + o_tmp);
-    P->g.sx = (float *)(db + o_s[0]); P->g.sy = (float *)(db + o_s[1]); P->g.sz = (float *)(db + o_s[2]);
+    P->g.sp = (float4 *)(db + o_sp);
     P->g.snx = (float *)(db + o_s[3]); P->g.sny = (float *)(db + o_s[4]); P->g.snz = (float *)(db + o_s[5]);
     P->g.sorig = (int32_t *)(db + o_sorig);
     P->d.nx = (double *)(db + o_n[0]); P->d.ny = (double *)(db + o_n[1]); P->d.nz = (double *)(db + o_n[2]);

@@ -22,7 +22,7 @@ namespace lsr {
 
 struct GridView {
     const int32_t *cstart, *ccount;
-    const float *sx, *sy, *sz;
+    const float4 *p;           // sorted (x, y, z, 0)
 };
 
 // Visit every sorted point within the 27-cell stencil of (px, py, pz): the
@@ -102,11 +102,13 @@ __global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *bl
     int i = b.start + threadIdx.x;
     if (i >= F.n) return;
     int64_t s = F.off + i;
-    double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+    const float4 p4 = g.p[s];
+    double px = p4.x, py = p4.y, pz = p4.z;
     // shifted sums (origin at p_i): sum d, sum d d^T
     double m = 1, s1x = 0, s1y = 0, s1z = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
     for_stencil(F, g, px, py, pz, [&](int32_t k) {
-        double qx = g.sx[k], qy = g.sy[k], qz = g.sz[k];
+        const float4 q4 = g.p[k];
+        double qx = q4.x, qy = q4.y, qz = q4.z;
         double d2 = pdist2(px, py, pz, qx, qy, qz);
         if (d2 > 0.0 && d2 <= r2) {
             double dx = qx - px, dy = qy - py, dz = qz - pz;
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *bl
 
 hipError_t launch_normals(const GridBufs &g, float r_normal, DescBufs &d, double *nrm_orig, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
-    GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
+    GridView gv{g.cstart, g.ccount, g.sp};
     double r2 = (double)r_normal * (double)r_normal;
     hipLaunchKernelGGL(k_normals, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
                        (const float *)g.snx, (const float *)g.sny, (const float *)g.snz, (const int32_t *)g.sorig,
@@ -214,11 +216,13 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
     const int i = b.start + threadIdx.x;
     if (i >= F.n) return;                       // no block-wide barrier follows
     const int64_t s = F.off + i;
-    const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+    const float4 p4 = g.p[s];
+    const double px = p4.x, py = p4.y, pz = p4.z;
     const double ax = nxa[s], ay = nya[s], az = nza[s];
     int k = 0, kp = 0;
     for_stencil(F, g, px, py, pz, [&](int32_t j) {
-        double dx = (double)g.sx[j] - px, dy = (double)g.sy[j] - py, dz = (double)g.sz[j] - pz;
+        const float4 q4 = g.p[j];
+        double dx = (double)q4.x - px, dy = (double)q4.y - py, dz = (double)q4.z - pz;
         double d2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
         if (!(d2 > 0.0 && d2 <= r2)) return;
         ++k;
@@ -253,15 +257,20 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
         h[2 * NB + bt] += 1;
     });
     float sc = kp > 0 ? 1.0f / (float)kp : 0.0f;
-    float *o = spfh + s * FD;
+    float4 *o = (float4 *)(spfh + s * FDP);
 #pragma unroll
-    for (int c = 0; c < FD; ++c) o[c] = kp > 0 ? (float)h[c] * sc : 0.0f;
+    for (int q = 0; q < FDP / 4; ++q) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < FD && kp > 0) ? (float)h[4 * q + e] * sc : 0.0f;
+        o[q] = make_float4(v[0], v[1], v[2], v[3]);
+    }
     knb[s] = k;
 }
 
 hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
-    GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
+    GridView gv{g.cstart, g.ccount, g.sp};
     double r2 = (double)r_feature * (double)r_feature;
     ThetaEdges te;
     const double PI = 3.14159265358979323846;
@@ -282,7 +291,7 @@ __global__ void __launch_bounds__(256) k_spfh_out(const Frag *frag, const Blk *b
     int i = b.start + threadIdx.x;
     if (i >= F.n) return;
     int64_t s = F.off + i, o = F.off + sorig[s];
-    for (int c = 0; c < FD; ++c) out[o * FD + c] = spfh[s * FD + c];
+    for (int c = 0; c < FD; ++c) out[o * FD + c] = spfh[s * FDP + c];
     kout[o] = knb[s];
 }
 
@@ -304,21 +313,29 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
     bool ok = false;
     if (i < F.n) {
         int64_t s = F.off + i;
-        const double px = g.sx[s], py = g.sy[s], pz = g.sz[s];
+        const float4 p4 = g.p[s];
+    const double px = p4.x, py = p4.y, pz = p4.z;
         float acc[FD];
 #pragma unroll
         for (int c = 0; c < FD; ++c) acc[c] = 0.f;
         for_stencil(F, g, px, py, pz, [&](int32_t j) {
-            double d2 = pdist2(px, py, pz, (double)g.sx[j], (double)g.sy[j], (double)g.sz[j]);
+            const float4 q4 = g.p[j];
+            double d2 = pdist2(px, py, pz, (double)q4.x, (double)q4.y, (double)q4.z);
             if (!(d2 > 0.0 && d2 <= r2)) return;
             float w = (float)rsqrt_nr(d2);
-            const float *sj = spfh + (int64_t)j * FD;
+            const float4 *sj = (const float4 *)(spfh + (int64_t)j * FDP);
 #pragma unroll
-            for (int c = 0; c < FD; ++c) acc[c] = fmaf(sj[c], w, acc[c]);
+            for (int q = 0; q < FDP / 4; ++q) {
+                const float4 v = sj[q];
+                acc[4 * q] = fmaf(v.x, w, acc[4 * q]);
+                if (4 * q + 1 < FD) acc[4 * q + 1] = fmaf(v.y, w, acc[4 * q + 1]);
+                if (4 * q + 2 < FD) acc[4 * q + 2] = fmaf(v.z, w, acc[4 * q + 2]);
+                if (4 * q + 3 < FD) acc[4 * q + 3] = fmaf(v.w, w, acc[4 * q + 3]);
+            }
         });
         int k = knb[s];
         float ik = k > 0 ? 1.0f / (float)k : 0.0f;
-        const float *si = spfh + s * FD;
+        const float *si = spfh + s * FDP;
         float f[FD];
 #pragma unroll
         for (int c = 0; c < FD; ++c) f[c] = si[c] + acc[c] * ik;
@@ -356,7 +373,7 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
 
 hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairState *ps, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
-    GridView gv{g.cstart, g.ccount, g.sx, g.sy, g.sz};
+    GridView gv{g.cstart, g.ccount, g.sp};
     double r2 = (double)r_feature * (double)r_feature;
     hipLaunchKernelGGL(k_fpfh, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
                        (const int32_t *)g.sorig, (const float *)d.spfh, (const int32_t *)d.knb, r2, d.F, d.valid, ps);

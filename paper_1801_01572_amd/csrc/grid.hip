@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) k_scatter(const Frag *frag, const Blk *bl
 
 __global__ void __launch_bounds__(256) k_rankfix(const Frag *frag, const Blk *blk, const int32_t *cell_of_pt,
                                                  const int32_t *cstart, const int32_t *ccount, const int32_t *tmp,
-                                                 float *sx, float *sy, float *sz, float *snx, float *sny, float *snz,
+                                                 float4 *sp, float *snx, float *sny, float *snz,
                                                  int32_t *sorig) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_rankfix(const Frag *frag, const Blk *bl
     int32_t st = cstart[gc], cnt = ccount[gc], rank = 0;
     for (int32_t k = 0; k < cnt; ++k) rank += tmp[st + k] < g;
     int32_t d = st + rank;
-    sx[d] = F.src[0][i]; sy[d] = F.src[1][i]; sz[d] = F.src[2][i];
+    sp[d] = make_float4(F.src[0][i], F.src[1][i], F.src[2][i], 0.f);
     const bool has_n = F.src[3] && F.src[4] && F.src[5];       // stage calls may omit normals
     snx[d] = has_n ? F.src[3][i] : 0.f;
     sny[d] = has_n ? F.src[4][i] : 0.f;
@@ -220,7 +220,7 @@ hipError_t build_grids(GridBufs &g, float r_cell, hipStream_t s) {
                        (const int32_t *)g.cell_of_pt, g.cursor, g.tmp);
     hipLaunchKernelGGL(k_rankfix, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const int32_t *)g.cell_of_pt, (const int32_t *)g.cstart, (const int32_t *)g.ccount,
-                       (const int32_t *)g.tmp, g.sx, g.sy, g.sz, g.snx, g.sny, g.snz, g.sorig);
+                       (const int32_t *)g.tmp, g.sp, g.snx, g.sny, g.snz, g.sorig);
     return hipGetLastError();
 }
 

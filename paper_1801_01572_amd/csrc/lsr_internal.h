@@ -17,6 +17,7 @@ namespace lsr {
 
 constexpr int FD = 33;          // descriptor length: 3 features x 11 bins
 constexpr int NB = 11;          // bins per feature
+constexpr int FDP = 36;         // SPFH row stride in floats (33 values + 3 zeros, 16-byte aligned)
 constexpr int PK = 64;          // packed screen row: hi and lo bf16 halves, 32 each (30 dims + 2 slots)
 
 struct Frag {
@@ -98,7 +99,7 @@ struct GridBufs {              // built per batch by build_grids()
     int32_t *ccount;           // ncells
     int32_t *cursor;           // ncells, scatter cursor
     int32_t *tmp;              // ntot, unstable scatter
-    float *sx, *sy, *sz;       // sorted coordinates
+    float4 *sp;                // sorted coordinates (x, y, z, 0): one 16-byte load per candidate
     float *snx, *sny, *snz;    // sorted input normals
     int32_t *sorig;            // sorted position -> original index within the fragment
     Blk *blk256; int nblk256;  // block tables: 256 points per block
@@ -109,7 +110,7 @@ struct GridBufs {              // built per batch by build_grids()
 
 struct DescBufs {
     double *nx, *ny, *nz;      // estimated normals, sorted order
-    float *spfh;               // sorted order, ntot x 33
+    float *spfh;               // sorted order, ntot x FDP (33 values, zero padded to 16-byte rows)
     int32_t *knb;              // neighbour count within r_feature, sorted order
     float *F;                  // descriptors, original order (fragment-relative via Frag::off), ntot x 33
     int32_t *valid;            // original order

@@ -12,8 +12,7 @@ namespace lsr {
 constexpr double FIX_SCALE = 1099511627776.0;   // 2^40: inlier d^2 / delta^2 in fixed point
 
 __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk, const int32_t *cstart,
-                                                const int32_t *ccount, const float *sx, const float *sy,
-                                                const float *sz, const double *nxa, const double *nya,
+                                                const int32_t *ccount, const float4 *sp, const double *nxa, const double *nya,
                                                 const double *nza, PairState *ps, double delta2, int normal_check,
                                                 double ncos) {
     const Blk b = blk[blockIdx.x];
@@ -27,7 +26,8 @@ __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk
     if (i < P.n) {
         int64_t s = P.off + i;                      // sorted position in P
         const double *T = S.T;
-        double px = sx[s], py = sy[s], pz = sz[s];
+        const float4 ps4 = sp[s];
+        double px = ps4.x, py = ps4.y, pz = ps4.z;
         double x = T[0] * px + T[1] * py + T[2] * pz + T[3];
         double y = T[4] * px + T[5] * py + T[6] * pz + T[7];
         double z = T[8] * px + T[9] * py + T[10] * pz + T[11];
@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk
                     int32_t kb = cstart[row + x0], ke = cstart[row + x1] + ccount[row + x1];
                     for (int32_t k = kb; k < ke; ++k) {
                         if (normal_check && rnx * nxa[k] + rny * nya[k] + rnz * nza[k] < ncos) continue;
-                        double d2 = pdist2(x, y, z, (double)sx[k], (double)sy[k], (double)sz[k]);
+                        const float4 q = sp[k];
+                        double d2 = pdist2(x, y, z, (double)q.x, (double)q.y, (double)q.z);
                         best = fmin(best, d2);
                     }
                 }
@@ -69,8 +70,7 @@ hipError_t launch_verify(const GridBufs &g, const DescBufs &d, PairState *ps, fl
     if (g.ntot == 0) return hipSuccess;
     double d2 = (double)delta * (double)delta;
     hipLaunchKernelGGL(k_verify, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)g.cstart, (const int32_t *)g.ccount, (const float *)g.sx, (const float *)g.sy,
-                       (const float *)g.sz, (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, ps, d2,
+                       (const int32_t *)g.cstart, (const int32_t *)g.ccount, (const float4 *)g.sp, (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, ps, d2,
                        normal_check, (double)normal_cos);
     return hipGetLastError();
 }

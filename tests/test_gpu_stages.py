@@ -237,3 +237,38 @@ def test_voxel_edge_cases(L, orc):
         L.voxel_downsample(dev(far), 0.01)
     with pytest.raises(L.LsrError):
         L.voxel_downsample(dev(c), 0.0)
+
+
+def _dense_mixed(seed):
+    """A dense 6 cm cluster (500-1500 r_f neighbours per point) beside a 1 cm plane
+    (~76): neighbourhood sizes far from the room recipe's."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0, 0.06, size=(3, 1500))
+    g = np.stack(np.meshgrid(np.arange(60) * 0.01, np.arange(60) * 0.01), 0).reshape(2, -1)
+    b = np.vstack([g + 0.5, np.full((1, g.shape[1]), 0.03)]) + rng.normal(0, 0.002, size=(3, g.shape[1]))
+    xyz = np.concatenate([a, b], 1)
+    n = rng.normal(size=(3, xyz.shape[1]))
+    n /= np.linalg.norm(n, axis=0)
+    return np.vstack([xyz, n]).astype(np.float32)
+
+
+def test_spfh_fpfh_dense_cluster(L, orc):
+    cloud = _dense_mixed(3)
+    print(f"dense+plane n={cloud.shape[1]}", flush=True)
+    nrm, gap, ori, _ = orc.normals(cloud, 0.025)
+    S, k, kp, mg = orc.spfh(cloud[:3], nrm, 0.05)
+    Sg, kg = L.stage_spfh(dev(cloud[:3]), dev(nrm), 0.05)
+    Sg, kg = Sg.cpu().numpy(), kg.cpu().numpy()
+    assert np.array_equal(kg, k)
+    assert k[:1500].min() > 400 and np.median(k[1500:]) < 100
+    keep = mg >= MARGIN
+    assert keep.mean() > 0.99
+    assert np.abs(Sg[keep] - S[keep]).max() <= 1e-6
+    F, v, exempt = desc_exempt(orc, cloud, nrm, gap, ori, 0.05)
+    Fg, vg = L.stage_fpfh(dev(cloud[:3]), dev(nrm), 0.05)
+    Fg, vg = Fg.cpu().numpy().astype(np.float64), vg.cpu().numpy()
+    assert np.array_equal(vg, v)
+    ok = (v == 1) & ~exempt
+    assert ok.mean() > 0.95
+    rel = np.linalg.norm(Fg[ok] - F[ok], axis=1) / np.linalg.norm(F[ok], axis=1)
+    assert rel.max() <= DESC_RTOL
