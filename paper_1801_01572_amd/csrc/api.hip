@@ -252,7 +252,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     size_t o_sorig = D.add(4 * n1);
     size_t o_n[3];
     for (int a = 0; a < 3; ++a) o_n[a] = D.add(8 * n1);
-    size_t o_spfh = D.add(4 * FDP * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
+    size_t o_spfh = D.add(16 * SPR * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
     size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
     size_t o_bits = D.add(8 * (size_t)mbits_words(ntot, nf));
     size_t o_cpack = D.add(32 * n1);
@@ -291,7 +291,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->g.snx = (float *)(db + o_s[3]); P->g.sny = (float *)(db + o_s[4]); P->g.snz = (float *)(db + o_s[5]);
     P->g.sorig = (int32_t *)(db + o_sorig);
     P->d.nx = (double *)(db + o_n[0]); P->d.ny = (double *)(db + o_n[1]); P->d.nz = (double *)(db + o_n[2]);
-    P->d.spfh = (float *)(db + o_spfh);
+    P->d.spfh = (uint4 *)(db + o_spfh);
     P->d.knb = (int32_t *)(db + o_knb);
     P->d.F = (float *)(db + o_F);
     P->d.valid = (int32_t *)(db + o_valid);

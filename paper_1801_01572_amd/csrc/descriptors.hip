@@ -206,7 +206,7 @@ constexpr int SPFH_T = 256;
 // theta = atan2(w.n_t, u.n_t) with w.n_t = ((u.d_s)(u.n_t) - (d_s.n_t)(u.u)) / sqrt(l2).
 __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, GridView g, const double *nxa,
                                                  const double *nya, const double *nza, double r2, ThetaEdges te,
-                                                 float *spfh, int32_t *knb) {
+                                                 uint4 *spfh, int32_t *knb) {
     __shared__ uint32_t hist[SPFH_T * FD];
     uint32_t *h = hist + threadIdx.x * FD;
 #pragma unroll
@@ -256,15 +256,23 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
         h[NB + bin11(NB * (phi + 1.0) / 2.0)] += 1;
         h[2 * NB + bt] += 1;
     });
+    // SPFH_i = counts / kp, stored as the exact counts (u16) and 1/kp.  Beyond
+    // 65535 pairs the counts are rescaled to 16 bits (relative error <= 2^-16).
     float sc = kp > 0 ? 1.0f / (float)kp : 0.0f;
-    float4 *o = (float4 *)(spfh + s * FDP);
+    uint32_t w[4 * SPR];
 #pragma unroll
-    for (int q = 0; q < FDP / 4; ++q) {
-        float v[4];
+    for (int m = 0; m < 4 * SPR; ++m) w[m] = 0u;
+    if (kp > 65535) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < FD && kp > 0) ? (float)h[4 * q + e] * sc : 0.0f;
-        o[q] = make_float4(v[0], v[1], v[2], v[3]);
+        for (int c = 0; c < FD; ++c) h[c] = (uint32_t)((double)h[c] * (65535.0 / (double)kp) + 0.5);
+        sc = 1.0f / 65535.0f;
     }
+#pragma unroll
+    for (int c = 0; c < FD; ++c) w[c >> 1] |= (h[c] & 0xffffu) << (16 * (c & 1));
+    w[4 * SPR - 1] = __float_as_uint(sc);
+    uint4 *o = spfh + s * SPR;
+#pragma unroll
+    for (int q = 0; q < SPR; ++q) o[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
     knb[s] = k;
 }
 
@@ -285,27 +293,29 @@ hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStrea
 
 // SPFH and neighbour count in original order (stage output).
 __global__ void __launch_bounds__(256) k_spfh_out(const Frag *frag, const Blk *blk, const int32_t *sorig,
-                                                  const float *spfh, const int32_t *knb, float *out, int32_t *kout) {
+                                                  const uint4 *spfh, const int32_t *knb, float *out, int32_t *kout) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     int i = b.start + threadIdx.x;
     if (i >= F.n) return;
     int64_t s = F.off + i, o = F.off + sorig[s];
-    for (int c = 0; c < FD; ++c) out[o * FD + c] = spfh[s * FDP + c];
+    const uint32_t *w = (const uint32_t *)(spfh + s * SPR);
+    const float sc = __uint_as_float(w[4 * SPR - 1]);
+    for (int c = 0; c < FD; ++c) out[o * FD + c] = (float)((w[c >> 1] >> (16 * (c & 1))) & 0xffffu) * sc;
     kout[o] = knb[s];
 }
 
 hipError_t launch_spfh_out(const GridBufs &g, const DescBufs &d, float *out, int32_t *kout, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_spfh_out, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)g.sorig, (const float *)d.spfh, (const int32_t *)d.knb, out, kout);
+                       (const int32_t *)g.sorig, (const uint4 *)d.spfh, (const int32_t *)d.knb, out, kout);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- FPFH
 
 __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, GridView g, const int32_t *sorig,
-                                              const float *spfh, const int32_t *knb, double r2, float *Fout,
+                                              const uint4 *spfh, const int32_t *knb, double r2, float *Fout,
                                               int32_t *valid, PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
@@ -322,23 +332,26 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
             const float4 q4 = g.p[j];
             double d2 = pdist2(px, py, pz, (double)q4.x, (double)q4.y, (double)q4.z);
             if (!(d2 > 0.0 && d2 <= r2)) return;
-            float w = (float)rsqrt_nr(d2);
-            const float4 *sj = (const float4 *)(spfh + (int64_t)j * FDP);
+            const uint4 *sj = spfh + (int64_t)j * SPR;
+            uint32_t wd[4 * SPR];
 #pragma unroll
-            for (int q = 0; q < FDP / 4; ++q) {
-                const float4 v = sj[q];
-                acc[4 * q] = fmaf(v.x, w, acc[4 * q]);
-                if (4 * q + 1 < FD) acc[4 * q + 1] = fmaf(v.y, w, acc[4 * q + 1]);
-                if (4 * q + 2 < FD) acc[4 * q + 2] = fmaf(v.z, w, acc[4 * q + 2]);
-                if (4 * q + 3 < FD) acc[4 * q + 3] = fmaf(v.w, w, acc[4 * q + 3]);
+            for (int q = 0; q < SPR; ++q) {
+                const uint4 v = sj[q];
+                wd[4 * q] = v.x; wd[4 * q + 1] = v.y; wd[4 * q + 2] = v.z; wd[4 * q + 3] = v.w;
             }
+            // SPFH_j / |p_j - p_i| = count * (scale_j / |p_j - p_i|)
+            const float w = (float)rsqrt_nr(d2) * __uint_as_float(wd[4 * SPR - 1]);
+#pragma unroll
+            for (int c = 0; c < FD; ++c)
+                acc[c] = fmaf((float)((wd[c >> 1] >> (16 * (c & 1))) & 0xffffu), w, acc[c]);
         });
         int k = knb[s];
         float ik = k > 0 ? 1.0f / (float)k : 0.0f;
-        const float *si = spfh + s * FDP;
+        const uint32_t *si = (const uint32_t *)(spfh + s * SPR);
+        const float sci = __uint_as_float(si[4 * SPR - 1]);
         float f[FD];
 #pragma unroll
-        for (int c = 0; c < FD; ++c) f[c] = si[c] + acc[c] * ik;
+        for (int c = 0; c < FD; ++c) f[c] = (float)((si[c >> 1] >> (16 * (c & 1))) & 0xffffu) * sci + acc[c] * ik;
         ok = k >= 1;
 #pragma unroll
         for (int blk3 = 0; blk3 < 3; ++blk3) {
@@ -376,7 +389,7 @@ hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairStat
     GridView gv{g.cstart, g.ccount, g.sp};
     double r2 = (double)r_feature * (double)r_feature;
     hipLaunchKernelGGL(k_fpfh, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
-                       (const int32_t *)g.sorig, (const float *)d.spfh, (const int32_t *)d.knb, r2, d.F, d.valid, ps);
+                       (const int32_t *)g.sorig, (const uint4 *)d.spfh, (const int32_t *)d.knb, r2, d.F, d.valid, ps);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ namespace lsr {
 
 constexpr int FD = 33;          // descriptor length: 3 features x 11 bins
 constexpr int NB = 11;          // bins per feature
-constexpr int FDP = 36;         // SPFH row stride in floats (33 values + 3 zeros, 16-byte aligned)
+constexpr int SPR = 5;          // SPFH row in 16-byte units: 33 u16 bin counts, 5 zero u16, float scale (80 B)
 constexpr int PK = 64;          // packed screen row: hi and lo bf16 halves, 32 each (30 dims + 2 slots)
 
 struct Frag {
@@ -110,7 +110,7 @@ struct GridBufs {              // built per batch by build_grids()
 
 struct DescBufs {
     double *nx, *ny, *nz;      // estimated normals, sorted order
-    float *spfh;               // sorted order, ntot x FDP (33 values, zero padded to 16-byte rows)
+    uint4 *spfh;               // sorted order, ntot x SPR: bin counts (u16) and the scale 1/kp (last word)
     int32_t *knb;              // neighbour count within r_feature, sorted order
     float *F;                  // descriptors, original order (fragment-relative via Frag::off), ntot x 33
     int32_t *valid;            // original order
