@@ -204,71 +204,155 @@ constexpr int SPFH_T = 256;
 // |d| more than once: the source test is (n_i + n_j).d >= 0; with
 // c = u x d_s and l2 = |c|^2: alpha = (c.n_t) / sqrt(l2), phi = (u.d_s)/|d|,
 // theta = atan2(w.n_t, u.n_t) with w.n_t = ((u.d_s)(u.n_t) - (d_s.n_t)(u.u)) / sqrt(l2).
+// Returns false for a degenerate frame (|u x e| <= 1e-12: the pair is skipped).
+__device__ __forceinline__ bool pair_bins(double px, double py, double pz, double ax, double ay, double az,
+                                          const float4 q4, double bx, double by, double bz, const ThetaEdges &te,
+                                          int &b0, int &b1, int &b2) {
+    double dx = (double)q4.x - px, dy = (double)q4.y - py, dz = (double)q4.z - pz;
+    double d2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+    bool src_i = (ax + bx) * dx + (ay + by) * dy + (az + bz) * dz >= 0.0;
+    double ux = src_i ? ax : bx, uy = src_i ? ay : by, uz = src_i ? az : bz;
+    double tx = src_i ? bx : ax, ty = src_i ? by : ay, tz = src_i ? bz : az;
+    if (!src_i) { dx = -dx; dy = -dy; dz = -dz; }
+    double cx = uy * dz - uz * dy, cy = uz * dx - ux * dz, cz = ux * dy - uy * dx;
+    double l2 = cx * cx + cy * cy + cz * cz;
+    if (!(l2 > 1e-24 * d2)) return false;
+    double il = rsqrt_nr(l2);
+    double ud = ux * dx + uy * dy + uz * dz;
+    double ut = ux * tx + uy * ty + uz * tz;
+    double dt = dx * tx + dy * ty + dz * tz;
+    double uu = ux * ux + uy * uy + uz * uz;
+    double alpha = (cx * tx + cy * ty + cz * tz) * il;
+    double phi = ud * rsqrt_nr(d2);
+    double wt = (ud * ut - dt * uu) * il;             // w . n_t
+    double sa = fabs(ut) + fabs(wt);
+    double pa = 0.0;
+    if (sa > 0.0) {
+        double q = ut * rcp_nr(sa);
+        pa = signbit(wt) ? q - 1.0 : 1.0 - q;
+    }
+    int bt = 0;
+#pragma unroll
+    for (int e = 0; e < NB - 1; ++e) bt += pa >= te.e[e];
+    b0 = bin11(NB * (alpha + 1.0) / 2.0);
+    b1 = NB + bin11(NB * (phi + 1.0) / 2.0);
+    b2 = 2 * NB + bt;
+    return true;
+}
+
+constexpr int SPFH_RING = 128;   // per-wavefront ring of (owner lane, neighbour) pairs
+
+__device__ __forceinline__ uint32_t lanes_below64(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lanes walk their stencils in lockstep (lanes of one cell read the same
+// candidates at the same time); every neighbour found is parked as
+// (owner lane, j) in a wavefront ring, and whenever 64 are parked each lane
+// takes one and bins that pair.  The expensive pair geometry thus runs on
+// full wavefronts instead of whenever any lane has a neighbour.  Bins are
+// counted with integer LDS atomics into the owner's histogram (order
+// independent); kp is the sum of the alpha block (each counted pair adds one
+// to every block).
 __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, GridView g, const double *nxa,
                                                  const double *nya, const double *nza, double r2, ThetaEdges te,
                                                  uint4 *spfh, int32_t *knb) {
     __shared__ uint32_t hist[SPFH_T * FD];
+    __shared__ int2 ring_all[SPFH_T / 64][SPFH_RING];
+    __shared__ uint32_t cur_all[SPFH_T / 64][2];      // ring head, tail of each wavefront
     uint32_t *h = hist + threadIdx.x * FD;
 #pragma unroll
     for (int c = 0; c < FD; ++c) h[c] = 0;
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int2 *ring = ring_all[wv];
+    uint32_t *hw = hist + wv * 64 * FD;               // this wavefront's 64 histograms
+    const int64_t s0 = F.off + b.start + wv * 64;      // sorted index of lane 0's point
     const int i = b.start + threadIdx.x;
-    if (i >= F.n) return;                       // no block-wide barrier follows
+    const bool live = i < F.n;
     const int64_t s = F.off + i;
-    const float4 p4 = g.p[s];
-    const double px = p4.x, py = p4.y, pz = p4.z;
-    const double ax = nxa[s], ay = nya[s], az = nza[s];
-    int k = 0, kp = 0;
-    for_stencil(F, g, px, py, pz, [&](int32_t j) {
-        const float4 q4 = g.p[j];
-        double dx = (double)q4.x - px, dy = (double)q4.y - py, dz = (double)q4.z - pz;
-        double d2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-        if (!(d2 > 0.0 && d2 <= r2)) return;
-        ++k;
-        double bx = nxa[j], by = nya[j], bz = nza[j];
-        bool src_i = (ax + bx) * dx + (ay + by) * dy + (az + bz) * dz >= 0.0;
-        double ux = src_i ? ax : bx, uy = src_i ? ay : by, uz = src_i ? az : bz;
-        double tx = src_i ? bx : ax, ty = src_i ? by : ay, tz = src_i ? bz : az;
-        if (!src_i) { dx = -dx; dy = -dy; dz = -dz; }
-        double cx = uy * dz - uz * dy, cy = uz * dx - ux * dz, cz = ux * dy - uy * dx;
-        double l2 = cx * cx + cy * cy + cz * cz;
-        if (!(l2 > 1e-24 * d2)) return;               // |u x e| <= 1e-12: degenerate frame, pair skipped
-        double il = rsqrt_nr(l2);
-        double ud = ux * dx + uy * dy + uz * dz;
-        double ut = ux * tx + uy * ty + uz * tz;
-        double dt = dx * tx + dy * ty + dz * tz;
-        double uu = ux * ux + uy * uy + uz * uz;
-        double alpha = (cx * tx + cy * ty + cz * tz) * il;
-        double phi = ud * rsqrt_nr(d2);
-        double wt = (ud * ut - dt * uu) * il;             // w . n_t
-        double sa = fabs(ut) + fabs(wt);
-        double pa = 0.0;
-        if (sa > 0.0) {
-            double q = ut * rcp_nr(sa);
-            pa = signbit(wt) ? q - 1.0 : 1.0 - q;
+    // The ring cursors live in LDS: lanes leave the stencil's x-runs at
+    // different times, so register copies would go stale in lanes that sat
+    // out some iterations.  Every active lane reads them; the first active
+    // lane writes them back.
+    uint32_t *cur = cur_all[wv];
+    if (lane == 0) { cur[0] = 0; cur[1] = 0; }
+    // bin the pair parked in slot e (owner lane o, neighbour j)
+    auto bin_pair = [&](int2 e) {
+        const int64_t so = s0 + e.x;
+        const float4 o4 = g.p[so];
+        int b0, b1, b2;
+        if (pair_bins(o4.x, o4.y, o4.z, nxa[so], nya[so], nza[so], g.p[e.y], nxa[e.y], nya[e.y], nza[e.y], te, b0, b1,
+                      b2)) {
+            uint32_t *ho = hw + e.x * FD;
+            atomicAdd(ho + b0, 1u);
+            atomicAdd(ho + b1, 1u);
+            atomicAdd(ho + b2, 1u);
         }
-        int bt = 0;
+    };
+    wave_sync_lds();
+    int k = 0;
+    if (live) {
+        const float4 p4 = g.p[s];
+        const double px = p4.x, py = p4.y, pz = p4.z;
+        for_stencil(F, g, px, py, pz, [&](int32_t j) {
+            const float4 q4 = g.p[j];
+            double dx = (double)q4.x - px, dy = (double)q4.y - py, dz = (double)q4.z - pz;
+            double d2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+            const bool hit = d2 > 0.0 && d2 <= r2;
+            k += hit ? 1 : 0;
+            const uint64_t m = __ballot(hit);
+            const uint64_t act = __ballot(true);
+            const uint32_t me = lanes_below64(act);
+            wave_sync_lds();
+            uint32_t head = cur[0], tail = cur[1];
+            if (hit) ring[(tail + lanes_below64(m)) & (SPFH_RING - 1)] = make_int2(lane, j);
+            tail += __popcll(m);
+            if (tail - head >= 64) {                   // the active lanes each bin one parked pair
+                wave_sync_lds();
+                bin_pair(ring[(head + me) & (SPFH_RING - 1)]);
+                head += __popcll(act);
+            }
+            wave_sync_lds();
+            if (me == 0) { cur[0] = head; cur[1] = tail; }
+        });
+    }
+    // drain with the whole wavefront
+    wave_sync_lds();
+    uint32_t head = cur[0];
+    const uint32_t tail = cur[1];
+    while (head != tail) {
+        const uint32_t n = min(64u, tail - head);
+        if ((uint32_t)lane < n) bin_pair(ring[(head + lane) & (SPFH_RING - 1)]);
+        head += n;
+    }
+    wave_sync_lds();
+    if (!live) return;
+    uint32_t kp = 0;
 #pragma unroll
-        for (int e = 0; e < NB - 1; ++e) bt += pa >= te.e[e];
-        ++kp;
-        h[bin11(NB * (alpha + 1.0) / 2.0)] += 1;
-        h[NB + bin11(NB * (phi + 1.0) / 2.0)] += 1;
-        h[2 * NB + bt] += 1;
-    });
+    for (int c = 0; c < NB; ++c) kp += h[c];
     // SPFH_i = counts / kp, stored as the exact counts (u16) and 1/kp.  Beyond
     // 65535 pairs the counts are rescaled to 16 bits (relative error <= 2^-16).
     float sc = kp > 0 ? 1.0f / (float)kp : 0.0f;
     uint32_t w[4 * SPR];
 #pragma unroll
     for (int m = 0; m < 4 * SPR; ++m) w[m] = 0u;
+    uint32_t hc[FD];
+#pragma unroll
+    for (int c = 0; c < FD; ++c) hc[c] = h[c];
     if (kp > 65535) {
 #pragma unroll
-        for (int c = 0; c < FD; ++c) h[c] = (uint32_t)((double)h[c] * (65535.0 / (double)kp) + 0.5);
+        for (int c = 0; c < FD; ++c) hc[c] = (uint32_t)((double)hc[c] * (65535.0 / (double)kp) + 0.5);
         sc = 1.0f / 65535.0f;
     }
 #pragma unroll
-    for (int c = 0; c < FD; ++c) w[c >> 1] |= (h[c] & 0xffffu) << (16 * (c & 1));
+    for (int c = 0; c < FD; ++c) w[c >> 1] |= (hc[c] & 0xffffu) << (16 * (c & 1));
     w[4 * SPR - 1] = __float_as_uint(sc);
     uint4 *o = spfh + s * SPR;
 #pragma unroll
