@@ -552,10 +552,11 @@ void orc_tie_flags(const double *F, int64_t nP, const double *G, int64_t nQ,
 /* O6: quadruple consistency filter (Algorithm 1, hypothesis pre-rejection,  */
 /* tau = 0.9).  Counter-based randomness: the n-th output of SplitMix64      */
 /* (Steele, Lea and Flood, 2014) with the stated seed, n packed from         */
-/* (trial, slot, attempt).  A slot draws P indices until one has a           */
-/* reciprocal correspondence and differs from the earlier slots (at most 64  */
-/* attempts, else the trial is void).  The closed quadrilateral of the 4     */
-/* points must have every edge ratio within tau in both directions.          */
+/* (trial, slot, attempt).  The reciprocal correspondences C are listed in  */
+/* ascending P index; a slot draws c = ((r >> 32) |C|) >> 32, a uniform pick */
+/* from C, until it differs from the earlier slots (at most 64 attempts,     */
+/* else the trial is void).  The closed quadrilateral of the 4 points must   */
+/* have every edge ratio within tau in both directions.                      */
 /* ------------------------------------------------------------------------ */
 uint64_t orc_splitmix64(uint64_t seed, uint64_t n) {
     uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ULL;
@@ -572,6 +573,11 @@ int64_t orc_consistency(const float *px, const float *py, const float *pz, int64
     memset(flag, 0, (size_t)nP);
     int64_t passed = 0;
     if (nP <= 0) return 0;
+    int64_t nC = 0;
+    for (int64_t i = 0; i < nP; ++i) nC += mutual[i] != 0;
+    if (nC == 0) return 0;
+    int64_t *Cl = (int64_t *)malloc(sizeof(int64_t) * (size_t)nC);
+    for (int64_t i = 0, c = 0; i < nP; ++i) if (mutual[i]) Cl[c++] = i;
     #pragma omp parallel for schedule(static) reduction(+ : passed)
     for (int64_t t = 0; t < n_trials; ++t) {
         int64_t id[4];
@@ -580,8 +586,7 @@ int64_t orc_consistency(const float *px, const float *py, const float *pz, int64
             int found = 0;
             for (int a = 0; a < 64; ++a) {
                 uint64_t r = orc_splitmix64(seed, ((uint64_t)t << 8) | ((uint64_t)s << 6) | (uint64_t)a);
-                int64_t i = (int64_t)(((r >> 32) * (uint64_t)nP) >> 32);
-                if (!mutual[i]) continue;
+                int64_t i = Cl[(int64_t)(((r >> 32) * (uint64_t)nC) >> 32)];
                 int dup = 0;
                 for (int u = 0; u < s; ++u) dup |= (id[u] == i);
                 if (dup) continue;
@@ -604,6 +609,7 @@ int64_t orc_consistency(const float *px, const float *py, const float *pz, int64
             flag[id[k]] = 1;
         }
     }
+    free(Cl);
     return passed;
 }
 

@@ -68,16 +68,18 @@ def test_splitmix64_published_vector(orc):
 
 
 def _drawn_quads(orc, nP, mutual, n_trials, seed):
-    """The quadruples the sampler draws, reconstructed from its generator."""
+    """The quadruples the sampler draws, reconstructed from its generator:
+    uniform picks from the reciprocal correspondences in ascending P order."""
     quads = []
+    C = [i for i in range(nP) if mutual[i]]
     for t in range(n_trials):
         ids = []
         for s in range(4):
             got = None
             for a in range(64):
                 r = orc.splitmix64(seed, (t << 8) | (s << 6) | a)
-                i = ((r >> 32) * nP) >> 32
-                if mutual[i] and i not in ids:
+                i = C[((r >> 32) * len(C)) >> 32]
+                if i not in ids:
                     got = i
                     break
             if got is None:
