@@ -62,7 +62,6 @@ struct Plan {
     TrialBlk *tb = nullptr;
     int ntb = 0;
     int32_t *scan_tmp = nullptr;
-    int max_nP = 0;                // largest P fragment (consistency LDS sizing)
     double *nrm_orig = nullptr;    // stage calls: normals in original order (3 per point)
     int64_t *cnt64 = nullptr;      // small device scalars for stage outputs
     void *mscratch = nullptr;      // matcher scratch
@@ -213,7 +212,6 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
         for (int32_t st = 0; st < F.n; st += 256) b256.push_back(Blk{f, st});
         for (int32_t st = 0; st < F.n; st += 512) b512.push_back(Blk{f, st});
         pk_rows += ((int64_t)F.n + 127) / 128 * 128;
-        if ((f & 1) == 0) P->max_nP = std::max(P->max_nP, (int)F.n);
     }
     if (paired && prm) {
         const int tpb = trials_per_block();
@@ -254,7 +252,6 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     for (int a = 0; a < 3; ++a) o_n[a] = D.add(8 * n1);
     size_t o_spfh = D.add(16 * SPR * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
     size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
-    size_t o_bits = D.add(8 * (size_t)mbits_words(ntot, nf));
     size_t o_cpack = D.add(32 * n1);
     size_t o_nn = D.add(4 * n1), o_dist = D.add(4 * n1), o_mut = D.add(n1), o_flag = D.add(4 * n1),
            o_kpos = D.add(4 * n1), o_kp = D.add(12 * n1), o_kq = D.add(12 * n1), o_ki = D.add(4 * n1);
@@ -299,7 +296,6 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->m.nn = (int32_t *)(db + o_nn);
     P->m.dist = (float *)(db + o_dist);
     P->m.mutual = (uint8_t *)(db + o_mut);
-    P->m.mbits = (uint64_t *)(db + o_bits);
     P->m.cpack = (float4 *)(db + o_cpack);
     P->m.flag = (int32_t *)(db + o_flag);
     P->m.kpos = (int32_t *)(db + o_kpos);
@@ -369,7 +365,7 @@ int run_pairs(lsr_ctx *c, Plan *P, const lsr_params &prm, lsr_result *d_out, hip
         tmark("match_fp32", s);
     }
     HIPCHK(c, launch_mutual(P->g, P->m, P->ps, s));
-    HIPCHK(c, launch_consistency(P->g, P->m, P->ps, P->tb, P->ntb, P->max_nP, prm.tau, prm.seed, c->tune_cons, s));
+    HIPCHK(c, launch_consistency(P->g, P->m, P->ps, P->tb, P->ntb, prm.tau, prm.seed, c->tune_cons, P->scan_tmp, s));
     tmark("consistency", s);
     HIPCHK(c, launch_compact(P->g, P->m, P->ps, P->scan_tmp, s));
     HIPCHK(c, launch_gnc(P->g, P->m, P->ps, P->npairs, prm, s));
@@ -657,7 +653,7 @@ int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, c
         }, &res.screen_ms[v]);
     for (int v = 0; v < res.n_consistency_shapes && !rc; ++v)
         rc = time_ms(ctx, s, reps, [&]() -> int {
-            HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, pl->max_nP, tp.tau, tp.seed, v, s));
+            HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, tp.tau, tp.seed, v, pl->scan_tmp, s));
             return LSR_OK;
         }, &res.consistency_ms[v]);
     g_timing.on = timing;
@@ -802,8 +798,7 @@ int lsr_stage_consistency(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, 
     HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
     HIPCHK(ctx, copy<int32_t>(pl->m.nn, d_nnQ, P->n, s));
     HIPCHK(ctx, copy<uint8_t>(pl->m.mutual, d_mutual, P->n, s));
-    HIPCHK(ctx, launch_mutual_bits(pl->g, pl->m, s));
-    HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, pl->max_nP, tau, seed, ctx->tune_cons, s));
+    HIPCHK(ctx, launch_consistency(pl->g, pl->m, pl->ps, pl->tb, pl->ntb, tau, seed, ctx->tune_cons, pl->scan_tmp, s));
     if (P->n > 0) {
         hipLaunchKernelGGL(k_flag_out, dim3(nblk(P->n, 256)), dim3(256), 0, s, (const int32_t *)pl->m.flag, P->n, d_flag);
         HIPCHK(ctx, hipGetLastError());

@@ -1,15 +1,14 @@
 // Reciprocal test, quadruple consistency filter and compaction.
 //
-// Reciprocal: (i, nnQ(i)) is kept when nnP(nnQ(i)) = i; the flags are also
-// written as a bitmap (one wavefront ballot per 64 points) that the
-// consistency trials read from LDS.
-// Consistency (Algorithm 1's pre-rejection, used as a filter): trial t draws
-// four distinct P indices that have a reciprocal correspondence; slot s takes
-// the first of up to 64 draws i = ((r >> 32) * N_P) >> 32 that qualifies, with
-// r the n-th output of SplitMix64 (Steele, Lea and Flood 2014) for the given
-// seed and n = (t << 8) | (s << 6) | attempt.  The closed quadrilateral passes
-// when every edge length ratio lies within tau in both directions (squared,
-// FP64); the correspondences of a passing trial are flagged.
+// Reciprocal: (i, nnQ(i)) is kept when nnP(nnQ(i)) = i.
+// Consistency (Algorithm 1's pre-rejection, used as a filter): the reciprocal
+// correspondences C of a pair are packed in ascending P index; trial t draws
+// four distinct members of C, slot s taking the first of up to 64 draws
+// c = ((r >> 32) * |C|) >> 32 that differs from the earlier slots, with r the
+// n-th output of SplitMix64 (Steele, Lea and Flood 2014) for the given seed
+// and n = (t << 8) | (s << 6) | attempt.  The closed quadrilateral passes when
+// every edge length ratio lies within tau in both directions (squared, FP64);
+// the correspondences of a passing trial are flagged.
 // Compaction: flagged correspondences in ascending P index, as float xyz of p
 // and q, the input of the pose solve.
 #include <algorithm>
@@ -18,10 +17,8 @@
 
 namespace lsr {
 
-__device__ __forceinline__ int64_t mbits_base(const Frag &F, int f) { return F.off / 64 + f; }
-
 __global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk, const int32_t *nn, uint8_t *mutual,
-                                                uint64_t *mbits, PairState *ps) {
+                                                PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     int i = b.start + threadIdx.x;
@@ -34,7 +31,6 @@ __global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk
     }
     unsigned long long bal = __ballot(m);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0 && b.start + 64 * w < F.n) mbits[mbits_base(F, b.frag) + (b.start + 64 * w) / 64] = bal;
     __shared__ int cnt[4];
     if ((threadIdx.x & 63) == 0) cnt[w] = __popcll(bal);
     __syncthreads();
@@ -47,26 +43,7 @@ __global__ void __launch_bounds__(256) k_mutual(const Frag *frag, const Blk *blk
 hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mutual, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)m.nn, m.mutual, m.mbits, ps);
-    return hipGetLastError();
-}
-
-// Bitmap of given reciprocal flags (stage calls).
-__global__ void __launch_bounds__(256) k_mutual_bits(const Frag *frag, const Blk *blk, const uint8_t *mutual,
-                                                     uint64_t *mbits) {
-    const Blk b = blk[blockIdx.x];
-    const Frag &F = frag[b.frag];
-    int i = b.start + threadIdx.x;
-    bool m = i < F.n && mutual[F.off + i];
-    unsigned long long bal = __ballot(m);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0 && b.start + 64 * w < F.n) mbits[mbits_base(F, b.frag) + (b.start + 64 * w) / 64] = bal;
-}
-
-hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s) {
-    if (g.ntot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mutual_bits, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const uint8_t *)m.mutual, m.mbits);
+                       (const int32_t *)m.nn, m.mutual, ps);
     return hipGetLastError();
 }
 
@@ -86,28 +63,47 @@ constexpr int TPB = 8192;    // trials per block (the trial table's granularity)
 constexpr int CONS_THREADS[] = {256, 128, 512};   // block widths the autotuner picks from
 constexpr int N_CONS_SHAPES = sizeof(CONS_THREADS) / sizeof(CONS_THREADS[0]);
 constexpr int QCAP = 128;    // per-wavefront ring of drawn quadruples awaiting the edge test
-constexpr int MB_LDS = 8192; // largest bitmap staged in LDS (words): fragments up to 524,288 points
 
-// Coordinates of each reciprocal correspondence, packed so that one trial
-// slot reads 32 contiguous bytes: (p_i, q_nnQ(i)).
+// usable[g] = 1 for a P point with a reciprocal correspondence inside Q (scan input).
+__global__ void __launch_bounds__(256) k_corr_usable(const Frag *frag, const Blk *blk, const int32_t *nn,
+                                                     const uint8_t *mutual, int32_t *usable) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &P = frag[b.frag];
+    int i = b.start + threadIdx.x;
+    if (i >= P.n) return;
+    bool u = false;
+    if ((b.frag & 1) == 0 && P.partner >= 0 && mutual[P.off + i]) {
+        int32_t j = nn[P.off + i];
+        u = j >= 0 && j < frag[P.partner].n;
+    }
+    usable[P.off + i] = u ? 1 : 0;
+}
+
+// C packed in ascending P index at the scanned slots, one trial slot reading 32
+// contiguous bytes: (p_i, q_nnQ(i)) and i; the pair's list start and length.
 __global__ void __launch_bounds__(256) k_corr_pack(const Frag *frag, const Blk *blk, const int32_t *nn,
-                                                   const uint8_t *mutual, uint64_t *mbits, float4 *cpack) {
+                                                   const int32_t *usable, const int32_t *cpos, float4 *cpack,
+                                                   PairState *ps) {
     const Blk b = blk[blockIdx.x];
     const Frag &P = frag[b.frag];
     if ((b.frag & 1) || P.partner < 0) return;
     const Frag &Q = frag[P.partner];
     int i = b.start + threadIdx.x;
-    if (i >= P.n || !mutual[P.off + i]) return;
-    int32_t j = nn[P.off + i];
-    if (j < 0 || j >= Q.n) {                      // not a usable correspondence: never drawn
-        atomicAnd((unsigned long long *)&mbits[mbits_base(P, b.frag) + i / 64], ~(1ull << (i & 63)));
-        return;
+    if (i >= P.n) return;
+    const int64_t gi = P.off + i;
+    if (i == P.n - 1) {
+        ps[P.pair].c_off = cpos[P.off];
+        ps[P.pair].c_cnt = cpos[gi] + usable[gi] - cpos[P.off];
     }
-    cpack[2 * (P.off + i)] = make_float4(P.src[0][i], P.src[1][i], P.src[2][i], Q.src[0][j]);
-    cpack[2 * (P.off + i) + 1] = make_float4(Q.src[1][j], Q.src[2][j], 0.f, 0.f);
+    if (!usable[gi]) return;
+    const int32_t j = nn[gi];
+    const int64_t c = cpos[gi];
+    cpack[2 * c] = make_float4(P.src[0][i], P.src[1][i], P.src[2][i], Q.src[0][j]);
+    cpack[2 * c + 1] = make_float4(Q.src[1][j], Q.src[2][j], __int_as_float(i), 0.f);
 }
 
-// Edge test of one drawn quadruple; flags its correspondences when it passes.
+// Edge test of one drawn quadruple (positions in the pair's packed C); flags
+// the correspondences' P points when it passes.
 __device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, int32_t *flag) {
     const int id[4] = {e.x, e.y, e.z, e.w};
     float4 a0[4], a1[4];
@@ -123,7 +119,7 @@ __device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, in
     }
     if (!ok) return 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) flag[id[k]] = 1;
+    for (int k = 0; k < 4; ++k) flag[__float_as_int(a1[k].z)] = 1;
     return 1;
 }
 
@@ -145,27 +141,19 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (they depend only on the trial index) nor the result (flags are set, counts
 // summed).
 template <int CT>
-__global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const uint64_t *mbits,
-                                                    const float4 *cpack, int32_t *flag, double t2, uint64_t seed,
-                                                    int use_lds, PairState *ps) {
-    extern __shared__ uint64_t bm[];
+__global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const float4 *cpack,
+                                                    int32_t *flag, double t2, uint64_t seed, PairState *ps) {
     __shared__ int4 ring[CT / 64][QCAP];
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
-    const uint32_t nP = (uint32_t)P.n;
-    const int nw = (P.n + 63) / 64;
-    const uint64_t *gbits = mbits + mbits_base(P, 2 * b.pair);
-    if (use_lds)
-        for (int k = threadIdx.x; k < nw; k += CT) bm[k] = gbits[k];
-    __syncthreads();
-    const uint32_t *bits = (const uint32_t *)(use_lds ? bm : gbits);
-    const float4 *cp = cpack + 2 * P.off;
+    const uint32_t nC = (uint32_t)ps[b.pair].c_cnt;
+    const float4 *cp = cpack + 2 * ps[b.pair].c_off;
     int32_t *fl = flag + P.off;
     const int lane = threadIdx.x & 63;
     int4 *q = ring[threadIdx.x >> 6];
     constexpr int PER_WAVE = TPB / (CT / 64);
     const int64_t wbeg = b.first + (int64_t)(threadIdx.x >> 6) * PER_WAVE;
-    const int64_t wend = nP ? min(b.count, wbeg + PER_WAVE) : wbeg;
+    const int64_t wend = nC ? min(b.count, wbeg + PER_WAVE) : wbeg;
     int64_t next = wbeg;                       // next unclaimed trial (uniform)
     uint32_t qhead = 0, qtail = 0;             // ring cursors (uniform)
     bool live = false;
@@ -187,9 +175,8 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
         int4 quad;
         bool push = false;
         if (live) {
-            const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z) * nP) >> 32);
-            bool hit = (bits[i >> 5] >> (i & 31)) & 1u;
-            hit = hit && !(sl > 0 && (int)i == id0) && !(sl > 1 && (int)i == id1) && !(sl > 2 && (int)i == id2);
+            const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z) * nC) >> 32);   // position in C
+            const bool hit = !(sl > 0 && (int)i == id0) && !(sl > 1 && (int)i == id1) && !(sl > 2 && (int)i == id2);
             if (hit) {
                 if (sl == 3) {
                     quad = make_int4(id0, id1, id2, (int)i);
@@ -227,26 +214,26 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
     if (lane == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
 }
 
-hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb, int max_nP,
-                              float tau, uint64_t seed, int shape, hipStream_t s) {
-    hipError_t e = fill<int32_t>(m.flag, 0, g.ntot, s);
-    if (e != hipSuccess || ntb == 0 || g.ntot == 0) return e;
+hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
+                              float tau, uint64_t seed, int shape, int32_t *scan_tmp, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corr_usable, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)m.nn, (const uint8_t *)m.mutual, m.flag);
+    hipError_t e = exclusive_scan_i32(m.flag, m.kpos, g.ntot, scan_tmp, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_corr_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)m.nn, (const uint8_t *)m.mutual, m.mbits, m.cpack);
+                       (const int32_t *)m.nn, (const int32_t *)m.flag, (const int32_t *)m.kpos, m.cpack, ps);
+    if ((e = fill<int32_t>(m.flag, 0, g.ntot, s)) != hipSuccess || ntb == 0) return e;
     double t2 = (double)tau * (double)tau;
-    int words = (max_nP + 63) / 64;
-    int use_lds = words <= MB_LDS ? 1 : 0;
-    size_t shm = use_lds ? sizeof(uint64_t) * (size_t)std::max(words, 1) : 0;
     const Frag *fr = (const Frag *)g.frag;
-    const uint64_t *mb = (const uint64_t *)m.mbits;
     const float4 *cp = (const float4 *)m.cpack;
     switch (shape) {
-    case 0: hipLaunchKernelGGL(k_consistency<CONS_THREADS[0]>, dim3(ntb), dim3(CONS_THREADS[0]), shm, s, fr, tb, mb, cp,
-                               m.flag, t2, seed, use_lds, ps); break;
-    case 1: hipLaunchKernelGGL(k_consistency<CONS_THREADS[1]>, dim3(ntb), dim3(CONS_THREADS[1]), shm, s, fr, tb, mb, cp,
-                               m.flag, t2, seed, use_lds, ps); break;
-    case 2: hipLaunchKernelGGL(k_consistency<CONS_THREADS[2]>, dim3(ntb), dim3(CONS_THREADS[2]), shm, s, fr, tb, mb, cp,
-                               m.flag, t2, seed, use_lds, ps); break;
+    case 0: hipLaunchKernelGGL(k_consistency<CONS_THREADS[0]>, dim3(ntb), dim3(CONS_THREADS[0]), 0, s, fr, tb, cp,
+                               m.flag, t2, seed, ps); break;
+    case 1: hipLaunchKernelGGL(k_consistency<CONS_THREADS[1]>, dim3(ntb), dim3(CONS_THREADS[1]), 0, s, fr, tb, cp,
+                               m.flag, t2, seed, ps); break;
+    case 2: hipLaunchKernelGGL(k_consistency<CONS_THREADS[2]>, dim3(ntb), dim3(CONS_THREADS[2]), 0, s, fr, tb, cp,
+                               m.flag, t2, seed, ps); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -55,6 +55,7 @@ struct PairState {
     double energy, mu_final;
     int32_t status, iters;
     int64_t k_off;                     // first consistent correspondence in the compact list
+    int64_t c_off, c_cnt;              // the pair's reciprocal correspondences in the packed list
     float mean_desc[PK];               // centring vector of the bf16 screen (projected space)
 };
 
@@ -121,8 +122,7 @@ struct MatchBufs {
     int32_t *nn;               // original order: nearest neighbour (index in partner fragment)
     float *dist;
     uint8_t *mutual;           // original order
-    uint64_t *mbits;           // the same flags as a bitmap, per fragment from word off/64 + f
-    float4 *cpack;             // per P point with a reciprocal match: (px, py, pz, qx), (qy, qz, 0, 0)
+    float4 *cpack;             // reciprocal correspondences packed per pair: (px, py, pz, qx), (qy, qz, i, 0)
     int32_t *flag;             // consistency flags, original order (int32 for the scan)
     int32_t *kpos;             // exclusive scan of flags over the batch
     float *kp, *kq;            // consistent correspondences, compacted: xyz of p and q (3 floats each)
@@ -145,10 +145,8 @@ hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStrea
 hipError_t launch_spfh_out(const GridBufs &g, const DescBufs &d, float *out, int32_t *kout, hipStream_t s);
 hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairState *ps, hipStream_t s);
 hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s);
-hipError_t launch_mutual_bits(const GridBufs &g, MatchBufs &m, hipStream_t s);
-inline int64_t mbits_words(int64_t ntot, int nfrag) { return ntot / 64 + nfrag + 1; }
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
-                              int max_nP, float tau, uint64_t seed, int shape, hipStream_t s);
+                              float tau, uint64_t seed, int shape, int32_t *scan_tmp, hipStream_t s);
 hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);
 hipError_t launch_gnc(const GridBufs &g, const MatchBufs &m, PairState *ps, int npairs, const lsr_params &prm,
                       hipStream_t s);
