@@ -44,6 +44,7 @@ def main():
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--shapes", default=None, help="force launch shapes 'screen,consistency' instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -76,7 +77,11 @@ def main():
     prm = lsr.default_params(precision=lsr.BF16_SCREEN)
     out = torch.empty(npairs * lsr._lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
     tune = None
-    if not args.no_autotune:                   # setup, like plan creation: outside the timed region
+    if args.shapes:
+        sv, cv = (int(x) for x in args.shapes.split(","))
+        lsr.set_tune(sv, cv)
+        tune = {"screen_shape": sv, "consistency_shape": cv, "forced": True}
+    elif not args.no_autotune:                   # setup, like plan creation: outside the timed region
         ta = time.perf_counter()
         tune = lsr.autotune(Pd, Qd, offP, offQ, prm, reps=1)
         log(f"autotune ({time.perf_counter() - ta:.1f}s): screen shape {tune['screen_shape']} "

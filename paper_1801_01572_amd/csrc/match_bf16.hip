@@ -43,12 +43,15 @@ namespace lsr {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Screen shapes: SW waves per block x SQB 16-query blocks per wave = 256
-// queries per block (one block per 256 rows of a fragment, any variant);
-// CH 16-row tiles per LDS chunk.  The variant is chosen by the autotuner.
-struct ScreenShape { int sw, sqb, ch; };
-constexpr ScreenShape SCREEN_SHAPES[] = {{4, 4, 8}, {4, 4, 4}, {8, 2, 8}, {8, 2, 4}};
+// Screen shapes: tile edge T (16: 16x16x32 MFMAs, 32: 32x32x16 MFMAs), SW
+// waves per block x SQB T-query blocks per wave = 256 queries per block (one
+// block per 256 rows of a fragment, any variant); CH T-row tiles per LDS
+// chunk.  The variant is chosen by the autotuner.
+struct ScreenShape { int t, sw, sqb, ch; };
+constexpr ScreenShape SCREEN_SHAPES[] = {{16, 4, 4, 8}, {16, 4, 4, 4}, {16, 8, 2, 8}, {16, 8, 2, 4},
+                                         {32, 4, 2, 4}, {32, 2, 4, 4}, {16, 2, 8, 8}, {16, 2, 8, 4}};
 constexpr int N_SCREEN_SHAPES = sizeof(SCREEN_SHAPES) / sizeof(SCREEN_SHAPES[0]);
 constexpr int PAD_ROWS = 128;      // fragments' packed rows are padded to a multiple of this
 constexpr int LCAP = 32;           // candidates collected per uncertified row
@@ -323,11 +326,18 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             for (int u = 0; u < PER; ++u) r[u] = nx[threadIdx.x + u * SW * 64];
         }
         const uint4 *L = (const uint4 *)lds[buf];
+        // operands of tile t + 1 are read before tile t's MFMAs issue, so the
+        // LDS latency hides behind a whole tile of matrix work
+        uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
 #pragma unroll 2
         for (int t = 0; t < CH; ++t) {
-            const uint4 *rowp = L + (t * 16 + col) * 8;
-            bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
-            bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, nh);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, nl);
+            if (t + 1 < CH) {
+                const uint4 *rowp = L + ((t + 1) * 16 + col) * 8;
+                nh = rowp[grp ^ swz];
+                nl = rowp[(4 + grp) ^ swz];
+            }
             // two chained products per query block, the four blocks interleaved so
             // that each chain step has three independent MFMAs between it and its input
             f32x4 accs[SQB];
@@ -361,6 +371,145 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     }
 }
 
+// 32x32 tiles: 32x32x16 MFMAs (two per K = 32).  Lane (col, h) holds query col
+// and, of every 32-row tile, candidate rows 8 i + 4 h + j (i, j < 4): one lane
+// half sees 16 of the tile's rows, so the epilogue costs 12 VALU operations
+// per four MFMAs (against 6 per two with 16x16 tiles); the re-rank then
+// checks 32 rows per query.
+template <bool COLLECT, int SW, int QB, int CH>
+__global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Blk *blk, const uint16_t *pk,
+                                                      int32_t *c1_out, float *v2_out, const int32_t *fb_row,
+                                                      const int32_t *fb_cnt, const float *thr, int32_t *lst,
+                                                      int32_t *lst_cnt) {
+    static_assert(SW * QB * 32 == 256 && PAD_ROWS % (CH * 32) == 0, "screen shape");
+    constexpr int CROWS = CH * 32;                               // rows per LDS chunk
+    __shared__ __align__(16) uint16_t lds[2][CROWS * PK];
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fq = frag[b.frag];
+    if (Fq.partner < 0) return;
+    int nq = Fq.n;
+    if (COLLECT) {
+        nq = min(fb_cnt[b.frag], lst_cap(Fq));
+        if (b.start >= nq) return;
+    }
+    const Frag &Fc = frag[Fq.partner];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 31, h = lane >> 5;
+    const int swz = lds_swz(col);
+
+    // query operands: lane (col, h) holds K elements 8h..8h+7 and 16+8h..16+8h+7 of [y_hi, 1, 1]
+    bf16x8 B0[QB], B1[QB];
+    float th[QB];
+    const int qw = b.start + wv * QB * 32;
+#pragma unroll
+    for (int k = 0; k < QB; ++k) {
+        int slot = qw + 32 * k + col;
+        uint4 w0 = make_uint4(0, 0, 0, 0), w1 = w0;
+        th[k] = INFINITY;
+        if (slot < nq) {
+            int q = COLLECT ? fb_row[Fq.off + slot] : slot;
+            const uint16_t *r = pk + (Fq.pk_off + q) * PK;
+            w0 = *(const uint4 *)(r + 8 * h);
+            w1 = *(const uint4 *)(r + 16 + 8 * h);
+            if (COLLECT) th[k] = thr[Fq.off + slot];
+        }
+        if (h == 1) w1.w = 0x3f803f80u;                      // slots 30, 31 = 1.0
+        B0[k] = __builtin_bit_cast(bf16x8, w0);
+        B1[k] = __builtin_bit_cast(bf16x8, w1);
+    }
+    float v1[QB], v2[QB];
+    int32_t c1[QB];
+#pragma unroll
+    for (int k = 0; k < QB; ++k) { v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
+
+    const int nch = (Fc.n + CROWS - 1) / CROWS;
+    constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk
+    constexpr int PER = U4 / (SW * 64);
+    const uint4 *src = (const uint4 *)(pk + Fc.pk_off * PK);
+    uint4 r[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) r[u] = nch > 0 ? src[threadIdx.x + u * SW * 64] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
+    __syncthreads();
+    f32x16 zero;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) zero[e] = 0.f;
+    f32x16 prev[QB];
+    int prev_tile = -1;
+    auto epilogue = [&](const f32x16 *accs, int tile) {
+#pragma unroll
+        for (int k = 0; k < QB; ++k) {
+            const f32x16 a = accs[k];
+            float m0 = __builtin_fmaxf(__builtin_fmaxf(a[0], a[1]), __builtin_fmaxf(a[2], a[3]));
+            float m1 = __builtin_fmaxf(__builtin_fmaxf(a[4], a[5]), __builtin_fmaxf(a[6], a[7]));
+            float m2 = __builtin_fmaxf(__builtin_fmaxf(a[8], a[9]), __builtin_fmaxf(a[10], a[11]));
+            float m3 = __builtin_fmaxf(__builtin_fmaxf(a[12], a[13]), __builtin_fmaxf(a[14], a[15]));
+            const float tm = __builtin_fmaxf(__builtin_fmaxf(m0, m1), __builtin_fmaxf(m2, m3));
+            if (!COLLECT) {
+                v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);      // v2 <= v1: max(v2, min(v1, tm))
+                c1[k] = tm > v1[k] ? tile : c1[k];
+                v1[k] = __builtin_fmaxf(v1[k], tm);
+            } else if (tm >= th[k]) {                                  // rare: near-ties of uncertified rows
+                int64_t slot = lst_base(Fq, b.frag) + qw + 32 * k + col;
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (a[e] >= th[k]) {
+                        int pos = atomicAdd(&lst_cnt[slot], 1);
+                        if (pos < LCAP) lst[slot * LCAP + pos] = tile * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                    }
+            }
+        }
+    };
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) {
+            const uint4 *nx = src + (int64_t)(ch + 1) * U4;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) r[u] = nx[threadIdx.x + u * SW * 64];
+        }
+        const uint4 *L = (const uint4 *)lds[buf];
+#pragma unroll 2
+        for (int t = 0; t < CH; ++t) {
+            const uint4 *rowp = L + (t * 32 + col) * 8;
+            const bf16x8 ah0 = __builtin_bit_cast(bf16x8, rowp[h ^ swz]);
+            const bf16x8 ah1 = __builtin_bit_cast(bf16x8, rowp[(2 + h) ^ swz]);
+            const bf16x8 al0 = __builtin_bit_cast(bf16x8, rowp[(4 + h) ^ swz]);
+            const bf16x8 al1 = __builtin_bit_cast(bf16x8, rowp[(6 + h) ^ swz]);
+            f32x16 accs[QB];
+#pragma unroll
+            for (int k = 0; k < QB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, B0[k], zero, 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < QB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, B1[k], accs[k], 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < QB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, B0[k], accs[k], 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < QB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, B1[k], accs[k], 0, 0, 0);
+            if (prev_tile >= 0) epilogue(prev, prev_tile);
+#pragma unroll
+            for (int k = 0; k < QB; ++k) prev[k] = accs[k];
+            prev_tile = ch * CH + t;
+        }
+        if (ch + 1 < nch) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) ((uint4 *)lds[buf ^ 1])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
+        }
+        __syncthreads();
+    }
+    if (prev_tile >= 0) epilogue(prev, prev_tile);
+    if (!COLLECT) {
+#pragma unroll
+        for (int k = 0; k < QB; ++k) {
+            int q = qw + 32 * k + col;
+            if (q < Fq.n) {
+                int64_t o = (Fq.off + q) * 4 + h;                 // entries 0, 1 of the row's four
+                c1_out[o] = c1[k];
+                v2_out[o] = v2[k];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- re-rank
 
 __device__ __forceinline__ void load_row(const float *F, int64_t r, float *x) {
@@ -379,6 +528,7 @@ __device__ __forceinline__ float screen_err(float4 q, float best) {
     return q.z * Rp + 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;   // |d_i| Rp + 2^-15 (|y_i| R + R^2 / 2)
 }
 
+template <int T>
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
                                                 const float4 *yq, const int32_t *c1, const float *v2, int32_t *nn,
                                                 float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
@@ -400,12 +550,15 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
             float best = INFINITY;
             int32_t bj = -1;
             float a2 = -INFINITY;
-            for (int g = 0; g < 4; ++g) {
+            // T = 16: four lane groups, rows 4 g + e of their best tile;
+            // T = 32: two lane halves, rows 8 (e / 4) + 4 g + e % 4
+            constexpr int G = T == 16 ? 4 : 2, NE = T == 16 ? 4 : 16;
+            for (int g = 0; g < G; ++g) {
                 int32_t tl = c1[gi * 4 + g];
                 a2 = fmaxf(a2, v2[gi * 4 + g]);
                 if (tl < 0) continue;
-                for (int e = 0; e < 4; ++e) {
-                    int32_t j = tl * 16 + 4 * g + e;
+                for (int e = 0; e < NE; ++e) {
+                    int32_t j = T == 16 ? tl * 16 + 4 * g + e : tl * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
                     if (j >= Fc.n || !valid[Fc.off + j]) continue;
                     float x[FD];
                     load_row(F, Fc.off + j, x);
@@ -520,27 +673,48 @@ __global__ void __launch_bounds__(256) k_fallback(const Frag *frag, const float 
     }
 }
 
-template <bool COLLECT, int SW, int SQB, int CH>
+template <bool COLLECT, int T, int SW, int SQB, int CH>
 static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScratch &S, hipStream_t s) {
-    if (COLLECT)
-        hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
-                           (const Blk *)g.blk256, pk, nullptr, nullptr, (const int32_t *)S.fb_row,
-                           (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst, S.lst_cnt);
-    else
-        hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
-                           (const Blk *)g.blk256, pk, S.c1, S.v2, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if constexpr (T == 16) {
+        if (COLLECT)
+            hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr,
+                               (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
+                               S.lst_cnt);
+        else
+            hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, nullptr, nullptr, nullptr,
+                               nullptr, nullptr);
+    } else {
+        if (COLLECT)
+            hipLaunchKernelGGL((k_screen32<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr,
+                               (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
+                               S.lst_cnt);
+        else
+            hipLaunchKernelGGL((k_screen32<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, nullptr, nullptr, nullptr,
+                               nullptr, nullptr);
+    }
 }
 
 template <bool COLLECT>
 static hipError_t launch_screen_c(int shape, const GridBufs &g, const uint16_t *pk, const ScreenScratch &S,
                                   hipStream_t s) {
+#define LSR_SHAPE(v) screen_launch<COLLECT, SCREEN_SHAPES[v].t, SCREEN_SHAPES[v].sw, SCREEN_SHAPES[v].sqb, \
+                                     SCREEN_SHAPES[v].ch>(g, pk, S, s)
     switch (shape) {
-    case 0: screen_launch<COLLECT, SCREEN_SHAPES[0].sw, SCREEN_SHAPES[0].sqb, SCREEN_SHAPES[0].ch>(g, pk, S, s); break;
-    case 1: screen_launch<COLLECT, SCREEN_SHAPES[1].sw, SCREEN_SHAPES[1].sqb, SCREEN_SHAPES[1].ch>(g, pk, S, s); break;
-    case 2: screen_launch<COLLECT, SCREEN_SHAPES[2].sw, SCREEN_SHAPES[2].sqb, SCREEN_SHAPES[2].ch>(g, pk, S, s); break;
-    case 3: screen_launch<COLLECT, SCREEN_SHAPES[3].sw, SCREEN_SHAPES[3].sqb, SCREEN_SHAPES[3].ch>(g, pk, S, s); break;
+    case 0: LSR_SHAPE(0); break;
+    case 1: LSR_SHAPE(1); break;
+    case 2: LSR_SHAPE(2); break;
+    case 3: LSR_SHAPE(3); break;
+    case 4: LSR_SHAPE(4); break;
+    case 5: LSR_SHAPE(5); break;
+    case 6: LSR_SHAPE(6); break;
+    case 7: LSR_SHAPE(7); break;
     default: return hipErrorInvalidValue;
     }
+#undef LSR_SHAPE
     return hipGetLastError();
 }
 
@@ -567,10 +741,17 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     tmark("pack", s);
     if ((e = launch_screen(false, shape, g, d.pk, S, s)) != hipSuccess) return e;
     tmark("screen", s);
-    hipLaunchKernelGGL(k_rerank, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
-                       (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
-                       S.full_cnt, ps);
+    if (shape < 0 || shape >= N_SCREEN_SHAPES) return hipErrorInvalidValue;
+    if (SCREEN_SHAPES[shape].t == 16)
+        hipLaunchKernelGGL(k_rerank<16>, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
+                           (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
+                           S.full_cnt, ps);
+    else
+        hipLaunchKernelGGL(k_rerank<32>, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
+                           (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
+                           S.full_cnt, ps);
     tmark("rerank", s);
     if ((e = launch_screen(true, shape, g, d.pk, S, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rerank_list, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,

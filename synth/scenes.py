@@ -108,22 +108,36 @@ def _cyl_prims(cx, cy, r, h):
 
 
 def _inside_solids(pts, solids, eps=1e-3):
-    """Mask of points strictly inside any solid object (hidden surfaces)."""
+    """Mask of points strictly inside any solid object (hidden surfaces).
+    Each solid is tested only against the points in the x-slab its footprint
+    spans (points sorted by x once); the mask is the same as a full test."""
     bad = np.zeros(len(pts), bool)
+    order = np.argsort(pts[:, 0], kind="stable")
+    xs = pts[order, 0]
+
+    def slab(cx, rad):
+        lo, hi = np.searchsorted(xs, cx - rad - 1e-9), np.searchsorted(xs, cx + rad + 1e-9, side="right")
+        return order[lo:hi]
+
     for s in solids:
         if s[0] == "box":
             _, cx, cy, hx, hy, hz, yaw = s
-            d = pts[:, :2] - np.array([cx, cy])
+            idx = slab(cx, float(np.hypot(hx, hy)))
+            q = pts[idx]
+            d = q[:, :2] - np.array([cx, cy])
             lx = d[:, 0] * np.cos(yaw) + d[:, 1] * np.sin(yaw)
             ly = -d[:, 0] * np.sin(yaw) + d[:, 1] * np.cos(yaw)
-            bad |= (np.abs(lx) < hx - eps) & (np.abs(ly) < hy - eps) & (pts[:, 2] < hz - eps)
+            bad[idx] |= (np.abs(lx) < hx - eps) & (np.abs(ly) < hy - eps) & (q[:, 2] < hz - eps)
         elif s[0] == "cyl":
             _, cx, cy, r, h = s
-            rr = np.hypot(pts[:, 0] - cx, pts[:, 1] - cy)
-            bad |= (rr < r - eps) & (pts[:, 2] < h - eps)
+            idx = slab(cx, r)
+            q = pts[idx]
+            rr = np.hypot(q[:, 0] - cx, q[:, 1] - cy)
+            bad[idx] |= (rr < r - eps) & (q[:, 2] < h - eps)
         else:  # sphere
             _, c, r = s
-            bad |= np.linalg.norm(pts - c, axis=1) < r - eps
+            idx = slab(c[0], r)
+            bad[idx] |= np.linalg.norm(pts[idx] - c, axis=1) < r - eps
     return bad
 
 

@@ -196,7 +196,8 @@ def test_autotune_variants_agree(L):
                     ref = res
                 for b in range(len(prs)):
                     for k in ref[b]:
-                        assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), (sv, cv, b, k)
+                        if k != "n_fallback_rows":          # how many rows the screen certifies depends on its tiles
+                            assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), (sv, cv, b, k)
         t = L.autotune(Pd, Qd, offP, offQ, prm, reps=1)
         assert 0 <= t["screen_shape"] < info["n_screen_shapes"]
         assert 0 <= t["consistency_shape"] < info["n_consistency_shapes"]
@@ -207,7 +208,8 @@ def test_autotune_variants_agree(L):
         res = L.register_batch(Pd, Qd, offP, offQ, prm)
         for b in range(len(prs)):
             for k in ref[b]:
-                assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), ("tuned", b, k)
+                if k != "n_fallback_rows":
+                    assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), ("tuned", b, k)
         with pytest.raises(lib.LsrError):
             L.set_tune(info["n_screen_shapes"], 0)
     finally:

@@ -122,9 +122,14 @@ def test_match_bf16_random_and_edge_sizes(L):
         vG = (rng.random(nQ) > 0.05).astype(np.int32)
         args = (dev(F), dev(vF), dev(G), dev(vG))
         a = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.FP32)]
-        b = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.BF16_SCREEN)]
-        for k in range(4):
-            assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), (nP, nQ, k)
+        try:
+            for shape in range(L.get_tune()["n_screen_shapes"]):      # every screen tiling the autotuner may pick
+                L.set_tune(shape, 0)
+                b = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.BF16_SCREEN)]
+                for k in range(4):
+                    assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), (nP, nQ, shape, k)
+        finally:
+            L.set_tune(0, 0)
         # float32 scan == brute force in numpy's float64 on non-tied rows
         if nP and nQ:
             D = ((F[:, None, :].astype(np.float64) - G[None].astype(np.float64)) ** 2).sum(2)
