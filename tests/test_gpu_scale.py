@@ -132,3 +132,87 @@ def test_building_scale_500k(L, orc):
         d2 = np.partition(d, 1)[:2]
         if d2[1] - d2[0] > 1e-5:                    # clear of the float32 rounding of near ties
             assert m32[0][i] == j, (i, m32[0][i], j)
+
+
+def test_align_loss_c4_scale(L, orc):
+    """The differentiation workload: 64 problems of 20,000 correspondences, energy
+    at the pose the GPU's robust solve converges to, its adjoint against the
+    oracle's gradient, and central differences (h = 1e-4) on the pose."""
+    rng = np.random.default_rng(4)
+    nprob, n = 64, 20000
+    Ps, Qs, Ts, mus, Es = [], [], [], [], []
+    for k in range(nprob):
+        a = rng.normal(size=3)
+        a /= np.linalg.norm(a)
+        th = rng.uniform(0.1, 1.0)
+        K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+        R = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K
+        p = rng.uniform(-1.5, 1.5, (n, 3))
+        q = p @ R.T + rng.uniform(-0.5, 0.5, 3) + rng.normal(0, 0.003, (n, 3))
+        out = rng.random(n) < 0.3
+        q[out] = rng.uniform(-2, 2, (out.sum(), 3))
+        p32, q32 = p.astype(np.float32), q.astype(np.float32)
+        Tg, info = L.stage_gnc(dev(p32.astype(np.float64)), dev(q32.astype(np.float64)))
+        info = info.cpu().numpy()
+        assert int(info[0]) != orc.DEGENERATE
+        Ps.append(p32); Qs.append(q32); Ts.append(Tg.cpu().numpy()); mus.append(info[2]); Es.append(info[3])
+    Pf, Qf = np.concatenate(Ps), np.concatenate(Qs)
+    coff = [k * n for k in range(nprob + 1)]
+    C = np.stack([np.arange(nprob * n), np.arange(nprob * n)], 1).astype(np.int32)
+    Td, mud = dev(np.stack(Ts)), dev(np.array(mus))
+    E = L.align_loss(dev(Pf.T), dev(Qf.T), dev(C), coff, Td, mud).cpu().numpy()
+    dE = rng.uniform(0.5, 2.0, nprob)
+    dP, dQ, dxi = [t.cpu().numpy() for t in L.align_loss_backward(dev(Pf.T), dev(Qf.T), dev(C), coff, Td, mud,
+                                                                  dev(dE))]
+    for k in range(nprob):
+        s = slice(coff[k], coff[k + 1])
+        Eo, gp, gq, gx = orc.align_loss(Pf[s].astype(np.float64), Qf[s].astype(np.float64), Ts[k], mus[k])
+        assert abs(E[k] - Eo) <= 1e-12 * (1 + abs(Eo))
+        assert abs(E[k] - Es[k]) <= 1e-9 * (1 + abs(Es[k]))           # the solve's own final energy
+        assert np.abs(dxi[k] - dE[k] * gx).max() <= 1e-10 * (1 + np.abs(dE[k] * gx).max())
+        assert np.abs(dP[:, s].T - dE[k] * gp).max() <= 1e-6 * (1 + np.abs(gp).max())
+        assert np.abs(dQ[:, s].T - dE[k] * gq).max() <= 1e-6 * (1 + np.abs(gq).max())
+    # central differences, h = 1e-4.  The converged pose is stationary, so the pose
+    # check runs at a pose moved off it (there the gradient is large); the point
+    # check runs at the converged pose with the float32-representable step.
+    h = 1e-4
+
+    def exp_left(w, v):
+        Kx = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+        th = np.linalg.norm(w)
+        R = np.eye(3) if th == 0 else np.eye(3) + np.sin(th) / th * Kx + (1 - np.cos(th)) / th ** 2 * Kx @ Kx
+        D = np.eye(4)
+        D[:3, :3] = R
+        D[:3, 3] = v
+        return D
+
+    for k in (0, 1):
+        s = slice(coff[k], coff[k + 1])
+        Pk, Qk = dev(Pf[s].T.copy()), dev(Qf[s].T.copy())
+        Ck = dev(np.stack([np.arange(n), np.arange(n)], 1).astype(np.int32))
+        muk = dev(np.array([mus[k]]))
+        T1 = exp_left(np.array([0.01, -0.02, 0.015]), np.array([0.01, 0.02, -0.01])) @ Ts[k]
+        _, _, gx1 = [t.cpu().numpy() for t in L.align_loss_backward(Pk, Qk, Ck, [0, n], dev(T1[None]), muk,
+                                                                    dev(np.ones(1)))]
+        for c in range(6):
+            vals = []
+            for sg in (1, -1):
+                w, v = np.zeros(3), np.zeros(3)
+                (w if c < 3 else v)[c % 3] = sg * h
+                vals.append(L.align_loss(Pk, Qk, Ck, [0, n], dev((exp_left(w, v) @ T1)[None]), muk).item())
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - gx1[0][c]) <= 1e-4 * (1 + abs(fd)), (k, c, fd, gx1[0][c])
+        Tk = dev(Ts[k][None])
+        dPk, dQk, _ = [t.cpu().numpy() for t in L.align_loss_backward(Pk, Qk, Ck, [0, n], Tk, muk, dev(np.ones(1)))]
+        for i in rng.choice(n, 4, replace=False):
+            for side, X, G in (("p", Pf[s], dPk), ("q", Qf[s], dQk)):
+                for c in range(3):
+                    vals = []
+                    for sg in (1, -1):
+                        Xp = X.copy()
+                        Xp[i, c] = np.float32(X[i, c] + sg * h)
+                        vals.append((L.align_loss(dev(Xp.T.copy()) if side == "p" else Pk,
+                                                  dev(Xp.T.copy()) if side == "q" else Qk,
+                                                  Ck, [0, n], Tk, muk).item(), float(Xp[i, c])))
+                    fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+                    assert abs(fd - G[c, i]) <= 1e-3 * (1 + abs(fd)), (k, side, i, c, fd, G[c, i])
