@@ -68,6 +68,7 @@ struct ScreenScratch {
     float4 *yq;           // pk_rows: (|y|^2, c = d . y, |d|, 0) with d = y - bf16(y)
     int32_t *c1;          // ntot x 4: best tile per lane group
     float *v2;            // ntot x 4: second-best tile maximum per lane group
+    float *v1;            // ntot x 4: best tile maximum per lane group
     int32_t *fb_row;      // ntot: uncertified rows, per fragment from Frag::off
     float *thr;           // ntot: collection threshold of each uncertified row
     int32_t *fb_cnt;      // nfrag
@@ -91,6 +92,7 @@ static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     s.yq = (float4 *)take(sizeof(float4) * (size_t)std::max<int64_t>(g.pk_rows, 1));
     s.c1 = (int32_t *)take(sizeof(int32_t) * 4 * n1);
     s.v2 = (float *)take(sizeof(float) * 4 * n1);
+    s.v1 = (float *)take(sizeof(float) * 4 * n1);
     s.fb_row = (int32_t *)take(sizeof(int32_t) * n1);
     s.thr = (float *)take(sizeof(float) * n1);
     s.fb_cnt = (int32_t *)take(sizeof(int32_t) * (size_t)std::max(g.nfrag, 1));
@@ -237,7 +239,7 @@ __device__ __forceinline__ int lds_slot(int idx) {            // uint4 index of 
 // reaches the row's threshold to the row's candidate list.
 template <bool COLLECT, int SW, int SQB, int CH>
 __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, const uint16_t *pk,
-                                                    int32_t *c1_out, float *v2_out, const int32_t *fb_row,
+                                                    int32_t *c1_out, float *v2_out, float *v1_out, const int32_t *fb_row,
                                                     const int32_t *fb_cnt, const float *thr, int32_t *lst,
                                                     int32_t *lst_cnt) {
     static_assert(SW * SQB * 16 == 256 && PAD_ROWS % (CH * 16) == 0, "screen shape");
@@ -366,6 +368,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
                 int64_t o = (Fq.off + q) * 4 + grp;
                 c1_out[o] = c1[k];
                 v2_out[o] = v2[k];
+                v1_out[o] = v1[k];
             }
         }
     }
@@ -378,7 +381,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 // checks 32 rows per query.
 template <bool COLLECT, int SW, int QB, int CH>
 __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Blk *blk, const uint16_t *pk,
-                                                      int32_t *c1_out, float *v2_out, const int32_t *fb_row,
+                                                      int32_t *c1_out, float *v2_out, float *v1_out, const int32_t *fb_row,
                                                       const int32_t *fb_cnt, const float *thr, int32_t *lst,
                                                       int32_t *lst_cnt) {
     static_assert(SW * QB * 32 == 256 && PAD_ROWS % (CH * 32) == 0, "screen shape");
@@ -505,6 +508,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
                 int64_t o = (Fq.off + q) * 4 + h;                 // entries 0, 1 of the row's four
                 c1_out[o] = c1[k];
                 v2_out[o] = v2[k];
+                v1_out[o] = v1[k];
             }
         }
     }
@@ -530,7 +534,8 @@ __device__ __forceinline__ float screen_err(float4 q, float best) {
 
 template <int T>
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                                const float4 *yq, const int32_t *c1, const float *v2, int32_t *nn,
+                                                const float4 *yq, const int32_t *c1, const float *v2,
+                                                const float *v1, int32_t *nn,
                                                 float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
                                                 int32_t *full_row, int32_t *full_frag, int32_t *full_cnt,
                                                 PairState *ps) {
@@ -550,13 +555,31 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
             float best = INFINITY;
             int32_t bj = -1;
             float a2 = -INFINITY;
+            const float4 qv = yq[Fq.pk_off + i];
+            const float ny2 = qv.x;
             // T = 16: four lane groups, rows 4 g + e of their best tile;
             // T = 32: two lane halves, rows 8 (e / 4) + 4 g + e % 4
             constexpr int G = T == 16 ? 4 : 2, NE = T == 16 ? 4 : 16;
+            float gv[G];
+            int gord[G];
+#pragma unroll
             for (int g = 0; g < G; ++g) {
-                int32_t tl = c1[gi * 4 + g];
                 a2 = fmaxf(a2, v2[gi * 4 + g]);
+                gv[g] = c1[gi * 4 + g] >= 0 ? v1[gi * 4 + g] : -INFINITY;
+                gord[g] = g;
+            }
+#pragma unroll
+            for (int a = 0; a < G; ++a)                    // groups by descending best-tile maximum
+#pragma unroll
+                for (int c = a + 1; c < G; ++c)
+                    if (gv[gord[c]] > gv[gord[a]]) { int t = gord[a]; gord[a] = gord[c]; gord[c] = t; }
+            for (int r = 0; r < G; ++r) {
+                const int g = gord[r];
+                int32_t tl = c1[gi * 4 + g];
                 if (tl < 0) continue;
+                // A tile whose screened maximum t obeys t + c_i + E < (|y_i|^2 - D - slack) / 2
+                // holds only rows with distance above D + slack: it cannot hold the minimum.
+                if (bj >= 0 && gv[g] + qv.y + screen_err(qv, best) < 0.5f * (ny2 - best - slack(best))) continue;
                 for (int e = 0; e < NE; ++e) {
                     int32_t j = T == 16 ? tl * 16 + 4 * g + e : tl * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
                     if (j >= Fc.n || !valid[Fc.off + j]) continue;
@@ -566,8 +589,6 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                     if (d < best || (d == best && j < bj)) { best = d; bj = j; }
                 }
             }
-            const float4 qv = yq[Fq.pk_off + i];
-            const float ny2 = qv.x;
             float E = screen_err(qv, best);
             bool cert = a2 == -INFINITY || (bj >= 0 && best + slack(best) < ny2 - 2.0f * (a2 + qv.y + E));
             if (cert) {
@@ -678,22 +699,22 @@ static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScr
     if constexpr (T == 16) {
         if (COLLECT)
             hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr, nullptr,
                                (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
                                S.lst_cnt);
         else
             hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, nullptr, nullptr, nullptr,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
                                nullptr, nullptr);
     } else {
         if (COLLECT)
             hipLaunchKernelGGL((k_screen32<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr, nullptr,
                                (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
                                S.lst_cnt);
         else
             hipLaunchKernelGGL((k_screen32<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, nullptr, nullptr, nullptr,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
                                nullptr, nullptr);
     }
 }
@@ -745,12 +766,12 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     if (SCREEN_SHAPES[shape].t == 16)
         hipLaunchKernelGGL(k_rerank<16>, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                            (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
-                           (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
+                           (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps);
     else
         hipLaunchKernelGGL(k_rerank<32>, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                            (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
-                           (const float *)S.v2, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
+                           (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps);
     tmark("rerank", s);
     if ((e = launch_screen(true, shape, g, d.pk, S, s)) != hipSuccess) return e;
