@@ -103,23 +103,28 @@ __global__ void __launch_bounds__(256) k_corr_pack(const Frag *frag, const Blk *
 }
 
 // Edge test of one drawn quadruple (positions in the pair's packed C); flags
-// the correspondences' P points when it passes.
+// the correspondences' P points when it passes.  The edges are tested in
+// order and a correspondence is fetched only while every edge so far holds:
+// the verdict is that of the full test, with fewer random gathers (the
+// kernel is bound by them).
+__device__ __forceinline__ bool edge_ok(const float4 &a0, const float4 &a1, const float4 &b0, const float4 &b1,
+                                        double t2) {
+    double a = pdist2(a0.x, a0.y, a0.z, b0.x, b0.y, b0.z);
+    double c = pdist2(a0.w, a1.x, a1.y, b0.w, b1.x, b1.y);
+    return !(a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a);
+}
+
 __device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, int32_t *flag) {
-    const int id[4] = {e.x, e.y, e.z, e.w};
-    float4 a0[4], a1[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { a0[k] = cp[2 * id[k]]; a1[k] = cp[2 * id[k] + 1]; }
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int k1 = (k + 1) & 3;
-        double a = pdist2(a0[k].x, a0[k].y, a0[k].z, a0[k1].x, a0[k1].y, a0[k1].z);
-        double c = pdist2(a0[k].w, a1[k].x, a1[k].y, a0[k1].w, a1[k1].x, a1[k1].y);
-        if (a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a) ok = false;
-    }
-    if (!ok) return 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) flag[__float_as_int(a1[k].z)] = 1;
+    const float4 p0 = cp[2 * e.x], p1 = cp[2 * e.y], q0 = cp[2 * e.x + 1], q1 = cp[2 * e.y + 1];
+    if (!edge_ok(p0, q0, p1, q1, t2)) return 0;
+    const float4 p2 = cp[2 * e.z], q2 = cp[2 * e.z + 1];
+    if (!edge_ok(p1, q1, p2, q2, t2)) return 0;
+    const float4 p3 = cp[2 * e.w], q3 = cp[2 * e.w + 1];
+    if (!edge_ok(p2, q2, p3, q3, t2) || !edge_ok(p3, q3, p0, q0, t2)) return 0;
+    flag[__float_as_int(q0.z)] = 1;
+    flag[__float_as_int(q1.z)] = 1;
+    flag[__float_as_int(q2.z)] = 1;
+    flag[__float_as_int(q3.z)] = 1;
     return 1;
 }
 
@@ -144,6 +149,9 @@ template <int CT>
 __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const float4 *cpack,
                                                     int32_t *flag, double t2, uint64_t seed, PairState *ps) {
     __shared__ int4 ring[CT / 64][QCAP];
+    __shared__ uint64_t rstep[64];             // r * 256 * gamma: a trial's first state is uniform + rstep[rank]
+    if (threadIdx.x < 64) rstep[threadIdx.x] = (uint64_t)threadIdx.x * (256ull * GAMMA);
+    __syncthreads();
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
     const uint32_t nC = (uint32_t)ps[b.pair].c_cnt;
@@ -160,43 +168,34 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
     uint64_t zslot = 0, z = 0;                 // SplitMix64 state at the slot's first draw, at the current draw
     int sl = 0, a = 0, id0 = 0, id1 = 0, id2 = 0, passed = 0;
     for (;;) {
+        // lanes without a trial take the next unclaimed ones (selects, no branches)
         const uint64_t need = __ballot(!live);
-        if (!live) {
-            const int64_t t = next + lanes_below(need);
-            if (t < wend) {
-                live = true;
-                sl = 0;
-                a = 0;
-                zslot = z = seed + (((uint64_t)t << 8) + 1ull) * GAMMA;
-            }
-        }
+        const uint32_t rank = lanes_below(need);
+        const int64_t t = next + rank;
+        const bool start = !live && t < wend;
+        const uint64_t z0 = (seed + (((uint64_t)next << 8) + 1ull) * GAMMA) + rstep[rank];   // state of trial t
+        live = live || start;
+        sl = start ? 0 : sl;
+        a = start ? 0 : a;
+        zslot = start ? z0 : zslot;
+        z = start ? z0 : z;
         next += __popcll(need);
         if (!__ballot(live)) break;
-        int4 quad;
-        bool push = false;
-        if (live) {
-            const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z) * nC) >> 32);   // position in C
-            const bool hit = !(sl > 0 && (int)i == id0) && !(sl > 1 && (int)i == id1) && !(sl > 2 && (int)i == id2);
-            if (hit) {
-                if (sl == 3) {
-                    quad = make_int4(id0, id1, id2, (int)i);
-                    push = true;
-                    live = false;
-                } else {
-                    id0 = sl == 0 ? (int)i : id0;
-                    id1 = sl == 1 ? (int)i : id1;
-                    id2 = sl == 2 ? (int)i : id2;
-                    ++sl;
-                    a = 0;
-                    zslot += 64ull * GAMMA;   // n advances by one slot (1 << 6)
-                    z = zslot;
-                }
-            } else if (++a == 64) {
-                live = false;                  // slot exhausted: the trial fails
-            } else {
-                z += GAMMA;
-            }
-        }
+        // one draw per lane: a position in C, kept unless it repeats an earlier slot
+        const int i = (int)(((uint64_t)splitmix64_hi(z) * nC) >> 32);
+        const bool dup = ((sl > 0) & (i == id0)) | ((sl > 1) & (i == id1)) | ((sl > 2) & (i == id2));
+        const bool hit = live & !dup;
+        const bool push = hit & (sl == 3);
+        const bool fail = live & !hit & (a == 63);      // 64 draws without a new member: the trial fails
+        const int4 quad = make_int4(id0, id1, id2, i);
+        id0 = (hit & (sl == 0)) ? i : id0;
+        id1 = (hit & (sl == 1)) ? i : id1;
+        id2 = (hit & (sl == 2)) ? i : id2;
+        sl += hit ? 1 : 0;
+        a = hit ? 0 : a + 1;
+        zslot += hit ? 64ull * GAMMA : 0ull;           // n advances by one slot (1 << 6)
+        z = hit ? zslot : z + GAMMA;
+        live = live & !push & !fail;
         const uint64_t pm = __ballot(push);
         if (push) q[(qtail + lanes_below(pm)) & (QCAP - 1)] = quad;
         qtail += __popcll(pm);
