@@ -10,12 +10,14 @@
 // to polish_iter iterations at max_corr^2 until |xi|_inf < 1e-12.
 //
 // One block per pair; 27 FP64 sums per iteration reduced with wavefront
-// shuffles and a fixed-order combine, so results are deterministic.
+// shuffles and a fixed-order combine, so results are deterministic.  The
+// correspondence loop is latency bound (one block per CU): 1024 threads and
+// an unrolled loop keep several loads in flight per thread.
 #include "lsr_internal.h"
 
 namespace lsr {
 
-constexpr int GT = 256;
+constexpr int GT = 1024;          // one block per pair: 16 wavefronts share each iteration's sums
 constexpr int GW = GT / 64;
 constexpr int NS = 27;            // 21 entries of the symmetric H + 6 of g
 
@@ -90,6 +92,7 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
     const double *R = sh.R, *t = sh.t;
+#pragma unroll 4
     for (int64_t c = threadIdx.x; c < m; c += GT) {
         double p[3], q[3];
         src.get(c, p, q);
@@ -120,34 +123,49 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
     }
     block_sums<NS>(acc, sh);
     if (threadIdx.x == 0) {
+        // Fully unrolled (constant indices keep H and L in registers); the first
+        // pivot at or below 1e-12 trace(H) marks the system degenerate.
         double H[6][6];
-        int k = 0;
-        for (int a = 0; a < 6; ++a)
-            for (int b = a; b < 6; ++b) { H[a][b] = acc[k]; H[b][a] = acc[k]; ++k; }
+        {
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int b = a; b < 6; ++b) { H[a][b] = acc[k]; H[b][a] = acc[k]; ++k; }
+        }
         double tr = H[0][0] + H[1][1] + H[2][2] + H[3][3] + H[4][4] + H[5][5];
         double L[6][6];
-        int ok = 1;
-        for (int j = 0; j < 6 && ok; ++j) {
+        bool okc = true;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
             double d = H[j][j];
+#pragma unroll
             for (int u = 0; u < j; ++u) d -= L[j][u] * L[j][u];
-            if (!(d > 1e-12 * tr)) { ok = 0; break; }
-            L[j][j] = sqrt(d);
+            okc = okc && d > 1e-12 * tr;
+            L[j][j] = sqrt(okc ? d : 1.0);
+#pragma unroll
             for (int i = j + 1; i < 6; ++i) {
                 double s = H[i][j];
+#pragma unroll
                 for (int u = 0; u < j; ++u) s -= L[i][u] * L[j][u];
                 L[i][j] = s / L[j][j];
             }
         }
+        const int ok = okc ? 1 : 0;
         sh.ok = ok;
         if (ok) {
             double yv[6], xi[6];
+#pragma unroll
             for (int i = 0; i < 6; ++i) {
                 double s = -acc[21 + i];
+#pragma unroll
                 for (int u = 0; u < i; ++u) s -= L[i][u] * yv[u];
                 yv[i] = s / L[i][i];
             }
+#pragma unroll
             for (int i = 5; i >= 0; --i) {
                 double s = yv[i];
+#pragma unroll
                 for (int u = i + 1; u < 6; ++u) s -= L[u][i] * xi[u];
                 xi[i] = s / L[i][i];
             }
