@@ -27,15 +27,26 @@ struct GridView {
 
 // Visit every sorted point within the 27-cell stencil of (px, py, pz): the
 // three cells adjacent along x are consecutive in the table, so the stencil is
-// nine contiguous runs of the sorted arrays.
+// nine contiguous runs of the sorted arrays.  For a search radius r of at most
+// half a cell (r >= 0 given) a point within r of p lies, along each axis, in
+// p's cell and the neighbour on the side of p's half of the cell: 2 x 2 x 2
+// cells, four runs.
 template <class Fn>
-__device__ __forceinline__ void for_stencil(const Frag &F, const GridView &g, double px, double py, double pz, Fn &&fn) {
-    int cx, cy, cz;
-    cell_of(F, px, py, pz, cx, cy, cz);
-    int x0 = max(cx - 1, 0), x1 = min(cx + 1, F.gx - 1);
+__device__ __forceinline__ void for_stencil(const Frag &F, const GridView &g, double px, double py, double pz, Fn &&fn,
+                                            double r = -1.0) {
+    const double c = (double)F.cell;
+    const double fx = (px - (double)F.ox) / c, fy = (py - (double)F.oy) / c, fz = (pz - (double)F.oz) / c;
+    const int cx = (int)floor(fx), cy = (int)floor(fy), cz = (int)floor(fz);
+    int lx = cx - 1, ly = cy - 1, lz = cz - 1, hx = cx + 1, hy = cy + 1, hz = cz + 1;
+    if (r >= 0.0 && r <= 0.499999 * c) {
+        lx = fx - cx < 0.5 ? cx - 1 : cx; hx = lx + 1;
+        ly = fy - cy < 0.5 ? cy - 1 : cy; hy = ly + 1;
+        lz = fz - cz < 0.5 ? cz - 1 : cz; hz = lz + 1;
+    }
+    int x0 = max(lx, 0), x1 = min(hx, F.gx - 1);
     if (x0 > x1) return;
-    for (int z = max(cz - 1, 0); z <= min(cz + 1, F.gz - 1); ++z) {
-        for (int y = max(cy - 1, 0); y <= min(cy + 1, F.gy - 1); ++y) {
+    for (int z = max(lz, 0); z <= min(hz, F.gz - 1); ++z) {
+        for (int y = max(ly, 0); y <= min(hy, F.gy - 1); ++y) {
             int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
             int32_t b = g.cstart[row + x0];
             int32_t e = g.cstart[row + x1] + g.ccount[row + x1];
@@ -106,6 +117,7 @@ __global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *bl
     double px = p4.x, py = p4.y, pz = p4.z;
     // shifted sums (origin at p_i): sum d, sum d d^T
     double m = 1, s1x = 0, s1y = 0, s1z = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+    const double rn = sqrt(r2);
     for_stencil(F, g, px, py, pz, [&](int32_t k) {
         const float4 q4 = g.p[k];
         double qx = q4.x, qy = q4.y, qz = q4.z;
@@ -115,7 +127,7 @@ __global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *bl
             m += 1; s1x += dx; s1y += dy; s1z += dz;
             sxx += dx * dx; sxy += dx * dy; sxz += dx * dz; syy += dy * dy; syz += dy * dz; szz += dz * dz;
         }
-    });
+    }, rn);
     double ix = snx[s], iy = sny[s], iz = snz[s];
     double v[3];
     if (m < 3) {

@@ -38,12 +38,21 @@ __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk
             rny = T[4] * a + T[5] * bb + T[6] * c;
             rnz = T[8] * a + T[9] * bb + T[10] * c;
         }
-        int cx, cy, cz;
-        cell_of(Q, x, y, z, cx, cy, cz);
-        int x0 = max(cx - 1, 0), x1 = min(cx + 1, Q.gx - 1);
+        // cells that can hold a point within delta: 3 per axis, or 2 (p's cell and the
+        // neighbour on the side of p's half) when delta is at most half a cell
+        const double c = (double)Q.cell;
+        const double fx = (x - (double)Q.ox) / c, fy = (y - (double)Q.oy) / c, fz = (z - (double)Q.oz) / c;
+        const int cx = (int)floor(fx), cy = (int)floor(fy), cz = (int)floor(fz);
+        int lx = cx - 1, ly = cy - 1, lz = cz - 1, hx = cx + 1, hy = cy + 1, hz = cz + 1;
+        if (sqrt(delta2) <= 0.499999 * c) {
+            lx = fx - cx < 0.5 ? cx - 1 : cx; hx = lx + 1;
+            ly = fy - cy < 0.5 ? cy - 1 : cy; hy = ly + 1;
+            lz = fz - cz < 0.5 ? cz - 1 : cz; hz = lz + 1;
+        }
+        int x0 = max(lx, 0), x1 = min(hx, Q.gx - 1);
         if (x0 <= x1) {
-            for (int zz = max(cz - 1, 0); zz <= min(cz + 1, Q.gz - 1); ++zz)
-                for (int yy = max(cy - 1, 0); yy <= min(cy + 1, Q.gy - 1); ++yy) {
+            for (int zz = max(lz, 0); zz <= min(hz, Q.gz - 1); ++zz)
+                for (int yy = max(ly, 0); yy <= min(hy, Q.gy - 1); ++yy) {
                     int64_t row = Q.cell_off + ((int64_t)zz * Q.gy + yy) * Q.gx;
                     int32_t kb = cstart[row + x0], ke = cstart[row + x1] + ccount[row + x1];
                     for (int32_t k = kb; k < ke; ++k) {
