@@ -38,6 +38,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--distinct", type=int, default=64, help="distinct generated pairs, tiled to --pairs")
     ap.add_argument("--points", type=int, default=50000)
+    ap.add_argument("--recipe", type=int, default=1,
+                    help="scene recipe: 1 = indoor rooms at --points per fragment (the headline workload), "
+                         "2 = ragged loop-closure pairs (5k-80k points, 20%% negatives)")
     ap.add_argument("--baseline-pairs", type=int, default=16)
     ap.add_argument("--cpu-pairs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
@@ -63,7 +66,7 @@ def main():
     lsr.lib()
     t0 = time.time()
     distinct = max(1, min(args.distinct, args.pairs))
-    prs = synth.make_batch(1, distinct, n_points=args.points)
+    prs = synth.make_batch(args.recipe, distinct, n_points=args.points if args.recipe == 1 else None)
     log(f"generated {distinct} distinct pairs in {time.time() - t0:.1f}s")
     order = [k % distinct for k in range(args.pairs)]
     P_all = np.concatenate([prs[k].P for k in order], 1)
@@ -126,7 +129,7 @@ def main():
     if os.path.exists(tr_path):
         tr = json.load(open(tr_path))
         if tr.get("source_sha1") == hashlib.sha1(src).hexdigest() and tr.get("pairs") == npairs \
-                and tr.get("points") == args.points:
+                and tr.get("points") == args.points and tr.get("recipe", 1) == args.recipe:
             traffic = tr.get("bytes_per_launch")
     log(f"screen kernel {scr:.3f} ms/launch -> {achieved:.1f} TFLOP/s algorithmic")
     log("stages (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in stage_ms.items()))
@@ -196,10 +199,12 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16+f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"indoor-room pairs, {args.points}/{args.points} pts per fragment, "
-                               f"batch of {npairs} ({distinct} distinct, tiled), one graph replay per step",
-                   "pairs": npairs, "points_per_fragment": args.points, "precision": "bf16 screen + fp32 re-rank",
-                   "parallelism": "single GPU"},
+        "config": {"workload": (f"indoor-room pairs, {args.points}/{args.points} pts per fragment, "
+                                if args.recipe == 1 else "ragged loop-closure pairs, 5k-80k pts per fragment, "
+                                                         "20% negatives, ")
+                               + f"batch of {npairs} ({distinct} distinct, tiled), one graph replay per step",
+                   "pairs": npairs, "points_per_fragment": args.points if args.recipe == 1 else "5k-80k",
+                   "precision": "bf16 screen + fp32 re-rank", "parallelism": "single GPU"},
         "plain_fp32_pairs_per_s": None if base is None else round(base, 3),
         "speedup_vs_plain_fp32": None if base is None else round(value / base, 3),
         "roofline": {"bound": "mfma", "kernel": "k_screen", "achieved": round(achieved, 2),
