@@ -244,7 +244,12 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
                                                     int32_t *lst_cnt) {
     static_assert(SW * SQB * 16 == 256 && PAD_ROWS % (CH * 16) == 0, "screen shape");
     constexpr int CROWS = CH * 16;                               // rows per LDS chunk
-    __shared__ __align__(16) uint16_t lds[2][CROWS * PK];
+    constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk (1024)
+    // two separate arrays, not one indexed by chunk parity: the compiler then
+    // sees that the copy into one buffer cannot alias reads of the other and
+    // does not wait for it before those reads
+    __shared__ __align__(16) uint4 ldsA[U4];
+    __shared__ __align__(16) uint4 ldsB[U4];
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
@@ -282,14 +287,25 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     for (int k = 0; k < SQB; ++k) { v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
 
     const int nch = (Fc.n + CROWS - 1) / CROWS;
-    constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk (1024)
-    constexpr int PER = U4 / (SW * 64);                         // per thread (4)
+    constexpr int PER = U4 / (SW * 64);                         // 16-byte copies per thread per chunk
     const uint4 *src = (const uint4 *)(pk + Fc.pk_off * PK);
-    uint4 r[PER];
+    // Chunks go from global memory straight into LDS (global_load_lds_dwordx4:
+    // lane i of a wave's copy fills the 16 bytes at base + 16 i), with no trip
+    // through registers.  Copy u of wave wv fills LDS positions
+    // [u SW 64 + 64 wv, + 64); position p holds chunk element lds_slot(p), the
+    // swizzle being its own inverse within a row.
+    auto stage = [&](uint4 *dst, const uint4 *from) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) r[u] = nch > 0 ? src[threadIdx.x + u * SW * 64] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
+        for (int u = 0; u < PER; ++u) {
+            const int base = u * SW * 64 + wv * 64;
+            __builtin_amdgcn_global_load_lds((const void *)(from + lds_slot(base + lane)),
+                                             (__attribute__((address_space(3))) void *)(dst + base), 16, 0, 0);
+        }
+    };
+    // vmcnt(0) with the other counters left alone (gfx9 s_waitcnt encoding)
+    auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
+    if (nch > 0) stage(ldsA, src);
+    wait_copies();
     __syncthreads();
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     // Software pipeline: the MFMAs of tile t are issued before the epilogue of
@@ -297,16 +313,31 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     f32x4 prev[SQB];
     int prev_tile = -1;
     auto epilogue = [&](const f32x4 *accs, int tile) {
+        if (!COLLECT) {
+            // v2 <= v1 always, so max(v2, min(v1, tm)) is the median of the three.
+            // A new best tile is rare once a few hundred tiles have passed, so
+            // the best tile index is updated behind a wave-uniform branch.
+            bool up[SQB];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) {
+                const f32x4 acc = accs[k];
+                const float tm = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
+                v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);
+                up[k] = tm > v1[k];
+                any |= up[k];
+                v1[k] = __builtin_fmaxf(v1[k], tm);
+            }
+            if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+                for (int k = 0; k < SQB; ++k) c1[k] = up[k] ? tile : c1[k];
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < SQB; ++k) {
             const f32x4 acc = accs[k];
-            if (!COLLECT) {
-                // v2 <= v1 always, so max(v2, min(v1, tm)) is the median of the three
-                float tm = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
-                v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);
-                c1[k] = tm > v1[k] ? tile : c1[k];
-                v1[k] = __builtin_fmaxf(v1[k], tm);
-            } else {
+            {
                 bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
                 if (hit) {                                 // rare: near-ties of uncertified rows
                     int64_t slot = lst_base(Fq, b.frag) + qw + 16 * k + col;
@@ -320,14 +351,9 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             }
         }
     };
-    for (int ch = 0; ch < nch; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nch) {
-            const uint4 *nx = src + (int64_t)(ch + 1) * U4;
-#pragma unroll
-            for (int u = 0; u < PER; ++u) r[u] = nx[threadIdx.x + u * SW * 64];
-        }
-        const uint4 *L = (const uint4 *)lds[buf];
+    // one chunk: start copying the next chunk into D, sweep the tiles of L
+    auto chunk = [&](const uint4 *L, uint4 *D, int ch) {
+        if (ch + 1 < nch) stage(D, src + (int64_t)(ch + 1) * U4);
         // operands of tile t + 1 are read before tile t's MFMAs issue, so the
         // LDS latency hides behind a whole tile of matrix work
         uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
@@ -352,11 +378,12 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
             for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
             prev_tile = ch * CH + t;
         }
-        if (ch + 1 < nch) {
-#pragma unroll
-            for (int u = 0; u < PER; ++u) ((uint4 *)lds[buf ^ 1])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
-        }
+        wait_copies();
         __syncthreads();
+    };
+    for (int ch = 0; ch < nch; ch += 2) {
+        chunk(ldsA, ldsB, ch);
+        if (ch + 1 < nch) chunk(ldsB, ldsA, ch + 1);
     }
     if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
