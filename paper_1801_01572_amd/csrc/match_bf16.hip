@@ -413,7 +413,9 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
                                                       int32_t *lst_cnt) {
     static_assert(SW * QB * 32 == 256 && PAD_ROWS % (CH * 32) == 0, "screen shape");
     constexpr int CROWS = CH * 32;                               // rows per LDS chunk
-    __shared__ __align__(16) uint16_t lds[2][CROWS * PK];
+    constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk
+    __shared__ __align__(16) uint4 ldsA[U4];                    // two arrays: see k_screen
+    __shared__ __align__(16) uint4 ldsB[U4];
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
@@ -453,14 +455,20 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
     for (int k = 0; k < QB; ++k) { v1[k] = -INFINITY; v2[k] = -INFINITY; c1[k] = -1; }
 
     const int nch = (Fc.n + CROWS - 1) / CROWS;
-    constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk
     constexpr int PER = U4 / (SW * 64);
     const uint4 *src = (const uint4 *)(pk + Fc.pk_off * PK);
-    uint4 r[PER];
+    // chunks copied straight into LDS, as in k_screen
+    auto stage = [&](uint4 *dst, const uint4 *from) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) r[u] = nch > 0 ? src[threadIdx.x + u * SW * 64] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) ((uint4 *)lds[0])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
+        for (int u = 0; u < PER; ++u) {
+            const int base = u * SW * 64 + wv * 64;
+            __builtin_amdgcn_global_load_lds((const void *)(from + lds_slot(base + lane)),
+                                             (__attribute__((address_space(3))) void *)(dst + base), 16, 0, 0);
+        }
+    };
+    auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };   // vmcnt(0)
+    if (nch > 0) stage(ldsA, src);
+    wait_copies();
     __syncthreads();
     f32x16 zero;
 #pragma unroll
@@ -468,6 +476,8 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
     f32x16 prev[QB];
     int prev_tile = -1;
     auto epilogue = [&](const f32x16 *accs, int tile) {
+        bool up[QB];
+        bool any = false;
 #pragma unroll
         for (int k = 0; k < QB; ++k) {
             const f32x16 a = accs[k];
@@ -478,7 +488,8 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
             const float tm = __builtin_fmaxf(__builtin_fmaxf(m0, m1), __builtin_fmaxf(m2, m3));
             if (!COLLECT) {
                 v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);      // v2 <= v1: max(v2, min(v1, tm))
-                c1[k] = tm > v1[k] ? tile : c1[k];
+                up[k] = tm > v1[k];
+                any |= up[k];
                 v1[k] = __builtin_fmaxf(v1[k], tm);
             } else if (tm >= th[k]) {                                  // rare: near-ties of uncertified rows
                 int64_t slot = lst_base(Fq, b.frag) + qw + 32 * k + col;
@@ -490,15 +501,13 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
                     }
             }
         }
-    };
-    for (int ch = 0; ch < nch; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nch) {
-            const uint4 *nx = src + (int64_t)(ch + 1) * U4;
+        if (!COLLECT && __builtin_amdgcn_ballot_w64(any)) {      // a new best tile: rare
 #pragma unroll
-            for (int u = 0; u < PER; ++u) r[u] = nx[threadIdx.x + u * SW * 64];
+            for (int k = 0; k < QB; ++k) c1[k] = up[k] ? tile : c1[k];
         }
-        const uint4 *L = (const uint4 *)lds[buf];
+    };
+    auto chunk = [&](const uint4 *L, uint4 *D, int ch) {
+        if (ch + 1 < nch) stage(D, src + (int64_t)(ch + 1) * U4);
 #pragma unroll 2
         for (int t = 0; t < CH; ++t) {
             const uint4 *rowp = L + (t * 32 + col) * 8;
@@ -520,11 +529,12 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
             for (int k = 0; k < QB; ++k) prev[k] = accs[k];
             prev_tile = ch * CH + t;
         }
-        if (ch + 1 < nch) {
-#pragma unroll
-            for (int u = 0; u < PER; ++u) ((uint4 *)lds[buf ^ 1])[lds_slot(threadIdx.x + u * SW * 64)] = r[u];
-        }
+        wait_copies();
         __syncthreads();
+    };
+    for (int ch = 0; ch < nch; ch += 2) {
+        chunk(ldsA, ldsB, ch);
+        if (ch + 1 < nch) chunk(ldsB, ldsA, ch + 1);
     }
     if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
