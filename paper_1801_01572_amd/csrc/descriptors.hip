@@ -410,73 +410,153 @@ hipError_t launch_spfh_out(const GridBufs &g, const DescBufs &d, float *out, int
 
 // ---------------------------------------------------------------- FPFH
 
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// The neighbour sum of FPFH_i is a sparse product: sum_j w_ij C_j with
+// w_ij = scale_j / |p_j - p_i| over the r_f neighbours j and C_j the 33
+// integer counts of SPFH_j (SPFH_j = scale_j C_j).  A wavefront takes 16
+// consecutive sorted points at a time.  Sorted order is cell order with x
+// fastest, so the group's points that share a grid row (cy, cz) are
+// contiguous, ordered by cx, and all their neighbours lie in nine x-runs:
+// rows (cy + dy, cz + dz), cells [first cx - 1, last cx + 1].  Each step
+// covers 4 candidates of a run: lane (i, k) = (l % 16, l / 16) forms w for
+// point i and candidate j = c0 + k (0 unless j is within r_f of p_i, the
+// same FP64 test as the per-point stencil) and loads the counts of j for bins
+// i, i + 16, i + 32; three 16x16x4 f32 MFMAs add W (16 x 4) times C (4 x 48)
+// into the group's sums.  A group spanning several rows takes one pass per
+// row, each with W masked to that row's points.  Only the float32 summation
+// order differs from a per-point loop.
 __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, GridView g, const int32_t *sorig,
                                               const uint4 *spfh, const int32_t *knb, double r2, float *Fout,
                                               int32_t *valid, PairState *ps) {
+    __shared__ float red[4][16][49];                  // per wavefront: 16 points x 48 bins (+1 pad)
+    __shared__ int cnt[4];
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
-    int i = b.start + threadIdx.x;
-    bool ok = false;
-    if (i < F.n) {
-        int64_t s = F.off + i;
-        const float4 p4 = g.p[s];
-    const double px = p4.x, py = p4.y, pz = p4.z;
-        float acc[FD];
-#pragma unroll
-        for (int c = 0; c < FD; ++c) acc[c] = 0.f;
-        for_stencil(F, g, px, py, pz, [&](int32_t j) {
-            const float4 q4 = g.p[j];
-            double d2 = pdist2(px, py, pz, (double)q4.x, (double)q4.y, (double)q4.z);
-            if (!(d2 > 0.0 && d2 <= r2)) return;
-            const uint4 *sj = spfh + (int64_t)j * SPR;
-            uint32_t wd[4 * SPR];
-#pragma unroll
-            for (int q = 0; q < SPR; ++q) {
-                const uint4 v = sj[q];
-                wd[4 * q] = v.x; wd[4 * q + 1] = v.y; wd[4 * q + 2] = v.z; wd[4 * q + 3] = v.w;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int pi = lane & 15, kk = lane >> 4;
+    const double c = (double)F.cell;
+    const f32x4v zero = {0.f, 0.f, 0.f, 0.f};
+    int nok = 0;                                      // valid descriptors written by this lane
+    for (int gq = 0; gq < 4; ++gq) {
+        const int base = b.start + wv * 64 + gq * 16;
+        if (base >= F.n) break;                       // uniform across the wavefront
+        const int i = base + pi;
+        const bool live = i < F.n;
+        const int64_t s = F.off + i;
+        const float4 p4 = live ? g.p[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const double px = p4.x, py = p4.y, pz = p4.z;
+        // the point's cell, as the per-point stencil computes it
+        const int cx = (int)floor((px - (double)F.ox) / c), cy = (int)floor((py - (double)F.oy) / c),
+                  cz = (int)floor((pz - (double)F.oz) / c);
+        const int x0i = max(cx - 1, 0), x1i = min(cx + 1, F.gx - 1);   // the point's own x-run
+        f32x4v acc0 = zero, acc1 = zero, acc2 = zero;
+        uint64_t pend = __ballot(live && kk == 0);
+        while (pend) {
+            const int lead = __builtin_ctzll(pend);
+            const int ry = __builtin_amdgcn_readlane(cy, lead), rz = __builtin_amdgcn_readlane(cz, lead);
+            const bool inrow = live && ((pend >> pi) & 1) && cy == ry && cz == rz;
+            const uint64_t rowm = __ballot(inrow && kk == 0);
+            pend &= ~rowm;
+            // union of the row's points' x-runs (a point with an empty run adds nothing)
+            const bool use = inrow && x0i <= x1i;
+            int x0 = use ? x0i : INT_MAX, x1 = use ? x1i : INT_MIN;
+            for (int o = 1; o < 16; o <<= 1) {
+                x0 = min(x0, __shfl_xor(x0, o, 64));
+                x1 = max(x1, __shfl_xor(x1, o, 64));
             }
-            // SPFH_j / |p_j - p_i| = count * (scale_j / |p_j - p_i|)
-            const float w = (float)rsqrt_nr(d2) * __uint_as_float(wd[4 * SPR - 1]);
-#pragma unroll
-            for (int c = 0; c < FD; ++c)
-                acc[c] = fmaf((float)((wd[c >> 1] >> (16 * (c & 1))) & 0xffffu), w, acc[c]);
-        });
-        int k = knb[s];
-        float ik = k > 0 ? 1.0f / (float)k : 0.0f;
-        const uint32_t *si = (const uint32_t *)(spfh + s * SPR);
-        const float sci = __uint_as_float(si[4 * SPR - 1]);
-        float f[FD];
-#pragma unroll
-        for (int c = 0; c < FD; ++c) f[c] = (float)((si[c >> 1] >> (16 * (c & 1))) & 0xffffu) * sci + acc[c] * ik;
-        ok = k >= 1;
-#pragma unroll
-        for (int blk3 = 0; blk3 < 3; ++blk3) {
-            float sum = 0.f;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) sum += f[NB * blk3 + c];
-            if (sum > 0.f) {
-                float inv = 1.0f / sum;
-#pragma unroll
-                for (int c = 0; c < NB; ++c) f[NB * blk3 + c] *= inv;
-            } else {
-                ok = false;
+            x0 = __builtin_amdgcn_readfirstlane(x0);
+            x1 = __builtin_amdgcn_readfirstlane(x1);
+            if (x0 > x1) continue;
+            for (int z = max(rz - 1, 0); z <= min(rz + 1, F.gz - 1); ++z) {
+                for (int y = max(ry - 1, 0); y <= min(ry + 1, F.gy - 1); ++y) {
+                    const int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
+                    const int32_t rb = g.cstart[row + x0], re = g.cstart[row + x1] + g.ccount[row + x1];
+                    // Branch-free steps, two per iteration so that both steps' loads
+                    // are in flight together: a lane past the run's end reads the run's
+                    // last candidate (always in bounds) and adds zero.
+                    struct Cand { float4 q; float sc; uint32_t u0, u1, u2; bool in; };
+                    auto fetch = [&](int32_t c0) {
+                        const int32_t j = c0 + kk;
+                        const int64_t jj = min(j, re - 1);
+                        const uint16_t *cj = (const uint16_t *)(spfh + jj * SPR);
+                        Cand r;
+                        r.in = j < re;
+                        r.q = g.p[jj];
+                        r.sc = ((const float *)(spfh + jj * SPR))[4 * SPR - 1];
+                        r.u0 = cj[pi];
+                        r.u1 = cj[pi + 16];
+                        r.u2 = cj[pi == 0 ? 32 : 33];
+                        return r;
+                    };
+                    auto step = [&](const Cand &cd) {
+                        const double d2 = pdist2(px, py, pz, (double)cd.q.x, (double)cd.q.y, (double)cd.q.z);
+                        const bool hit = cd.in && inrow && d2 > 0.0 && d2 <= r2;
+                        const float wv = (float)rsqrt_nr(hit ? d2 : 1.0) * cd.sc;
+                        const float w = hit ? wv : 0.f;
+                        const float b0 = cd.in ? (float)cd.u0 : 0.f, b1 = cd.in ? (float)cd.u1 : 0.f;
+                        const float b2 = cd.in && pi == 0 ? (float)cd.u2 : 0.f;
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1, acc1, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b2, acc2, 0, 0, 0);
+                    };
+                    for (int32_t c0 = rb; c0 < re; c0 += 8) {
+                        const Cand A = fetch(c0), B = fetch(c0 + 4);
+                        step(A);
+                        if (c0 + 4 < re) step(B);                 // uniform
+                    }
+                }
             }
         }
-        int64_t o = F.off + sorig[s];
-        float *dst = Fout + o * FD;
+        // lane (i, k) holds the sums of points 4 k + r, bins i + 16 m (r < 4, m < 3)
 #pragma unroll
-        for (int c = 0; c < FD; ++c) dst[c] = ok ? f[c] : 0.f;
-        valid[o] = ok ? 1 : 0;
+        for (int r = 0; r < 4; ++r) {
+            red[wv][4 * kk + r][pi] = acc0[r];
+            red[wv][4 * kk + r][pi + 16] = acc1[r];
+            red[wv][4 * kk + r][pi + 32] = acc2[r];
+        }
+        wave_sync_lds();
+        if (kk == 0 && live) {
+            const float *acc = red[wv][pi];
+            const int k = knb[s];
+            const float ik = k > 0 ? 1.0f / (float)k : 0.0f;
+            const uint32_t *si = (const uint32_t *)(spfh + s * SPR);
+            const float sci = __uint_as_float(si[4 * SPR - 1]);
+            float f[FD];
+#pragma unroll
+            for (int cc = 0; cc < FD; ++cc)
+                f[cc] = (float)((si[cc >> 1] >> (16 * (cc & 1))) & 0xffffu) * sci + acc[cc] * ik;
+            bool ok = k >= 1;
+#pragma unroll
+            for (int blk3 = 0; blk3 < 3; ++blk3) {
+                float sum = 0.f;
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc) sum += f[NB * blk3 + cc];
+                if (sum > 0.f) {
+                    const float inv = 1.0f / sum;
+#pragma unroll
+                    for (int cc = 0; cc < NB; ++cc) f[NB * blk3 + cc] *= inv;
+                } else {
+                    ok = false;
+                }
+            }
+            const int64_t o = F.off + sorig[s];
+            float *dst = Fout + o * FD;
+#pragma unroll
+            for (int cc = 0; cc < FD; ++cc) dst[cc] = ok ? f[cc] : 0.f;
+            valid[o] = ok ? 1 : 0;
+            nok += ok ? 1 : 0;
+        }
+        wave_sync_lds();                              // red is rewritten by the next group
     }
     // per-pair count of valid descriptors
-    unsigned long long bal = __ballot(ok);
-    __shared__ int cnt[4];
-    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+    int t = nok;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) cnt[wv] = t;
     __syncthreads();
     if (threadIdx.x == 0 && ps && F.pair >= 0) {
-        int t = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += cnt[w];
-        if (t) atomicAdd(&ps[F.pair].n_valid[b.frag & 1], (unsigned long long)t);
+        const int tot = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        if (tot) atomicAdd(&ps[F.pair].n_valid[b.frag & 1], (unsigned long long)tot);
     }
 }
 
