@@ -472,8 +472,8 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
                 for (int y = max(ry - 1, 0); y <= min(ry + 1, F.gy - 1); ++y) {
                     const int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
                     const int32_t rb = g.cstart[row + x0], re = g.cstart[row + x1] + g.ccount[row + x1];
-                    // Branch-free steps, two per iteration so that both steps' loads
-                    // are in flight together: a lane past the run's end reads the run's
+                    // Branch-free steps, four per iteration so that their loads are
+                    // in flight together: a lane past the run's end reads the run's
                     // last candidate (always in bounds) and adds zero.
                     struct Cand { float4 q; float sc; uint32_t u0, u1, u2; bool in; };
                     auto fetch = [&](int32_t c0) {
@@ -492,7 +492,11 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
                     auto step = [&](const Cand &cd) {
                         const double d2 = pdist2(px, py, pz, (double)cd.q.x, (double)cd.q.y, (double)cd.q.z);
                         const bool hit = cd.in && inrow && d2 > 0.0 && d2 <= r2;
-                        const float wv = (float)rsqrt_nr(hit ? d2 : 1.0) * cd.sc;
+                        // the weight in float32 (v_rsq_f32, within 1 ulp): only the
+                        // neighbour decision above needs FP64.  A distance below the
+                        // smallest normal float (coincident-looking points) is clamped
+                        // there, keeping the weight finite; it dominates the sum either way.
+                        const float wv = __builtin_amdgcn_rsqf(fmaxf((float)(hit ? d2 : 1.0), 1.17549435e-38f)) * cd.sc;
                         const float w = hit ? wv : 0.f;
                         const float b0 = cd.in ? (float)cd.u0 : 0.f, b1 = cd.in ? (float)cd.u1 : 0.f;
                         const float b2 = cd.in && pi == 0 ? (float)cd.u2 : 0.f;
@@ -500,10 +504,12 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
                         acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1, acc1, 0, 0, 0);
                         acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b2, acc2, 0, 0, 0);
                     };
-                    for (int32_t c0 = rb; c0 < re; c0 += 8) {
-                        const Cand A = fetch(c0), B = fetch(c0 + 4);
+                    for (int32_t c0 = rb; c0 < re; c0 += 16) {
+                        const Cand A = fetch(c0), B = fetch(c0 + 4), C = fetch(c0 + 8), D = fetch(c0 + 12);
                         step(A);
                         if (c0 + 4 < re) step(B);                 // uniform
+                        if (c0 + 8 < re) step(C);
+                        if (c0 + 12 < re) step(D);
                     }
                 }
             }
