@@ -481,11 +481,11 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
 #pragma unroll
         for (int k = 0; k < QB; ++k) {
             const f32x16 a = accs[k];
-            float m0 = __builtin_fmaxf(__builtin_fmaxf(a[0], a[1]), __builtin_fmaxf(a[2], a[3]));
-            float m1 = __builtin_fmaxf(__builtin_fmaxf(a[4], a[5]), __builtin_fmaxf(a[6], a[7]));
-            float m2 = __builtin_fmaxf(__builtin_fmaxf(a[8], a[9]), __builtin_fmaxf(a[10], a[11]));
-            float m3 = __builtin_fmaxf(__builtin_fmaxf(a[12], a[13]), __builtin_fmaxf(a[14], a[15]));
-            const float tm = __builtin_fmaxf(__builtin_fmaxf(m0, m1), __builtin_fmaxf(m2, m3));
+            // a chain of three-way maxima: 8 v_max3 / v_max for 16 scores
+            float tm = __builtin_fmaxf(__builtin_fmaxf(a[0], a[1]), a[2]);
+#pragma unroll
+            for (int e = 3; e < 15; e += 2) tm = __builtin_fmaxf(__builtin_fmaxf(tm, a[e]), a[e + 1]);
+            tm = __builtin_fmaxf(tm, a[15]);
             if (!COLLECT) {
                 v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);      // v2 <= v1: max(v2, min(v1, tm))
                 up[k] = tm > v1[k];
