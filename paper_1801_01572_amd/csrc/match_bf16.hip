@@ -232,13 +232,26 @@ __device__ __forceinline__ int lds_slot(int idx) {            // uint4 index of 
     return (idx & ~7) | ((idx & 7) ^ lds_swz(idx >> 3));
 }
 
+// XCD-aware block order for the second screen.  The device hands workgroups to
+// its 8 XCDs round-robin (workgroup w runs on XCD w % 8), and only the first few
+// blocks of each fragment have uncertified rows, so in table order one
+// fragment's working blocks land on different XCDs and each XCD streams the
+// partner's rows from HBM.  Workgroup w takes table entry (w % 8) per + w / 8
+// instead: consecutive entries share an XCD, and its L2 serves the partner's rows
+// to all of them.  The grid has 8 per workgroups, per = ceil(nblk / 8).
+__device__ __forceinline__ int xcd_block(int nblk) {
+    const int per = (nblk + 7) >> 3;
+    return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+}
+static int xcd_grid(int nblk) { return 8 * ((nblk + 7) / 8); }
+
 // COLLECT = false: every row of the fragment is a query; write the best tile
 // and second-best tile maximum per lane group.
 // COLLECT = true: the queries are the fragment's uncertified rows (slots
 // [start, start + 256) of its list); append every candidate whose score
 // reaches the row's threshold to the row's candidate list.
 template <bool COLLECT, int SW, int SQB, int CH>
-__global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, const uint16_t *pk,
+__global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk,
                                                     int32_t *c1_out, float *v2_out, float *v1_out, const int32_t *fb_row,
                                                     const int32_t *fb_cnt, const float *thr, int32_t *lst,
                                                     int32_t *lst_cnt) {
@@ -250,7 +263,9 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     // does not wait for it before those reads
     __shared__ __align__(16) uint4 ldsA[U4];
     __shared__ __align__(16) uint4 ldsB[U4];
-    const Blk b = blk[blockIdx.x];
+    const int bi = COLLECT ? xcd_block(nblk) : (int)blockIdx.x;
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
     int nq = Fq.n;
@@ -407,7 +422,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 // per four MFMAs (against 6 per two with 16x16 tiles); the re-rank then
 // checks 32 rows per query.
 template <bool COLLECT, int SW, int QB, int CH>
-__global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Blk *blk, const uint16_t *pk,
+__global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk,
                                                       int32_t *c1_out, float *v2_out, float *v1_out, const int32_t *fb_row,
                                                       const int32_t *fb_cnt, const float *thr, int32_t *lst,
                                                       int32_t *lst_cnt) {
@@ -416,7 +431,9 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
     constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk
     __shared__ __align__(16) uint4 ldsA[U4];                    // two arrays: see k_screen
     __shared__ __align__(16) uint4 ldsB[U4];
-    const Blk b = blk[blockIdx.x];
+    const int bi = COLLECT ? xcd_block(nblk) : (int)blockIdx.x;
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
     int nq = Fq.n;
@@ -735,23 +752,23 @@ template <bool COLLECT, int T, int SW, int SQB, int CH>
 static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScratch &S, hipStream_t s) {
     if constexpr (T == 16) {
         if (COLLECT)
-            hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr, nullptr,
+            hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, nullptr, nullptr, nullptr,
                                (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
                                S.lst_cnt);
         else
             hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
                                nullptr, nullptr);
     } else {
         if (COLLECT)
-            hipLaunchKernelGGL((k_screen32<true, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, nullptr, nullptr, nullptr,
+            hipLaunchKernelGGL((k_screen32<true, SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, nullptr, nullptr, nullptr,
                                (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
                                S.lst_cnt);
         else
             hipLaunchKernelGGL((k_screen32<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
                                nullptr, nullptr);
     }
 }
