@@ -277,3 +277,45 @@ def test_spfh_fpfh_dense_cluster(L, orc):
     assert ok.mean() > 0.95
     rel = np.linalg.norm(Fg[ok] - F[ok], axis=1) / np.linalg.norm(F[ok], axis=1)
     assert rel.max() <= DESC_RTOL
+
+
+def _edge_clouds():
+    """Clouds that stress the row-group FPFH: tiny sizes around the 16-point group,
+    a z-line (every point its own grid row), a diagonal line (groups span cells and
+    rows), and a cloud inside one cell."""
+    rng = np.random.default_rng(11)
+    out = []
+    for n in (1, 2, 3, 15, 16, 17, 33, 100):
+        out.append((f"box n={n}", rng.uniform(0.0, 0.06, size=(3, n))))
+    t = np.arange(400) * 0.004
+    out.append(("z-line", np.vstack([np.full_like(t, 0.3), np.full_like(t, 0.2), t])))
+    out.append(("diagonal", np.vstack([t, t * 0.7, t * 0.4]) + rng.normal(scale=1e-4, size=(3, t.size))))
+    out.append(("one cell", rng.uniform(0.0, 0.02, size=(3, 300))))
+    clouds = []
+    for name, xyz in out:
+        n = rng.normal(size=(3, xyz.shape[1]))
+        n /= np.linalg.norm(n, axis=0)
+        clouds.append((name, np.vstack([xyz, n]).astype(np.float32)))
+    return clouds
+
+
+@pytest.mark.parametrize("case", range(11))
+def test_fpfh_edge_shapes(L, orc, case):
+    name, cloud = _edge_clouds()[case]
+    print(f"fpfh edge {name} n={cloud.shape[1]}", flush=True)
+    # the clouds' own unit normals (lines and blobs have no well-conditioned PCA normal),
+    # so only decisions within MARGIN of a bin edge are exempt
+    nrm = np.ascontiguousarray(cloud[3:].T.astype(np.float64))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    ones = np.ones(cloud.shape[1])
+    F, v, exempt = desc_exempt(orc, cloud, nrm, ones, ones, 0.05)
+    Fg, vg = L.stage_fpfh(dev(cloud[:3]), dev(nrm), 0.05)
+    Fg, vg = Fg.cpu().numpy().astype(np.float64), vg.cpu().numpy()
+    assert np.array_equal(vg, v)
+    ok = (v == 1) & ~exempt
+    assert ok.sum() >= 0.9 * v.sum()
+    if ok.any():
+        rel = np.linalg.norm(Fg[ok] - F[ok], axis=1) / np.linalg.norm(F[ok], axis=1)
+        print(f"  valid {int(v.sum())} compared {int(ok.sum())} max rel {rel.max():.2e}", flush=True)
+        assert rel.max() <= DESC_RTOL
+    assert np.all(Fg[v == 0] == 0)
