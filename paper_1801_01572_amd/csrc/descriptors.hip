@@ -263,39 +263,37 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Lanes walk their stencils in lockstep (lanes of one cell read the same
-// candidates at the same time); every neighbour found is parked as
-// (owner lane, j) in a wavefront ring, and whenever 64 are parked each lane
-// takes one and bins that pair.  The expensive pair geometry thus runs on
-// full wavefronts instead of whenever any lane has a neighbour.  Bins are
-// counted with integer LDS atomics into the owner's histogram (order
-// independent); kp is the sum of the alpha block (each counted pair adds one
+// A wavefront's 64 points are taken 16 at a time, as in the FPFH kernel: the
+// group's points that share a grid row find all their neighbours in nine
+// x-runs, and each step tests 4 candidates against the 16 points (lane
+// (i, k) = (l % 16, l / 16) tests point i against candidate c0 + k, with the
+// same FP64 distance as the per-point stencil).  Every lane runs every step,
+// so the loop is uniform and the ring of found pairs (owner, j) keeps its
+// cursors in scalar registers.  Whenever 64 pairs are parked each lane bins
+// one (FP64 Darboux frame, hardware rsq/rcp seeds with two Newton steps,
+// theta by pseudo-angle comparisons against edges precomputed on the host);
+// bins are counted with integer LDS atomics into the owner's histogram (order
+// independent).  kp is the sum of the alpha block (each counted pair adds one
 // to every block).
 __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, GridView g, const double *nxa,
                                                  const double *nya, const double *nza, double r2, ThetaEdges te,
                                                  uint4 *spfh, int32_t *knb) {
     __shared__ uint32_t hist[SPFH_T * FD];
     __shared__ int2 ring_all[SPFH_T / 64][SPFH_RING];
-    __shared__ uint32_t cur_all[SPFH_T / 64][2];      // ring head, tail of each wavefront
     uint32_t *h = hist + threadIdx.x * FD;
 #pragma unroll
     for (int c = 0; c < FD; ++c) h[c] = 0;
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int pi = lane & 15, kk = lane >> 4;
     int2 *ring = ring_all[wv];
     uint32_t *hw = hist + wv * 64 * FD;               // this wavefront's 64 histograms
-    const int64_t s0 = F.off + b.start + wv * 64;      // sorted index of lane 0's point
+    const int64_t s0 = F.off + b.start + wv * 64;      // sorted index of the wavefront's first point
     const int i = b.start + threadIdx.x;
     const bool live = i < F.n;
     const int64_t s = F.off + i;
-    // The ring cursors live in LDS: lanes leave the stencil's x-runs at
-    // different times, so register copies would go stale in lanes that sat
-    // out some iterations.  Every active lane reads them; the first active
-    // lane writes them back.
-    uint32_t *cur = cur_all[wv];
-    if (lane == 0) { cur[0] = 0; cur[1] = 0; }
-    // bin the pair parked in slot e (owner lane o, neighbour j)
+    // bin the pair parked in slot e (owner o = point index in the wavefront, neighbour j)
     auto bin_pair = [&](int2 e) {
         const int64_t so = s0 + e.x;
         const float4 o4 = g.p[so];
@@ -309,42 +307,82 @@ __global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *bl
         }
     };
     wave_sync_lds();
-    int k = 0;
-    if (live) {
-        const float4 p4 = g.p[s];
+    const double c = (double)F.cell;
+    uint32_t head = 0, tail = 0;                      // ring cursors (uniform)
+    int kmine = 0;                                    // neighbour count of this lane's own point
+    for (int gq = 0; gq < 4; ++gq) {
+        const int gbase = b.start + wv * 64 + gq * 16;
+        if (gbase >= F.n) break;                      // uniform
+        const int ip = gbase + pi;
+        const bool pl = ip < F.n;
+        const float4 p4 = pl ? g.p[F.off + ip] : make_float4(0.f, 0.f, 0.f, 0.f);
         const double px = p4.x, py = p4.y, pz = p4.z;
-        for_stencil(F, g, px, py, pz, [&](int32_t j) {
-            const float4 q4 = g.p[j];
-            double dx = (double)q4.x - px, dy = (double)q4.y - py, dz = (double)q4.z - pz;
-            double d2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-            const bool hit = d2 > 0.0 && d2 <= r2;
-            k += hit ? 1 : 0;
-            const uint64_t m = __ballot(hit);
-            const uint64_t act = __ballot(true);
-            const uint32_t me = lanes_below64(act);
-            wave_sync_lds();
-            uint32_t head = cur[0], tail = cur[1];
-            if (hit) ring[(tail + lanes_below64(m)) & (SPFH_RING - 1)] = make_int2(lane, j);
-            tail += __popcll(m);
-            if (tail - head >= 64) {                   // the active lanes each bin one parked pair
-                wave_sync_lds();
-                bin_pair(ring[(head + me) & (SPFH_RING - 1)]);
-                head += __popcll(act);
+        const int cx = (int)floor((px - (double)F.ox) / c), cy = (int)floor((py - (double)F.oy) / c),
+                  cz = (int)floor((pz - (double)F.oz) / c);
+        const int x0i = max(cx - 1, 0), x1i = min(cx + 1, F.gx - 1);
+        int kc = 0;
+        uint64_t pend = __ballot(pl && kk == 0);
+        while (pend) {
+            const int lead = __builtin_ctzll(pend);
+            const int ry = __builtin_amdgcn_readlane(cy, lead), rz = __builtin_amdgcn_readlane(cz, lead);
+            const bool inrow = pl && ((pend >> pi) & 1) && cy == ry && cz == rz;
+            pend &= ~__ballot(inrow && kk == 0);
+            const bool use = inrow && x0i <= x1i;
+            int x0 = use ? x0i : INT_MAX, x1 = use ? x1i : INT_MIN;
+            for (int o = 1; o < 16; o <<= 1) {
+                x0 = min(x0, __shfl_xor(x0, o, 64));
+                x1 = max(x1, __shfl_xor(x1, o, 64));
             }
-            wave_sync_lds();
-            if (me == 0) { cur[0] = head; cur[1] = tail; }
-        });
+            x0 = __builtin_amdgcn_readfirstlane(x0);
+            x1 = __builtin_amdgcn_readfirstlane(x1);
+            if (x0 > x1) continue;
+            for (int z = max(rz - 1, 0); z <= min(rz + 1, F.gz - 1); ++z) {
+                for (int y = max(ry - 1, 0); y <= min(ry + 1, F.gy - 1); ++y) {
+                    const int64_t row = F.cell_off + ((int64_t)z * F.gy + y) * F.gx;
+                    const int32_t rb = g.cstart[row + x0], re = g.cstart[row + x1] + g.ccount[row + x1];
+                    // four steps per iteration, their candidate loads issued together
+                    // (a lane past the run's end reads the run's last candidate)
+                    auto test = [&](int32_t j, const float4 &q4) {
+                        const double d2 = pdist2(px, py, pz, (double)q4.x, (double)q4.y, (double)q4.z);
+                        const bool hit = j < re && inrow && d2 > 0.0 && d2 <= r2;
+                        kc += hit ? 1 : 0;
+                        const uint64_t m = __ballot(hit);
+                        if (hit) ring[(tail + lanes_below64(m)) & (SPFH_RING - 1)] = make_int2(gq * 16 + pi, j);
+                        tail += __popcll(m);
+                        if (tail - head >= 64) {      // every lane bins one parked pair
+                            wave_sync_lds();
+                            bin_pair(ring[(head + lane) & (SPFH_RING - 1)]);
+                            head += 64;
+                            wave_sync_lds();
+                        }
+                    };
+                    for (int32_t c0 = rb; c0 < re; c0 += 16) {
+                        const int32_t j0 = c0 + kk, j1 = j0 + 4, j2 = j0 + 8, j3 = j0 + 12;
+                        const float4 q0 = g.p[min(j0, re - 1)], q1 = g.p[min(j1, re - 1)];
+                        const float4 q2 = g.p[min(j2, re - 1)], q3 = g.p[min(j3, re - 1)];
+                        test(j0, q0);
+                        if (c0 + 4 < re) test(j1, q1);  // uniform
+                        if (c0 + 8 < re) test(j2, q2);
+                        if (c0 + 12 < re) test(j3, q3);
+                    }
+                }
+            }
+        }
+        // neighbour count of point gq * 16 + pi: the four lanes that tested it
+        kc += __shfl_xor(kc, 16, 64);
+        kc += __shfl_xor(kc, 32, 64);
+        const int kg = __shfl(kc, lane & 15, 64);
+        if (kk == gq) kmine = kg;
     }
     // drain with the whole wavefront
     wave_sync_lds();
-    uint32_t head = cur[0];
-    const uint32_t tail = cur[1];
     while (head != tail) {
         const uint32_t n = min(64u, tail - head);
         if ((uint32_t)lane < n) bin_pair(ring[(head + lane) & (SPFH_RING - 1)]);
         head += n;
     }
     wave_sync_lds();
+    const int k = kmine;
     if (!live) return;
     uint32_t kp = 0;
 #pragma unroll
