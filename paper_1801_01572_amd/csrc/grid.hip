@@ -188,11 +188,16 @@ __global__ void __launch_bounds__(256) k_rankfix(const Frag *frag, const Blk *bl
                                                  const int32_t *cstart, const int32_t *ccount, const int32_t *tmp,
                                                  float4 *sp, float *snx, float *sny, float *snz,
                                                  int32_t *sorig) {
+    // One thread per sorted slot: the point the scatter parked in slot q (in
+    // arrival order) moves to its final slot st + rank, rank = its order by
+    // original index within the cell.  The writes stay inside the cell's slot
+    // range; the point's own fields are gathered from the input.
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
-    int i = b.start + threadIdx.x;
-    if (i >= F.n) return;
-    int32_t g = (int32_t)(F.off + i);
+    const int q = b.start + threadIdx.x;
+    if (q >= F.n) return;
+    const int32_t g = tmp[F.off + q];
+    const int i = (int)(g - F.off);
     int32_t gc = cell_of_pt[g];
     int32_t st = cstart[gc], cnt = ccount[gc], rank = 0;
     for (int32_t k = 0; k < cnt; ++k) rank += tmp[st + k] < g;
