@@ -19,7 +19,9 @@
  *    caller; "host" pointers are read before the call returns.
  *  - Clouds are float32 structure-of-arrays: six arrays x, y, z, nx, ny, nz
  *    of n entries each.  Normals are the fragment's input normals (used to
- *    orient the estimated normals).
+ *    orient the estimated normals).  Coordinates should be finite: a fragment
+ *    with a non-finite coordinate is indexed with a single grid cell (results
+ *    stay exact, neighbour searches cost O(n^2) for that fragment).
  *  - All calls enqueue work on `stream` (a hipStream_t; NULL means the
  *    default stream) and return without waiting.  Outputs are valid once the
  *    caller synchronises the stream.
