@@ -104,11 +104,13 @@ __device__ void jacobi_min_vec(double a00, double a01, double a02, double a11, d
     v[0] = x * inv; v[1] = y * inv; v[2] = z * inv;
 }
 
-__global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *blk, GridView g,
+__global__ void __launch_bounds__(256) k_normals(const Frag *frag, const Blk *blk, int nblk, GridView g,
                                                  const float *snx, const float *sny, const float *snz,
                                                  const int32_t *sorig, double r2, double *nx, double *ny, double *nz,
                                                  double *nrm_orig) {
-    const Blk b = blk[blockIdx.x];
+    const int bi = xcd_block(nblk);                   // neighbouring blocks share candidates
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
     const Frag &F = frag[b.frag];
     int i = b.start + threadIdx.x;
     if (i >= F.n) return;
@@ -152,7 +154,8 @@ hipError_t launch_normals(const GridBufs &g, float r_normal, DescBufs &d, double
     if (g.ntot == 0) return hipSuccess;
     GridView gv{g.cstart, g.ccount, g.sp};
     double r2 = (double)r_normal * (double)r_normal;
-    hipLaunchKernelGGL(k_normals, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
+    hipLaunchKernelGGL(k_normals, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag,
+                       (const Blk *)g.blk256, g.nblk256, gv,
                        (const float *)g.snx, (const float *)g.sny, (const float *)g.snz, (const int32_t *)g.sorig,
                        r2, d.nx, d.ny, d.nz, nrm_orig);
     return hipGetLastError();
@@ -275,15 +278,18 @@ __device__ __forceinline__ void wave_sync_lds() {
 // bins are counted with integer LDS atomics into the owner's histogram (order
 // independent).  kp is the sum of the alpha block (each counted pair adds one
 // to every block).
-__global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, GridView g, const double *nxa,
-                                                 const double *nya, const double *nza, double r2, ThetaEdges te,
-                                                 uint4 *spfh, int32_t *knb) {
+__global__ void __launch_bounds__(SPFH_T) k_spfh(const Frag *frag, const Blk *blk, int nblk, GridView g,
+                                                 const double *nxa, const double *nya, const double *nza, double r2,
+                                                 ThetaEdges te, uint4 *spfh, int32_t *knb) {
     __shared__ uint32_t hist[SPFH_T * FD];
     __shared__ int2 ring_all[SPFH_T / 64][SPFH_RING];
+    // XCD-aware order: neighbouring blocks share most candidate rows
+    const int bi = xcd_block(nblk);
+    if (bi >= nblk) return;
     uint32_t *h = hist + threadIdx.x * FD;
 #pragma unroll
     for (int c = 0; c < FD; ++c) h[c] = 0;
-    const Blk b = blk[blockIdx.x];
+    const Blk b = blk[bi];
     const Frag &F = frag[b.frag];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int pi = lane & 15, kk = lane >> 4;
@@ -420,7 +426,8 @@ hipError_t launch_spfh(const GridBufs &g, float r_feature, DescBufs &d, hipStrea
         double t = -PI + 2.0 * PI * k / NB, x = std::cos(t), y = std::sin(t), sa = std::fabs(x) + std::fabs(y);
         te.e[k - 1] = std::signbit(y) ? x / sa - 1.0 : 1.0 - x / sa;
     }
-    hipLaunchKernelGGL(k_spfh, dim3(g.nblk256), dim3(SPFH_T), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
+    hipLaunchKernelGGL(k_spfh, dim3(xcd_grid(g.nblk256)), dim3(SPFH_T), 0, s, (const Frag *)g.frag,
+                       (const Blk *)g.blk256, g.nblk256, gv,
                        (const double *)d.nx, (const double *)d.ny, (const double *)d.nz, r2, te, d.spfh, d.knb);
     return hipGetLastError();
 }
@@ -464,12 +471,15 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 // into the group's sums.  A group spanning several rows takes one pass per
 // row, each with W masked to that row's points.  Only the float32 summation
 // order differs from a per-point loop.
-__global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, GridView g, const int32_t *sorig,
-                                              const uint4 *spfh, const int32_t *knb, double r2, float *Fout,
-                                              int32_t *valid, PairState *ps) {
+__global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, int nblk, GridView g,
+                                              const int32_t *sorig, const uint4 *spfh, const int32_t *knb, double r2,
+                                              float *Fout, int32_t *valid, PairState *ps) {
     __shared__ float red[4][16][49];                  // per wavefront: 16 points x 48 bins (+1 pad)
     __shared__ int cnt[4];
-    const Blk b = blk[blockIdx.x];
+    // XCD-aware order: neighbouring blocks share most candidate rows
+    const int bi = xcd_block(nblk);
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
     const Frag &F = frag[b.frag];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int pi = lane & 15, kk = lane >> 4;
@@ -608,7 +618,8 @@ hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairStat
     if (g.ntot == 0) return hipSuccess;
     GridView gv{g.cstart, g.ccount, g.sp};
     double r2 = (double)r_feature * (double)r_feature;
-    hipLaunchKernelGGL(k_fpfh, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256, gv,
+    hipLaunchKernelGGL(k_fpfh, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       g.nblk256, gv,
                        (const int32_t *)g.sorig, (const uint4 *)d.spfh, (const int32_t *)d.knb, r2, d.F, d.valid, ps);
     return hipGetLastError();
 }

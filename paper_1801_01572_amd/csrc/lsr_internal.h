@@ -66,6 +66,19 @@ __device__ __forceinline__ double pdist2(double xi, double yi, double zi, double
     return __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
 }
 
+// XCD-aware block order.  The device hands workgroups to its 8 XCDs
+// round-robin (workgroup w runs on XCD w % 8), so consecutive entries of a
+// block table (neighbouring points, or one fragment's blocks) would run on
+// different XCDs and each XCD's L2 would fetch the data they share.
+// Workgroup w takes table entry (w % 8) per + w / 8 instead: each XCD walks a
+// contiguous eighth of the table.  The grid has xcd_grid(nblk) = 8 per
+// workgroups, per = ceil(nblk / 8); entries >= nblk do nothing.
+__device__ __forceinline__ int xcd_block(int nblk) {
+    const int per = (nblk + 7) >> 3;
+    return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+}
+static inline int xcd_grid(int nblk) { return 8 * ((nblk + 7) / 8); }
+
 __device__ __forceinline__ uint32_t f2ord(float f) {   // order-preserving float -> uint
     uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);

@@ -232,18 +232,10 @@ __device__ __forceinline__ int lds_slot(int idx) {            // uint4 index of 
     return (idx & ~7) | ((idx & 7) ^ lds_swz(idx >> 3));
 }
 
-// XCD-aware block order for the second screen.  The device hands workgroups to
-// its 8 XCDs round-robin (workgroup w runs on XCD w % 8), and only the first few
-// blocks of each fragment have uncertified rows, so in table order one
-// fragment's working blocks land on different XCDs and each XCD streams the
-// partner's rows from HBM.  Workgroup w takes table entry (w % 8) per + w / 8
-// instead: consecutive entries share an XCD, and its L2 serves the partner's rows
-// to all of them.  The grid has 8 per workgroups, per = ceil(nblk / 8).
-__device__ __forceinline__ int xcd_block(int nblk) {
-    const int per = (nblk + 7) >> 3;
-    return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-}
-static int xcd_grid(int nblk) { return 8 * ((nblk + 7) / 8); }
+// The second screen takes its blocks in XCD-aware order (xcd_block): only the
+// first few blocks of each fragment have uncertified rows, and in table order
+// one fragment's working blocks would run on different XCDs, each streaming
+// the partner's rows from HBM.
 
 // COLLECT = false: every row of the fragment is a query; write the best tile
 // and second-best tile maximum per lane group.
@@ -592,8 +584,10 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                                                 const float *v1, int32_t *nn,
                                                 float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
                                                 int32_t *full_row, int32_t *full_frag, int32_t *full_cnt,
-                                                PairState *ps) {
-    const Blk b = blk[blockIdx.x];
+                                                PairState *ps, int nblk) {
+    const int bi = xcd_block(nblk);                   // neighbouring queries share candidate rows
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
     const Frag &Fq = frag[b.frag];
     const int i = b.start + threadIdx.x;
     bool fb = false;
@@ -818,15 +812,15 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     tmark("screen", s);
     if (shape < 0 || shape >= N_SCREEN_SHAPES) return hipErrorInvalidValue;
     if (SCREEN_SHAPES[shape].t == 16)
-        hipLaunchKernelGGL(k_rerank<16>, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+        hipLaunchKernelGGL(k_rerank<16>, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                            (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
-                           S.full_cnt, ps);
+                           S.full_cnt, ps, g.nblk256);
     else
-        hipLaunchKernelGGL(k_rerank<32>, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+        hipLaunchKernelGGL(k_rerank<32>, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                            (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
-                           S.full_cnt, ps);
+                           S.full_cnt, ps, g.nblk256);
     tmark("rerank", s);
     if ((e = launch_screen(true, shape, g, d.pk, S, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rerank_list, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
