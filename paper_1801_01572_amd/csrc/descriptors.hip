@@ -546,8 +546,9 @@ __global__ void __launch_bounds__(256) k_fpfh(const Frag *frag, const Blk *blk, 
                         // there, keeping the weight finite; it dominates the sum either way.
                         const float wv = __builtin_amdgcn_rsqf(fmaxf((float)(hit ? d2 : 1.0), 1.17549435e-38f)) * cd.sc;
                         const float w = hit ? wv : 0.f;
-                        const float b0 = cd.in ? (float)cd.u0 : 0.f, b1 = cd.in ? (float)cd.u1 : 0.f;
-                        const float b2 = cd.in && pi == 0 ? (float)cd.u2 : 0.f;
+                        // counts need no mask: a lane past the run's end has w = 0, and
+                        // slot 33 (read by pi != 0 for bin pi + 32) is the rows' zero pad
+                        const float b0 = (float)cd.u0, b1 = (float)cd.u1, b2 = (float)cd.u2;
                         acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0, acc0, 0, 0, 0);
                         acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1, acc1, 0, 0, 0);
                         acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b2, acc2, 0, 0, 0);
