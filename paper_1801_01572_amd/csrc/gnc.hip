@@ -56,8 +56,9 @@ __device__ void rod(const double w[3], double D[9]) {
         A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
         B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
     } else {
-        double h = sin(0.5 * th);
-        A = sin(th) / th;
+        double h, c;                                  // sin th = 2 h c, 1 - cos th = 2 h^2
+        sincos(0.5 * th, &h, &c);
+        A = 2.0 * h * c / th;
         B = 2.0 * h * h / th2;
     }
     // I + A [w]x + B [w]x^2, with [w]x^2 = w w^T - th2 I
@@ -134,7 +135,8 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
                 for (int b = a; b < 6; ++b) { H[a][b] = acc[k]; H[b][a] = acc[k]; ++k; }
         }
         double tr = H[0][0] + H[1][1] + H[2][2] + H[3][3] + H[4][4] + H[5][5];
-        double L[6][6];
+        // one FP64 division per column (the reciprocal of L[j][j]), products elsewhere
+        double L[6][6], il[6];
         bool okc = true;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
@@ -143,12 +145,13 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
             for (int u = 0; u < j; ++u) d -= L[j][u] * L[j][u];
             okc = okc && d > 1e-12 * tr;
             L[j][j] = sqrt(okc ? d : 1.0);
+            il[j] = 1.0 / L[j][j];
 #pragma unroll
             for (int i = j + 1; i < 6; ++i) {
                 double s = H[i][j];
 #pragma unroll
                 for (int u = 0; u < j; ++u) s -= L[i][u] * L[j][u];
-                L[i][j] = s / L[j][j];
+                L[i][j] = s * il[j];
             }
         }
         const int ok = okc ? 1 : 0;
@@ -160,14 +163,14 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
                 double s = -acc[21 + i];
 #pragma unroll
                 for (int u = 0; u < i; ++u) s -= L[i][u] * yv[u];
-                yv[i] = s / L[i][i];
+                yv[i] = s * il[i];
             }
 #pragma unroll
             for (int i = 5; i >= 0; --i) {
                 double s = yv[i];
 #pragma unroll
                 for (int u = i + 1; u < 6; ++u) s -= L[u][i] * xi[u];
-                xi[i] = s / L[i][i];
+                xi[i] = s * il[i];
             }
             double D[9], Rn[9], tn[3];
             rod(xi, D);
