@@ -140,6 +140,47 @@ def test_match_bf16_random_and_edge_sizes(L):
             assert (a[0][vF == 0] == -1).all()
 
 
+def test_match_bf16_ties_and_extremes(L):
+    """bf16 screen == float32 scan where the screen's certificate is hardest:
+    1500 identical rows (every query ties with all of them, so the collected
+    lists overflow and rows fall back to the float32 rescan), near-duplicates
+    differing below bf16 resolution, and one-hot against uniform histograms
+    (extreme norms after centring)."""
+    rng = np.random.default_rng(5)
+
+    def norm(x):
+        x = x.reshape(len(x), 3, 11)
+        x = x / x.sum(2, keepdims=True)
+        return x.reshape(len(x), 33).astype(np.float32)
+
+    base = norm(rng.random((1, 33)) ** 3)
+    G = np.concatenate([np.repeat(base, 1500, 0),
+                        norm(rng.random((300, 33)) ** 4),
+                        norm(np.eye(11)[rng.integers(0, 11, (200, 3))].reshape(200, 33) + 1e-7),
+                        norm(np.ones((20, 33)))])
+    near = np.repeat(base, 400, 0) * (1 + rng.normal(scale=2e-4, size=(400, 33)).astype(np.float32))
+    F = np.concatenate([np.repeat(base, 50, 0), norm(near), norm(rng.random((300, 33)) ** 4),
+                        norm(np.eye(11)[rng.integers(0, 11, (100, 3))].reshape(100, 33) + 1e-7),
+                        norm(np.ones((5, 33)))])
+    vF = np.ones(len(F), np.int32)
+    vG = np.ones(len(G), np.int32)
+    print(f"ties nP={len(F)} nQ={len(G)}", flush=True)
+    args = (dev(F), dev(vF), dev(G), dev(vG))
+    a = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.FP32)]
+    try:
+        for shape in range(L.get_tune()["n_screen_shapes"]):
+            L.set_tune(shape, 0)
+            b = [t.cpu().numpy() for t in L.stage_match(*args, precision=L.BF16_SCREEN)]
+            for k in range(4):
+                assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), (shape, k)
+            print(f"  shape {shape}: {int(b[4][0])} rows rescanned in float32", flush=True)
+            assert int(b[4][0]) >= 50            # the tie rows overflowed their lists
+    finally:
+        L.set_tune(0, 0)
+    # exact copies of the repeated row match its first copy (lowest index on ties)
+    assert (a[0][:50] == 0).all()
+
+
 def test_consistency_parity(L, orc):
     pr = pair(4, 3, 15000)
     F, vF, G, vG = _oracle_descriptors(orc, pr)
