@@ -19,7 +19,7 @@ namespace lsr {
 
 constexpr int GT = 1024;          // one block per pair: 16 wavefronts share each iteration's sums
 constexpr int GW = GT / 64;
-constexpr int NS = 27;            // 21 entries of the symmetric H + 6 of g
+constexpr int NS = 19;            // distinct entries: 13 of the symmetric H + 6 of g
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -107,32 +107,42 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
         // G = [[0, z, -y, 1,0,0], [-z, 0, x, 0,1,0], [y, -x, 0, 0,0,1]]
         // G^T G (upper triangle, row-major over 6x6) and G^T r
         double xx = x * x, yy = y * y, zz = z * z;
+        // the 19 distinct sums: H's six zero entries (rows 0-2 against the
+        // other rotation columns of I, and the off-diagonal of the I block) and
+        // its three equal diagonal entries sum l are not accumulated separately
         acc[0] += l * (yy + zz);  acc[1] += l * (-x * y);  acc[2] += l * (-x * z);
-        acc[3] += 0.0;            acc[4] += l * (-z);       acc[5] += l * (y);
-        acc[6] += l * (xx + zz);  acc[7] += l * (-y * z);   acc[8] += l * (z);
-        acc[9] += 0.0;            acc[10] += l * (-x);
-        acc[11] += l * (xx + yy); acc[12] += l * (-y);      acc[13] += l * (x);
-        acc[14] += 0.0;
-        acc[15] += l; acc[16] += 0.0; acc[17] += 0.0;
-        acc[18] += l; acc[19] += 0.0;
-        acc[20] += l;
+        acc[3] += l * (-z);       acc[4] += l * (y);
+        acc[5] += l * (xx + zz);  acc[6] += l * (-y * z);  acc[7] += l * (z);
+        acc[8] += l * (-x);
+        acc[9] += l * (xx + yy);  acc[10] += l * (-y);     acc[11] += l * (x);
+        acc[12] += l;
         // G^T r = [p' x r ; r]
-        acc[21] += l * (y * rz - z * ry);
-        acc[22] += l * (z * rx - x * rz);
-        acc[23] += l * (x * ry - y * rx);
-        acc[24] += l * rx; acc[25] += l * ry; acc[26] += l * rz;
+        acc[13] += l * (y * rz - z * ry);
+        acc[14] += l * (z * rx - x * rz);
+        acc[15] += l * (x * ry - y * rx);
+        acc[16] += l * rx; acc[17] += l * ry; acc[18] += l * rz;
     }
     block_sums<NS>(acc, sh);
     if (threadIdx.x == 0) {
         // Fully unrolled (constant indices keep H and L in registers); the first
         // pivot at or below 1e-12 trace(H) marks the system degenerate.
+        // upper triangle of H (row-major) from the distinct sums; -1: zero
+        constexpr int HIDX[21] = {0, 1, 2, -1, 3, 4,      // row 0
+                                  5, 6, 7, -1, 8,         // row 1
+                                  9, 10, 11, -1,          // row 2
+                                  12, -1, -1,             // row 3
+                                  12, -1,                 // row 4
+                                  12};                    // row 5
         double H[6][6];
         {
             int k = 0;
 #pragma unroll
             for (int a = 0; a < 6; ++a)
 #pragma unroll
-                for (int b = a; b < 6; ++b) { H[a][b] = acc[k]; H[b][a] = acc[k]; ++k; }
+                for (int b = a; b < 6; ++b) {
+                    const double h = HIDX[k] < 0 ? 0.0 : acc[HIDX[k] < 0 ? 0 : HIDX[k]];
+                    H[a][b] = h; H[b][a] = h; ++k;
+                }
         }
         double tr = H[0][0] + H[1][1] + H[2][2] + H[3][3] + H[4][4] + H[5][5];
         // one FP64 division per column (the reciprocal of L[j][j]), products elsewhere
@@ -160,7 +170,7 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
             double yv[6], xi[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
-                double s = -acc[21 + i];
+                double s = -acc[13 + i];
 #pragma unroll
                 for (int u = 0; u < i; ++u) s -= L[i][u] * yv[u];
                 yv[i] = s * il[i];
