@@ -93,6 +93,26 @@ def test_batch_equals_pairs_and_replays(L):
     assert want[3]["status"] == L.DEGENERATE
 
 
+def test_batch_tiny_fragments(L):
+    """Fragments of 1-17 points and an empty Q inside one batch (single partial
+    blocks, one-point row groups, XCD-ordered grids of one block): batch ==
+    per-pair in both precisions."""
+    sizes = [(1, 1), (3, 7), (15, 16), (17, 300), (300, 17), (100, 0), (2500, 2500)]
+    prs = [pair(2, 20 + k, (int(n1), max(int(n2), 1))) for k, (n1, n2) in enumerate(sizes)]
+    for pr, (_, n2) in zip(prs, sizes):
+        if n2 == 0:
+            pr.Q = pr.Q[:, :0].copy()                     # an empty Q
+    P, Q, offP, offQ = _batch(prs)
+    for prec in (L.FP32, L.BF16_SCREEN):
+        prm = L.default_params(precision=prec)
+        want = [L.register_pair(dev(p.P), dev(p.Q), prm) for p in prs]
+        got = L.register_batch(dev(P), dev(Q), offP, offQ, prm)
+        for b in range(len(prs)):
+            for k in want[b]:
+                assert np.array_equal(np.asarray(got[b][k]), np.asarray(want[b][k])), (prec, sizes[b], k)
+        print(prec, [g["status"] for g in got], flush=True)
+
+
 def test_deterministic(L):
     pr = pair(4, 6, 12000)
     a = L.register_pair(dev(pr.P), dev(pr.Q))
