@@ -62,7 +62,6 @@ __device__ __forceinline__ uint32_t splitmix64_hi(uint64_t z) {
 constexpr int TPB = 8192;    // trials per block (the trial table's granularity)
 constexpr int CONS_THREADS[] = {256, 128, 512};   // block widths the autotuner picks from
 constexpr int N_CONS_SHAPES = sizeof(CONS_THREADS) / sizeof(CONS_THREADS[0]);
-constexpr int QCAP = 128;    // per-wavefront ring of drawn quadruples awaiting the edge test
 
 // usable[g] = 1 for a P point with a reciprocal correspondence inside Q (scan input).
 __global__ void __launch_bounds__(256) k_corr_usable(const Frag *frag, const Blk *blk, const int32_t *nn,
@@ -128,89 +127,55 @@ __device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, in
     return 1;
 }
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+// Index drawn from SplitMix64 state z: a position in C.
+__device__ __forceinline__ int draw(uint64_t z, uint32_t nC) {
+    return (int)(((uint64_t)splitmix64_hi(z) * nC) >> 32);
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// A slot's member: the first of up to 64 draws from state z on (attempts
+// advance the state by one gamma) that differs from x, y and w (the earlier
+// slots, repeated when there are fewer); -1 when all 64 repeat one of them.
+__device__ int slot_member(uint64_t z, uint32_t nC, int x, int y, int w) {
+    for (int a = 0; a < 64; ++a, z += GAMMA) {
+        const int i = draw(z, nC);
+        if (i != x && i != y && i != w) return i;
+    }
+    return -1;
 }
 
-// Each wavefront owns a contiguous range of TPB / waves trials of one pair and
-// hands them to its lanes on demand: a lane draws one index per iteration,
-// takes the next unclaimed trial when its current one completes or fails, and
-// parks a complete quadruple in a wavefront ring; 64 parked quadruples are
-// tested together.  Which lane runs which trial changes neither the draws
-// (they depend only on the trial index) nor the result (flags are set, counts
-// summed).
+// Each thread takes trials first + threadIdx.x + k CT of its block.  A trial
+// whose four slots' first draws are pairwise distinct keeps them (each slot
+// accepts its first draw, which already differs from the earlier slots); with
+// |C| in the thousands that is nearly every trial, so the common case is four
+// hashes and the edge test in straight-line code.  A trial with a repeat
+// takes its slots again in order with further attempts, as defined above.
+// Fewer than four members in C: no trial can draw a quadruple.
 template <int CT>
 __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const float4 *cpack,
                                                     int32_t *flag, double t2, uint64_t seed, PairState *ps) {
-    __shared__ int4 ring[CT / 64][QCAP];
-    __shared__ uint64_t rstep[64];             // r * 256 * gamma: a trial's first state is uniform + rstep[rank]
-    if (threadIdx.x < 64) rstep[threadIdx.x] = (uint64_t)threadIdx.x * (256ull * GAMMA);
-    __syncthreads();
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
     const uint32_t nC = (uint32_t)ps[b.pair].c_cnt;
     const float4 *cp = cpack + 2 * ps[b.pair].c_off;
     int32_t *fl = flag + P.off;
-    const int lane = threadIdx.x & 63;
-    int4 *q = ring[threadIdx.x >> 6];
-    constexpr int PER_WAVE = TPB / (CT / 64);
-    const int64_t wbeg = b.first + (int64_t)(threadIdx.x >> 6) * PER_WAVE;
-    const int64_t wend = nC ? min(b.count, wbeg + PER_WAVE) : wbeg;
-    int64_t next = wbeg;                       // next unclaimed trial (uniform)
-    uint32_t qhead = 0, qtail = 0;             // ring cursors (uniform)
-    bool live = false;
-    uint64_t zslot = 0, z = 0;                 // SplitMix64 state at the slot's first draw, at the current draw
-    int sl = 0, a = 0, id0 = 0, id1 = 0, id2 = 0, passed = 0;
-    for (;;) {
-        // lanes without a trial take the next unclaimed ones (selects, no branches)
-        const uint64_t need = __ballot(!live);
-        const uint32_t rank = lanes_below(need);
-        const int64_t t = next + rank;
-        const bool start = !live && t < wend;
-        const uint64_t z0 = (seed + (((uint64_t)next << 8) + 1ull) * GAMMA) + rstep[rank];   // state of trial t
-        live = live || start;
-        sl = start ? 0 : sl;
-        a = start ? 0 : a;
-        zslot = start ? z0 : zslot;
-        z = start ? z0 : z;
-        next += __popcll(need);
-        if (!__ballot(live)) break;
-        // one draw per lane: a position in C, kept unless it repeats an earlier slot
-        const int i = (int)(((uint64_t)splitmix64_hi(z) * nC) >> 32);
-        const bool dup = ((sl > 0) & (i == id0)) | ((sl > 1) & (i == id1)) | ((sl > 2) & (i == id2));
-        const bool hit = live & !dup;
-        const bool push = hit & (sl == 3);
-        const bool fail = live & !hit & (a == 63);      // 64 draws without a new member: the trial fails
-        const int4 quad = make_int4(id0, id1, id2, i);
-        id0 = (hit & (sl == 0)) ? i : id0;
-        id1 = (hit & (sl == 1)) ? i : id1;
-        id2 = (hit & (sl == 2)) ? i : id2;
-        sl += hit ? 1 : 0;
-        a = hit ? 0 : a + 1;
-        zslot += hit ? 64ull * GAMMA : 0ull;           // n advances by one slot (1 << 6)
-        z = hit ? zslot : z + GAMMA;
-        live = live & !push & !fail;
-        const uint64_t pm = __ballot(push);
-        if (push) q[(qtail + lanes_below(pm)) & (QCAP - 1)] = quad;
-        qtail += __popcll(pm);
-        if (qtail - qhead >= 64) {
-            wave_lds_sync();
-            passed += quad_test(cp, q[(qhead + lane) & (QCAP - 1)], t2, fl);
-            qhead += 64;
-            wave_lds_sync();
+    const int64_t end = nC >= 4 ? min(b.count, b.first + TPB) : b.first;
+    int passed = 0;
+    for (int64_t t = b.first + threadIdx.x; t < end; t += CT) {
+        const uint64_t z0 = seed + (((uint64_t)t << 8) + 1ull) * GAMMA;      // slot 0, attempt 0
+        const uint64_t z1 = z0 + 64ull * GAMMA, z2 = z0 + 128ull * GAMMA, z3 = z0 + 192ull * GAMMA;
+        const int i0 = draw(z0, nC);
+        int i1 = draw(z1, nC), i2 = draw(z2, nC), i3 = draw(z3, nC);
+        const bool rep = (i1 == i0) | (i2 == i0) | (i2 == i1) | (i3 == i0) | (i3 == i1) | (i3 == i2);
+        if (rep) {
+            i1 = slot_member(z1, nC, i0, i0, i0);
+            i2 = i1 < 0 ? -1 : slot_member(z2, nC, i0, i1, i1);
+            i3 = i2 < 0 ? -1 : slot_member(z3, nC, i0, i1, i2);
         }
+        if (i3 >= 0) passed += quad_test(cp, make_int4(i0, i1, i2, i3), t2, fl);
     }
-    wave_lds_sync();
-    if ((uint32_t)lane < qtail - qhead) passed += quad_test(cp, q[(qhead + lane) & (QCAP - 1)], t2, fl);
     // passing-trial count per pair (integer, order independent)
     for (int o = 32; o > 0; o >>= 1) passed += __shfl_xor(passed, o, 64);
-    if (lane == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
+    if ((threadIdx.x & 63) == 0 && passed) atomicAdd(&ps[b.pair].trials_passed, (unsigned long long)passed);
 }
 
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,

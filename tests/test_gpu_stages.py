@@ -200,6 +200,27 @@ def test_consistency_parity(L, orc):
     assert int(passed.cpu()[0]) == 0 and not flag.cpu().numpy().any()
 
 
+@pytest.mark.parametrize("nC", [0, 3, 4, 5, 7, 12, 40])
+def test_consistency_small_c(L, orc, nC):
+    # Few reciprocal correspondences: repeated draws are common, so most trials
+    # take further attempts per slot, and below four members none can pass.
+    rng = np.random.default_rng(100 + nC)
+    n = 300
+    P = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+    Q = (P * 1.02 + rng.normal(0, 0.01, (3, n))).astype(np.float32)
+    Q[:, ::3] = rng.uniform(-1, 1, (3, Q[:, ::3].shape[1]))     # a third are outliers
+    nnQ = np.arange(n, dtype=np.int32)
+    mut = np.zeros(n, np.uint8)
+    mut[rng.choice(n, nC, replace=False)] = 1
+    for T, seed in ((1, 7), (20000, 99), (8193, 2**64 - 1)):
+        want, npass = orc.consistency(P, Q, nnQ, mut, T, 0.9, seed)
+        flag, passed = L.stage_consistency(dev(P), dev(Q), dev(nnQ), dev(mut), T, 0.9, seed)
+        assert np.array_equal(flag.cpu().numpy().astype(bool), want)
+        assert int(passed.cpu()[0]) == npass
+        if nC < 4:
+            assert npass == 0 and not want.any()
+
+
 def _corr(rng, n, frac_out=0.5, noise=0.003):
     a = rng.normal(size=3)
     a /= np.linalg.norm(a)
