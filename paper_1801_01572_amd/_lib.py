@@ -37,11 +37,13 @@ class Result(C.Structure):
         ("inlier_ratio", C.c_double), ("fitness", C.c_double),
         ("n_valid_P", C.c_int64), ("n_valid_Q", C.c_int64), ("n_recip", C.c_int64),
         ("n_consistent", C.c_int64), ("n_inliers", C.c_int64), ("n_fallback_rows", C.c_int64),
+        ("n_screen_chunks", C.c_int64), ("n_screen_chunks_swept", C.c_int64),
         ("status", C.c_int32), ("iters", C.c_int32),
     ]
 
 
 MAX_VARIANTS = 8
+PRUNED_SCREEN = 5          # screen variant that skips the partner's chunks by their centroid bounds
 
 
 class Tune(C.Structure):

@@ -37,6 +37,8 @@
 // reaches theta = (|y_i|^2 - D* - slack) / 2 - c_i - E (a superset of all rows
 // that can tie or beat D*), and those are re-ranked exactly.  Only a row with
 // more than LCAP such candidates is rescanned in float32.
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "match_common.h"
 
 namespace lsr {
@@ -48,10 +50,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Screen shapes: tile edge T (16: 16x16x32 MFMAs, 32: 32x32x16 MFMAs), SW
 // waves per block x SQB T-query blocks per wave = 256 queries per block (one
 // block per 256 rows of a fragment, any variant); CH T-row tiles per LDS
-// chunk.  The variant is chosen by the autotuner.
-struct ScreenShape { int t, sw, sqb, ch; };
-constexpr ScreenShape SCREEN_SHAPES[] = {{16, 4, 4, 8}, {16, 4, 4, 4}, {16, 8, 2, 8}, {16, 8, 2, 4},
-                                         {32, 4, 2, 4}, {32, 2, 4, 4}, {16, 2, 8, 8}, {16, 2, 8, 4}};
+// chunk; prune: skip the partner's chunks that provably cannot matter (the
+// pruned screen below).  The variant is chosen by the autotuner.
+struct ScreenShape { int t, sw, sqb, ch, prune; };
+constexpr ScreenShape SCREEN_SHAPES[] = {{16, 4, 4, 8, 0}, {16, 4, 4, 4, 0}, {16, 8, 2, 8, 0}, {16, 8, 2, 4, 0},
+                                         {32, 4, 2, 4, 0}, {16, 4, 4, 8, 1}, {16, 2, 8, 8, 0}, {16, 2, 8, 4, 0}};
 constexpr int N_SCREEN_SHAPES = sizeof(SCREEN_SHAPES) / sizeof(SCREEN_SHAPES[0]);
 constexpr int PAD_ROWS = 128;      // fragments' packed rows are padded to a multiple of this
 constexpr int LCAP = 32;           // candidates collected per uncertified row
@@ -62,6 +65,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) {     // round to nearest even
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint32_t lanes_below_w(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
 struct ScreenScratch {
     float *mean;          // (nfrag/2 + 1) x 32: projected centring vector per pair
@@ -75,12 +81,31 @@ struct ScreenScratch {
     int32_t *lst;         // list slots x LCAP
     int32_t *lst_cnt;     // list slots
     int32_t *full_row, *full_frag, *full_cnt;
+    // descriptor-space row order (see "Row order" below)
+    float *pca;           // (nfrag/2 + 1) x 96: three principal directions (30 each) and their key scales
+    uint64_t *key0, *key1;// ntot: (fragment, Morton key) sort keys
+    uint32_t *idx0;       // ntot: point index (sort values in)
+    int32_t *perm;        // ntot: packed row r of a fragment holds its point perm[off + r] (sort values out)
+    int32_t *rinv;        // ntot: packed row of each point
+    void *sort_tmp;
+    size_t sort_bytes;
+    uint16_t *cpk;        // centroid rows of the partner chunks (pruned screen), packed like candidate rows
+    float4 *cst;          // per centroid row: (radius, score offset bound, max |y|^2 + max h, |centroid|^2)
 };
 
 // list slots of fragment f: [off/4 + 64 f, ... + n/4 + 64)
 __device__ __forceinline__ int64_t lst_base(const Frag &F, int f) { return F.off / 4 + 64 * (int64_t)f; }
 __device__ __forceinline__ int32_t lst_cap(const Frag &F) { return F.n / 4 + 64; }
 static int64_t lst_slots(const GridBufs &g) { return g.ntot / 4 + 64 * (int64_t)g.nfrag + 64; }
+// centroid rows of fragment f: [pk_off / 128 + 128 f, + ceil(chunks / 128) 128), chunks = padded rows / 128
+__device__ __forceinline__ int64_t cent_base(const Frag &F, int f) { return F.pk_off / PAD_ROWS + 128 * (int64_t)f; }
+// sort keys: fragment index above a 25-bit Morton key (2^24 marks an invalid descriptor)
+static int sort_end_bit(int nfrag) {
+    int b = 1;
+    while ((1 << b) < nfrag + 1 && b < 31) ++b;
+    return 25 + b;
+}
+static int64_t cent_rows(const GridBufs &g) { return g.pk_rows / PAD_ROWS + 128 * (int64_t)g.nfrag + 128; }
 
 static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     char *p = (char *)base;
@@ -101,6 +126,19 @@ static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     s.full_row = (int32_t *)take(sizeof(int32_t) * n1);
     s.full_frag = (int32_t *)take(sizeof(int32_t) * n1);
     s.full_cnt = (int32_t *)take(256);
+    s.pca = (float *)take(sizeof(float) * 96 * (size_t)(g.nfrag / 2 + 1));
+    s.key0 = (uint64_t *)take(sizeof(uint64_t) * n1);
+    s.key1 = (uint64_t *)take(sizeof(uint64_t) * n1);
+    s.idx0 = (uint32_t *)take(sizeof(uint32_t) * n1);
+    s.perm = (int32_t *)take(sizeof(int32_t) * n1);
+    s.rinv = (int32_t *)take(sizeof(int32_t) * n1);
+    s.sort_bytes = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, s.sort_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                    (uint32_t *)nullptr, (uint32_t *)nullptr, n1, 0, sort_end_bit(g.nfrag));
+    s.sort_tmp = take(s.sort_bytes);
+    const size_t ncent = (size_t)cent_rows(g);
+    s.cpk = (uint16_t *)take(sizeof(uint16_t) * PK * ncent);
+    s.cst = (float4 *)take(sizeof(float4) * ncent);
     if (bytes) *bytes = tot;
     return s;
 }
@@ -165,18 +203,23 @@ __global__ void __launch_bounds__(256) k_desc_mean(const Frag *frag, int nfrag, 
     }
 }
 
+// Point i of a fragment goes to packed row rinv[off + i]; thread t < n takes
+// point t (rows read in order, whole 128-byte rows written), a thread in
+// [n, padded n) writes padding row t.  yq stays indexed by point.
 __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                              const float *mean, uint16_t *pk, float4 *yq) {
+                                              const float *mean, const int32_t *rinv, uint16_t *pk, float4 *yq) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
-    int i = b.start + threadIdx.x;
+    const int t = b.start + threadIdx.x;
     int npad = (Fr.n + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS;
-    if (i >= npad) return;
-    int64_t row = Fr.pk_off + i;
+    if (t >= npad) return;
+    const int i = t;
+    const int r = t < Fr.n ? rinv[Fr.off + t] : t;
+    int64_t row = Fr.pk_off + r;
     uint16_t hi[32], lo[32];
     float n2 = 0.f, dd = 0.f;
     double dy = 0.0;
-    bool v = i < Fr.n && valid[Fr.off + i];
+    bool v = t < Fr.n && valid[Fr.off + i];
     if (v) {
         const float *x = F + (Fr.off + i) * FD;
         const float *m = mean + 32 * (b.frag >> 1);
@@ -218,7 +261,265 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
         w.w = o[6] | ((uint32_t)o[7] << 16);
         dst[q] = w;
     }
-    yq[row] = make_float4(n2, (float)dy, sqrtf(dd) * 1.0001f, 0.f);
+    if (t < Fr.n) yq[Fr.pk_off + i] = make_float4(n2, (float)dy, sqrtf(dd) * 1.0001f, 0.f);
+}
+
+// ---------------------------------------------------------------- row order
+//
+// Row order.  Each fragment's packed rows are sorted by a Morton key of their
+// first three principal components (8 bits each, over the pair's descriptor
+// sample), so that a 256-row query block and a 128-row candidate chunk are
+// each compact in descriptor space.  The order changes no result: every
+// kernel maps packed rows back to points, and ties are broken by point index.
+// The pruned screen then bounds a whole chunk at once through its centroid.
+
+// One block per pair: the covariance of the centred, projected descriptors
+// of the same sample as the centring (up to 4096 valid rows per fragment),
+// then its three leading eigenvectors by power iteration with deflation.
+// Key scale of component c: 128 / (3 sigma_c), so +-3 sigma spans the 8 bits.
+__global__ void __launch_bounds__(256) k_pca(const Frag *frag, int nfrag, const float *F, const int32_t *valid,
+                                             const float *mean, float *pca) {
+    __shared__ float sy[64][31];
+    __shared__ float cv[30][31];
+    __shared__ int cnt_sh;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const float *m = mean + 32 * b;
+    // entries e = tid, tid + 256 of the upper triangle (465 entries)
+    int ea[2], ec[2];
+    for (int u = 0; u < 2; ++u) {
+        int e = tid + 256 * u, a = 0;
+        while (e >= 30 - a && a < 30) { e -= 30 - a; ++a; }
+        ea[u] = a < 30 ? a : -1;
+        ec[u] = a + e;
+    }
+    float acc[2] = {0.f, 0.f};
+    int cnt = 0;
+    for (int f = 2 * b; f <= 2 * b + 1 && f < nfrag; ++f) {
+        const Frag &Fr = frag[f];
+        const int lim = min(Fr.n, 4096);
+        for (int i0 = 0; i0 < lim; i0 += 64) {
+            if (tid < 64) {
+                const int i = i0 + tid;
+                float h[30];
+                const bool v = i < lim && valid[Fr.off + i];
+                if (v) {
+                    const float *x = F + (Fr.off + i) * FD;
+                    float xb[FD];
+                    for (int c = 0; c < FD; ++c) xb[c] = x[c];
+                    for (int k = 0; k < 3; ++k) helmert11(xb + NB * k, h + 10 * k);
+                }
+                for (int c = 0; c < 30; ++c) sy[tid][c] = v ? h[c] - m[c] : 0.f;
+                cnt += v ? 1 : 0;
+            }
+            __syncthreads();
+            for (int u = 0; u < 2; ++u)
+                if (ea[u] >= 0)
+                    for (int r = 0; r < 64; ++r) acc[u] = fmaf(sy[r][ea[u]], sy[r][ec[u]], acc[u]);
+            __syncthreads();
+        }
+    }
+    for (int u = 0; u < 2; ++u)
+        if (ea[u] >= 0) { cv[ea[u]][ec[u]] = acc[u]; cv[ec[u]][ea[u]] = acc[u]; }
+    if (tid < 64) {
+        int c = cnt;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (tid == 0) cnt_sh = c;
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+    const int lane = tid;
+    const float n = (float)max(cnt_sh, 1);
+    float *out = pca + 96 * b;
+    for (int comp = 0; comp < 3; ++comp) {
+        float v = lane < 30 ? 1.0f + 0.01f * (float)lane * (float)(comp + 1) : 0.f;
+        float lam = 0.f;
+        for (int it = 0; it < 64; ++it) {
+            float w = 0.f;
+            for (int k = 0; k < 30; ++k) {
+                const float vk = __shfl(v, k, 64);
+                if (lane < 30) w = fmaf(cv[lane][k], vk, w);
+            }
+            float n2 = w * w;
+            for (int o = 32; o > 0; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+            if (!(n2 > 0.f)) break;
+            lam = sqrtf(n2);
+            v = w / lam;
+        }
+        // deflate: cv -= lam v v^T
+        for (int k = 0; k < 30; ++k) {
+            const float vk = __shfl(v, k, 64);
+            if (lane < 30) cv[lane][k] -= lam * v * vk;
+        }
+        if (lane < 30) out[30 * comp + lane] = v;
+        if (lane == 0) out[90 + comp] = lam > 0.f ? 128.0f / (3.0f * sqrtf(lam / n)) : 0.f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {      // bit k of x to bit 3k (8 bits)
+    x &= 0xFFu;
+    x = (x | (x << 8)) & 0x00F00Fu;
+    x = (x | (x << 4)) & 0x0C30C3u;
+    x = (x | (x << 2)) & 0x249249u;
+    return x;
+}
+
+// Sort key of each point: fragment index above its 24-bit Morton key (2^24
+// for an invalid descriptor, so those rows go last).
+__global__ void __launch_bounds__(256) k_mkey(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
+                                              const float *mean, const float *pca, uint64_t *key, uint32_t *idx) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fr = frag[b.frag];
+    const int i = b.start + threadIdx.x;
+    if (i >= Fr.n) return;
+    uint32_t mk = 1u << 24;
+    if (valid[Fr.off + i]) {
+        const float *x = F + (Fr.off + i) * FD;
+        const float *m = mean + 32 * (b.frag >> 1);
+        const float *pc = pca + 96 * (b.frag >> 1);
+        float xb[FD], h[30];
+#pragma unroll
+        for (int c = 0; c < FD; ++c) xb[c] = x[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) helmert11(xb + NB * k, h + 10 * k);
+        float p[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 30; ++c) {
+            const float y = h[c] - m[c];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) p[k] = fmaf(y, pc[30 * k + c], p[k]);
+        }
+        uint32_t q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float t = floorf(fmaf(p[k], pc[90 + k], 128.0f));
+            t = fminf(fmaxf(t, 0.0f), 255.0f);           // NaN -> 0 through fmax
+            q[k] = (uint32_t)t;
+        }
+        mk = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    }
+    key[Fr.off + i] = ((uint64_t)b.frag << 25) | mk;
+    idx[Fr.off + i] = (uint32_t)i;
+}
+
+// rinv[off + perm[off + r]] = r
+__global__ void __launch_bounds__(256) k_rinv(const Frag *frag, const Blk *blk, const int32_t *perm, int32_t *rinv) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fr = frag[b.frag];
+    const int r = b.start + threadIdx.x;
+    if (r >= Fr.n) return;
+    rinv[Fr.off + perm[Fr.off + r]] = r;
+}
+
+// One wavefront per 128-row chunk of packed rows: the centroid mu of the valid
+// rows y~ = hi + lo (float32, exact), split like a candidate row, and the
+// chunk's bounds for the pruned screen: radius rho >= |y~_j - mu~|, score
+// offset delta >= |y~_j|^2 / 2 - h_j (h_j = -(c_hi + c_lo), FP64, rounded up),
+// max |y~_j|^2 + max h_j, and |mu~|^2.  A chunk without valid rows gets
+// radius -1 and a centroid that no query can approach.  The last chunk's
+// wavefront also writes the padding centroid rows.
+__global__ void __launch_bounds__(256) k_chunk_stats(const Frag *frag, const Blk *blk, const uint16_t *pk,
+                                                     uint16_t *cpk, float4 *cst) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fr = frag[b.frag];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nch = (Fr.n + PAD_ROWS - 1) / PAD_ROWS;
+    const int k = b.start / PAD_ROWS + wv;                 // 256-point block: chunks start/128 + {0, 1}
+    if (wv >= 2 || k >= nch) return;
+    const int64_t cb = cent_base(Fr, b.frag);
+    // one row (lane + 64 u of the chunk): y~ = hi + lo, h = -(c_hi + c_lo), valid
+    auto load = [&](int u, float *y, float &h) {
+        const uint4 *row4 = (const uint4 *)(pk + (Fr.pk_off + (int64_t)k * PAD_ROWS + lane + 64 * u) * PK);
+        uint4 w4[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w4[q] = row4[q];
+        const uint16_t *row = (const uint16_t *)w4;
+        const float chi = bf2f(row[30]), clo = bf2f(row[31]);
+        h = -(chi + clo);
+#pragma unroll
+        for (int c = 0; c < 30; ++c) y[c] = bf2f(row[c]) + bf2f(row[32 + c]);
+        return chi > -1.0e29f;
+    };
+    float s[30];
+#pragma unroll
+    for (int c = 0; c < 30; ++c) s[c] = 0.f;
+    int nv = 0;
+    for (int u = 0; u < 2; ++u) {
+        float y[30], h;
+        if (!load(u, y, h)) continue;
+#pragma unroll
+        for (int c = 0; c < 30; ++c) s[c] += y[c];
+        ++nv;
+    }
+    for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o, 64);
+    uint16_t mh[32], ml[32];
+    float mu[30], mu2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 30; ++c) {
+        float t = s[c];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        t = nv > 0 ? t / (float)nv : 0.f;
+        mh[c] = f2bf(t);
+        ml[c] = f2bf(t - bf2f(mh[c]));
+        mu[c] = bf2f(mh[c]) + bf2f(ml[c]);
+        mu2 = fmaf(mu[c], mu[c], mu2);
+    }
+    float rho = 0.f, ym = 0.f, hm = 0.f;
+    double del = -1.0e300;
+    for (int u = 0; u < 2; ++u) {
+        float y[30], h;
+        if (!load(u, y, h)) continue;
+        float d2 = 0.f, n2f = 0.f;
+        double n2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 30; ++c) {
+            const float d = y[c] - mu[c];
+            d2 = fmaf(d, d, d2);
+            n2f = fmaf(y[c], y[c], n2f);
+            n2 = fma((double)y[c], (double)y[c], n2);
+        }
+        rho = fmaxf(rho, sqrtf(d2));
+        ym = fmaxf(ym, n2f);
+        hm = fmaxf(hm, h);
+        del = fmax(del, 0.5 * n2 - (double)h);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        rho = fmaxf(rho, __shfl_xor(rho, o, 64));
+        ym = fmaxf(ym, __shfl_xor(ym, o, 64));
+        hm = fmaxf(hm, __shfl_xor(hm, o, 64));
+        del = fmax(del, __shfl_xor(del, o, 64));
+    }
+    const float cc = -0.5f * mu2;
+    if (lane == 0) {
+        float4 st;
+        if (nv > 0) {
+            float df = (float)del;
+            df += fabsf(df) * 2.4e-7f + 1.0e-30f;                // rounded up
+            st = make_float4(rho * (1.0f + 1.0e-6f) + 1.0e-30f, df, (ym + hm) * (1.0f + 1.0e-6f),
+                             mu2 * (1.0f + 1.0e-6f));
+        } else {
+            st = make_float4(-1.0f, 0.f, 0.f, 0.f);
+        }
+        cst[cb + k] = st;
+        uint16_t *dst = cpk + (cb + k) * PK;
+        for (int c = 0; c < 30; ++c) { dst[c] = mh[c]; dst[32 + c] = ml[c]; }
+        const uint16_t chi = nv > 0 ? f2bf(cc) : f2bf(-1.0e30f);
+        dst[30] = chi;
+        dst[31] = nv > 0 ? f2bf(cc - bf2f(chi)) : (uint16_t)0;
+        dst[62] = 0;
+        dst[63] = 0;
+    }
+    if (k == nch - 1) {                                   // padding rows up to a multiple of 128
+        const int ncp = (nch + 127) / 128 * 128;
+        for (int r = nch + lane; r < ncp; r += 64) {
+            uint16_t *dst = cpk + (cb + r) * PK;
+            for (int c = 0; c < PK; ++c) dst[c] = 0;
+            dst[30] = f2bf(-1.0e30f);
+            cst[cb + r] = make_float4(-1.0f, 0.f, 0.f, 0.f);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- screen
@@ -244,9 +545,10 @@ __device__ __forceinline__ int lds_slot(int idx) {            // uint4 index of 
 // reaches the row's threshold to the row's candidate list.
 template <bool COLLECT, int SW, int SQB, int CH>
 __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk,
+                                                    const int32_t *perm, const int32_t *rinv,
                                                     int32_t *c1_out, float *v2_out, float *v1_out, const int32_t *fb_row,
                                                     const int32_t *fb_cnt, const float *thr, int32_t *lst,
-                                                    int32_t *lst_cnt) {
+                                                    int32_t *lst_cnt, PairState *ps) {
     static_assert(SW * SQB * 16 == 256 && PAD_ROWS % (CH * 16) == 0, "screen shape");
     constexpr int CROWS = CH * 16;                               // rows per LDS chunk
     constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk (1024)
@@ -280,7 +582,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
         uint4 wh = make_uint4(0, 0, 0, 0);
         th[k] = INFINITY;
         if (slot < nq) {
-            int q = COLLECT ? fb_row[Fq.off + slot] : slot;
+            int q = COLLECT ? rinv[Fq.off + fb_row[Fq.off + slot]] : slot;      // packed row
             const uint16_t *r = pk + (Fq.pk_off + q) * PK;
             wh = *(const uint4 *)(r + 8 * grp);
             if (COLLECT) th[k] = thr[Fq.off + slot];
@@ -394,16 +696,322 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     }
     if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
+        if (threadIdx.x == 0 && ps && Fq.pair >= 0) {
+            const unsigned long long nc = (unsigned long long)((Fc.n + PAD_ROWS - 1) / PAD_ROWS);
+            atomicAdd(&ps[Fq.pair].scr_chunks, nc);
+            atomicAdd(&ps[Fq.pair].scr_swept, nc);
+        }
 #pragma unroll
         for (int k = 0; k < SQB; ++k) {
             // lane (col, grp): candidate rows tile*16 + 4 grp + {0..3} (MFMA output rows) of query col
             int q = qw + 16 * k + col;
             if (q < Fq.n) {
-                int64_t o = (Fq.off + q) * 4 + grp;
+                int64_t o = (Fq.off + perm[Fq.off + q]) * 4 + grp;
                 c1_out[o] = c1[k];
                 v2_out[o] = v2[k];
                 v1_out[o] = v1[k];
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pruned screen
+//
+// The partner's packed rows come in chunks of 128 with centroid rows mu~_k
+// (split like candidate rows, so the matrix cores screen them like rows) and
+// bounds rho_k >= |y~_j - mu~_k| and delta_k >= |y~_j|^2 / 2 - h_j.  For a
+// query with bf16 row yh_i and n_i = |yh_i|^2, every computed score of a row
+// j of chunk k obeys
+//   t_ij <= n_i / 2 - max(0, g_ik - rho_k)^2 / 2 + delta_k + acc_ik,
+// with g_ik <= |yh_i - mu~_k| taken from the screened centroid score tc_ik as
+// g_ik^2 = n_i - 2 tc_ik - m_ik, and m_ik, acc_ik margins of 2^-12 of the
+// magnitudes involved (float32 accumulation of 64 products errs by ~2^-18 of
+// them).  A block
+//  1. screens its 256 queries against every centroid, and sweeps the PR_K
+//     chunks whose centroids come nearest to any live query;
+//  2. screens the centroids again: a query needs chunk k unless the bound
+//     stays below its best screened score so far minus a margin (four times
+//     the certificate's error estimate), and the bound of a chunk a query does
+//     not need is folded into its second-best tile maximum, so the certificate
+//     still covers every row the block does not screen;
+//  3. sweeps the chunks some live query needs.
+// Rows with a 2^24 key (invalid descriptors) sort last in each fragment.
+constexpr int PR_K = 4;
+constexpr int PR_NCH_MAX = 4096;      // chunks one block can track (fragments up to 524288 rows); beyond: no pruning
+
+template <int SW, int SQB, int CH>
+__global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3))) k_screen_pr(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk,
+                                                       const uint16_t *cpk, const float4 *cst, const int32_t *perm,
+                                                       int32_t *c1_out, float *v2_out, float *v1_out, PairState *ps) {
+    static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS, "pruned screen shape");
+    constexpr int CROWS = CH * 16;
+    constexpr int U4 = CROWS * PK / 8;
+    constexpr float MRG = 2.44140625e-4f;                       // 2^-12
+    __shared__ __align__(16) uint4 ldsA[U4];
+    __shared__ __align__(16) uint4 ldsB[U4];                    // between sweeps: chunk keys, then need flags
+    __shared__ uint16_t seq[PR_NCH_MAX];                        // chunks of the current sweep
+    __shared__ float redv[SW];
+    __shared__ int redi[SW];
+    __shared__ int nseq;
+    const int bi = (int)blockIdx.x;
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
+    const Frag &Fq = frag[b.frag];
+    if (Fq.partner < 0) return;
+    const Frag &Fc = frag[Fq.partner];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int swz = lds_swz(col);
+    const int nch = (Fc.n + CROWS - 1) / CROWS;
+    const bool prune = nch <= PR_NCH_MAX;
+
+    // query operands [y_hi, 1, 1]; n_i = |yh_i|^2 over the 30 coordinates; a
+    // live query is a row with a valid descriptor (its c_hi slot is not -1e30)
+    bf16x8 Bh[SQB];
+    float nq2[SQB];
+    bool live[SQB];
+    const int qw = b.start + wv * SQB * 16;
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) {
+        const int slot = qw + 16 * k + col;
+        uint4 wh = make_uint4(0, 0, 0, 0);
+        if (slot < Fq.n) wh = *(const uint4 *)(pk + (Fq.pk_off + slot) * PK + 8 * grp);
+        const uint32_t w32[4] = {wh.x, wh.y, wh.z, wh.w};
+        float p2 = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = __uint_as_float((e & 1) ? (w32[e >> 1] & 0xFFFF0000u) : (w32[e >> 1] << 16));
+            if (grp < 3 || e < 6) p2 = fmaf(x, x, p2);
+        }
+        int bad = (grp == 3 && __uint_as_float(wh.w << 16) < -1.0e29f) ? 1 : 0;
+        p2 += __shfl_xor(p2, 16, 64);
+        p2 += __shfl_xor(p2, 32, 64);
+        bad |= __shfl_xor(bad, 16, 64);
+        bad |= __shfl_xor(bad, 32, 64);
+        nq2[k] = p2;
+        live[k] = slot < Fq.n && !bad;
+        if (grp == 3) wh.w = 0x3f803f80u;                     // slots 30, 31 = 1.0
+        Bh[k] = __builtin_bit_cast(bf16x8, wh);
+    }
+    float v1[SQB], v2[SQB], sf[SQB];
+    int32_t c1[SQB];
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) { v1[k] = -INFINITY; v2[k] = -INFINITY; sf[k] = -INFINITY; c1[k] = -1; }
+
+    constexpr int PER = U4 / (SW * 64);
+    const uint4 *src = (const uint4 *)(pk + Fc.pk_off * PK);
+    const int64_t cb = cent_base(Fc, Fq.partner);
+    const uint4 *csrc = (const uint4 *)(cpk + cb * PK);
+    auto stage = [&](uint4 *dst, const uint4 *from) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int base = u * SW * 64 + wv * 64;
+            __builtin_amdgcn_global_load_lds((const void *)(from + lds_slot(base + lane)),
+                                             (__attribute__((address_space(3))) void *)(dst + base), 16, 0, 0);
+        }
+    };
+    auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    f32x4 prev[SQB];
+    int prev_tile = -1;
+    auto epilogue = [&](const f32x4 *accs, int tile) {
+        bool up[SQB];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) {
+            const f32x4 acc = accs[k];
+            const float tm = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
+            v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);
+            up[k] = tm > v1[k];
+            any |= up[k];
+            v1[k] = __builtin_fmaxf(v1[k], tm);
+        }
+        if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) c1[k] = up[k] ? tile : c1[k];
+        }
+    };
+    auto cid = [&](int c) { return prune ? (int)seq[c] : c; };
+    // one chunk of a sweep: start copying the next chunk into D, sweep the tiles of L
+    auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) {
+        if (c + 1 < len) stage(D, src + (int64_t)cid(c + 1) * U4);
+        const int tbase = cid(c) * CH;
+        uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
+#pragma unroll 2
+        for (int t = 0; t < CH; ++t) {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, nh);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, nl);
+            if (t + 1 < CH) {
+                const uint4 *rowp = L + ((t + 1) * 16 + col) * 8;
+                nh = rowp[grp ^ swz];
+                nl = rowp[(4 + grp) ^ swz];
+            }
+            f32x4 accs[SQB];
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
+            if (prev_tile >= 0) epilogue(prev, prev_tile);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
+            prev_tile = tbase + t;
+        }
+        wait_copies();
+        __syncthreads();
+    };
+    auto sweep = [&](int len) {
+        if (len <= 0) return;
+        stage(ldsA, src + (int64_t)cid(0) * U4);
+        wait_copies();
+        __syncthreads();
+        for (int c = 0; c < len; c += 2) {
+            chunk(ldsA, ldsB, c, len);
+            if (c + 1 < len) chunk(ldsB, ldsA, c + 1, len);
+        }
+        if (prev_tile >= 0) epilogue(prev, prev_tile);
+        prev_tile = -1;
+    };
+    // screened scores of the block's queries against every centroid row, one
+    // staged chunk of 128 centroids at a time (single buffered: ldsB holds the
+    // per-chunk state); fn(accs, first centroid of the lane's four)
+    auto cent_pass = [&](auto &&fn) {
+        const int ncc = (nch + CROWS - 1) / CROWS;
+        for (int cc = 0; cc < ncc; ++cc) {
+            stage(ldsA, csrc + (int64_t)cc * U4);
+            wait_copies();
+            __syncthreads();
+            for (int t = 0; t < CH; ++t) {
+                const uint4 *rowp = ldsA + (t * 16 + col) * 8;
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
+                const bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
+                f32x4 accs[SQB];
+#pragma unroll
+                for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
+                fn(accs, cc * CROWS + t * 16 + 4 * grp);
+            }
+            __syncthreads();
+        }
+    };
+
+    int swept = nch;                                            // chunk visits made, centroid passes included
+    if (!prune) {
+        sweep(nch);
+    } else {
+        // 1. block-minimum distance bound per chunk, then the PR_K nearest chunks
+        float *keys = (float *)ldsB;
+        for (int k = threadIdx.x; k < nch; k += SW * 64) keys[k] = INFINITY;
+        __syncthreads();
+        cent_pass([&](const f32x4 *accs, int kc0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kc = kc0 + e;
+                const float mc2 = kc < nch ? cst[cb + kc].w : 0.f;
+                float m = INFINITY;
+#pragma unroll
+                for (int k = 0; k < SQB; ++k)
+                    if (live[k]) m = fminf(m, nq2[k] - 2.0f * accs[k][e] - MRG * (nq2[k] + mc2));
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) m = fminf(m, __shfl_xor(m, o, 64));
+                if (col == 0 && kc < nch && m < INFINITY) atomicMin((int *)&keys[kc], __float_as_int(fmaxf(m, 0.f)));
+            }
+        });
+        const int k1 = min(PR_K, nch);
+        for (int r = 0; r < k1; ++r) {
+            float bv = INFINITY;
+            int bk = 0x7fffffff;
+            for (int k = threadIdx.x; k < nch; k += SW * 64) {
+                const float v = keys[k];
+                if (v < bv || (v == bv && k < bk)) { bv = v; bk = k; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const float ov = __shfl_xor(bv, o, 64);
+                const int ok = __shfl_xor(bk, o, 64);
+                if (ov < bv || (ov == bv && ok < bk)) { bv = ov; bk = ok; }
+            }
+            if (lane == 0) { redv[wv] = bv; redi[wv] = bk; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int w = 1; w < SW; ++w)
+                    if (redv[w] < bv || (redv[w] == bv && redi[w] < bk)) { bv = redv[w]; bk = redi[w]; }
+                seq[r] = (uint16_t)bk;
+                keys[bk] = __uint_as_float(0x7fffffffu);               // NaN: never the minimum again
+            }
+            __syncthreads();
+        }
+        sweep(k1);
+        // 2. which chunks do the queries still need?
+        float thn[SQB];
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) {
+            float bq = v1[k];
+            bq = fmaxf(bq, __shfl_xor(bq, 16, 64));
+            bq = fmaxf(bq, __shfl_xor(bq, 32, 64));
+            const float D = fmaxf(nq2[k] - 2.0f * bq, 0.f);
+            const float dl = 7.8125e-3f * sqrtf(nq2[k] * D) + MRG * (nq2[k] + D) + 1.0e-7f;
+            thn[k] = bq - dl;                                       // -inf when no row was screened
+        }
+        uint8_t *need = (uint8_t *)ldsB;                            // 0 skip, 1 sweep, 2 already swept
+        for (int k = threadIdx.x; k < nch; k += SW * 64) need[k] = 0;
+        __syncthreads();
+        if (threadIdx.x < k1) need[seq[threadIdx.x]] = 2;
+        __syncthreads();
+        cent_pass([&](const f32x4 *accs, int kc0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kc = kc0 + e;
+                bool nd_any = false;
+                if (kc < nch) {
+                    const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
+                    const bool done = need[kc] == 2;
+#pragma unroll
+                    for (int k = 0; k < SQB; ++k) {
+                        if (!live[k] || st.x < 0.f) continue;        // dead query or empty chunk
+                        const float g2 = nq2[k] - 2.0f * accs[k][e] - MRG * (nq2[k] + st.w);
+                        const float L = fmaxf(sqrtf(fmaxf(g2, 0.f)) - st.x, 0.f);
+                        const float U = 0.5f * nq2[k] * (1.0f + 1.0e-6f) - 0.5f * L * L * (1.0f - 1.0e-6f) + st.y +
+                                        MRG * (nq2[k] + st.z);
+                        const bool nd = U >= thn[k];
+                        nd_any |= nd && !done;
+                        if (!nd && !done) sf[k] = fmaxf(sf[k], U);
+                    }
+                }
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(nd_any);
+                if (col == 0 && ((bal >> (16 * grp)) & 0xFFFFull)) need[kc] = 1;
+            }
+        });
+        // 3. the needed chunks, in index order
+        if (wv == 0) {
+            int cnt = 0;
+            for (int base = 0; base < nch; base += 64) {
+                const int k = base + lane;
+                const bool f = k < nch && need[k] == 1;
+                const uint64_t m = __builtin_amdgcn_ballot_w64(f);
+                if (f) seq[cnt + (int)lanes_below_w(m)] = (uint16_t)k;
+                cnt += __popcll(m);
+            }
+            if (lane == 0) nseq = cnt;
+        }
+        __syncthreads();
+        sweep(nseq);
+        swept = k1 + nseq + 2 * ((nch + CROWS - 1) / CROWS);
+    }
+    if (threadIdx.x == 0 && ps && Fq.pair >= 0) {
+        atomicAdd(&ps[Fq.pair].scr_chunks, (unsigned long long)nch);
+        atomicAdd(&ps[Fq.pair].scr_swept, (unsigned long long)swept);
+    }
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) {
+        float s = sf[k];
+        s = fmaxf(s, __shfl_xor(s, 16, 64));
+        s = fmaxf(s, __shfl_xor(s, 32, 64));
+        const int q = qw + 16 * k + col;
+        if (q < Fq.n) {
+            int64_t o = (Fq.off + perm[Fq.off + q]) * 4 + grp;
+            c1_out[o] = c1[k];
+            v2_out[o] = fmaxf(v2[k], s);
+            v1_out[o] = v1[k];
         }
     }
 }
@@ -415,9 +1023,10 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 // checks 32 rows per query.
 template <bool COLLECT, int SW, int QB, int CH>
 __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk,
-                                                      int32_t *c1_out, float *v2_out, float *v1_out, const int32_t *fb_row,
+                                                      const int32_t *perm, const int32_t *rinv, int32_t *c1_out,
+                                                      float *v2_out, float *v1_out, const int32_t *fb_row,
                                                       const int32_t *fb_cnt, const float *thr, int32_t *lst,
-                                                      int32_t *lst_cnt) {
+                                                      int32_t *lst_cnt, PairState *ps) {
     static_assert(SW * QB * 32 == 256 && PAD_ROWS % (CH * 32) == 0, "screen shape");
     constexpr int CROWS = CH * 32;                               // rows per LDS chunk
     constexpr int U4 = CROWS * PK / 8;                          // uint4 per chunk
@@ -448,7 +1057,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
         uint4 w0 = make_uint4(0, 0, 0, 0), w1 = w0;
         th[k] = INFINITY;
         if (slot < nq) {
-            int q = COLLECT ? fb_row[Fq.off + slot] : slot;
+            int q = COLLECT ? rinv[Fq.off + fb_row[Fq.off + slot]] : slot;      // packed row
             const uint16_t *r = pk + (Fq.pk_off + q) * PK;
             w0 = *(const uint4 *)(r + 8 * h);
             w1 = *(const uint4 *)(r + 16 + 8 * h);
@@ -547,11 +1156,16 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
     }
     if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
+        if (threadIdx.x == 0 && ps && Fq.pair >= 0) {
+            const unsigned long long nc = (unsigned long long)((Fc.n + PAD_ROWS - 1) / PAD_ROWS);
+            atomicAdd(&ps[Fq.pair].scr_chunks, nc);
+            atomicAdd(&ps[Fq.pair].scr_swept, nc);
+        }
 #pragma unroll
         for (int k = 0; k < QB; ++k) {
             int q = qw + 32 * k + col;
             if (q < Fq.n) {
-                int64_t o = (Fq.off + q) * 4 + h;                 // entries 0, 1 of the row's four
+                int64_t o = (Fq.off + perm[Fq.off + q]) * 4 + h;  // entries 0, 1 of the row's four
                 c1_out[o] = c1[k];
                 v2_out[o] = v2[k];
                 v1_out[o] = v1[k];
@@ -580,8 +1194,8 @@ __device__ __forceinline__ float screen_err(float4 q, float best) {
 
 template <int T>
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                                const float4 *yq, const int32_t *c1, const float *v2,
-                                                const float *v1, int32_t *nn,
+                                                const float4 *yq, const int32_t *perm, const int32_t *c1,
+                                                const float *v2, const float *v1, int32_t *nn,
                                                 float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
                                                 int32_t *full_row, int32_t *full_frag, int32_t *full_cnt,
                                                 PairState *ps, int nblk) {
@@ -629,8 +1243,10 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                 // holds only rows with distance above D + slack: it cannot hold the minimum.
                 if (bj >= 0 && gv[g] + qv.y + screen_err(qv, best) < 0.5f * (ny2 - best - slack(best))) continue;
                 for (int e = 0; e < NE; ++e) {
-                    int32_t j = T == 16 ? tl * 16 + 4 * g + e : tl * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
-                    if (j >= Fc.n || !valid[Fc.off + j]) continue;
+                    const int32_t r = T == 16 ? tl * 16 + 4 * g + e : tl * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+                    if (r >= Fc.n) continue;
+                    const int32_t j = perm[Fc.off + r];                 // packed row -> point
+                    if (!valid[Fc.off + j]) continue;
                     float x[FD];
                     load_row(F, Fc.off + j, x);
                     float d = d2_row(q, x);
@@ -664,8 +1280,9 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
 __global__ void __launch_bounds__(256) k_rerank_list(const Frag *frag, const Blk *blk, const float *F,
                                                      const int32_t *valid, const int32_t *fb_row,
                                                      const int32_t *fb_cnt, const float *thr, const int32_t *lst,
-                                                     const int32_t *lst_cnt, int32_t *nn, float *dist,
-                                                     int32_t *full_row, int32_t *full_frag, int32_t *full_cnt) {
+                                                     const int32_t *lst_cnt, const int32_t *perm, int32_t *nn,
+                                                     float *dist, int32_t *full_row, int32_t *full_frag,
+                                                     int32_t *full_cnt) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
@@ -688,8 +1305,10 @@ __global__ void __launch_bounds__(256) k_rerank_list(const Frag *frag, const Blk
     float best = INFINITY;
     int32_t bj = -1;
     for (int k = 0; k < cnt; ++k) {
-        int32_t j = lst[ls * LCAP + k];
-        if (j >= Fc.n || !valid[Fc.off + j]) continue;
+        const int32_t r = lst[ls * LCAP + k];                  // packed row
+        if (r >= Fc.n) continue;
+        const int32_t j = perm[Fc.off + r];
+        if (!valid[Fc.off + j]) continue;
         float x[FD];
         load_row(F, Fc.off + j, x);
         float d = d2_row(q, x);
@@ -742,36 +1361,42 @@ __global__ void __launch_bounds__(256) k_fallback(const Frag *frag, const float 
     }
 }
 
-template <bool COLLECT, int T, int SW, int SQB, int CH>
-static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScratch &S, hipStream_t s) {
+template <bool COLLECT, int T, int SW, int SQB, int CH, int PRUNE>
+static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScratch &S, PairState *ps,
+                          hipStream_t s) {
+    const int32_t *perm = S.perm, *rinv = S.rinv;
     if constexpr (T == 16) {
         if (COLLECT)
             hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, nullptr, nullptr, nullptr,
-                               (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
-                               S.lst_cnt);
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, nullptr, nullptr,
+                               nullptr, (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr,
+                               S.lst, S.lst_cnt, nullptr);
+        else if constexpr (PRUNE != 0)
+            hipLaunchKernelGGL((k_screen_pr<SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
+                               (const Blk *)g.blk256, g.nblk256, pk, (const uint16_t *)S.cpk, (const float4 *)S.cst,
+                               perm, S.c1, S.v2, S.v1, ps);
         else
             hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
-                               nullptr, nullptr);
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, S.c1, S.v2, S.v1,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, ps);
     } else {
         if (COLLECT)
             hipLaunchKernelGGL((k_screen32<true, SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, nullptr, nullptr, nullptr,
-                               (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr, S.lst,
-                               S.lst_cnt);
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, nullptr, nullptr,
+                               nullptr, (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr,
+                               S.lst, S.lst_cnt, nullptr);
         else
             hipLaunchKernelGGL((k_screen32<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
-                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, S.c1, S.v2, S.v1, nullptr, nullptr, nullptr,
-                               nullptr, nullptr);
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, S.c1, S.v2, S.v1,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, ps);
     }
 }
 
 template <bool COLLECT>
 static hipError_t launch_screen_c(int shape, const GridBufs &g, const uint16_t *pk, const ScreenScratch &S,
-                                  hipStream_t s) {
+                                  PairState *ps, hipStream_t s) {
 #define LSR_SHAPE(v) screen_launch<COLLECT, SCREEN_SHAPES[v].t, SCREEN_SHAPES[v].sw, SCREEN_SHAPES[v].sqb, \
-                                     SCREEN_SHAPES[v].ch>(g, pk, S, s)
+                                     SCREEN_SHAPES[v].ch, SCREEN_SHAPES[v].prune>(g, pk, S, ps, s)
     switch (shape) {
     case 0: LSR_SHAPE(0); break;
     case 1: LSR_SHAPE(1); break;
@@ -788,8 +1413,8 @@ static hipError_t launch_screen_c(int shape, const GridBufs &g, const uint16_t *
 }
 
 static hipError_t launch_screen(bool collect, int shape, const GridBufs &g, const uint16_t *pk,
-                                const ScreenScratch &S, hipStream_t s) {
-    return collect ? launch_screen_c<true>(shape, g, pk, S, s) : launch_screen_c<false>(shape, g, pk, S, s);
+                                const ScreenScratch &S, PairState *ps, hipStream_t s) {
+    return collect ? launch_screen_c<true>(shape, g, pk, S, ps, s) : launch_screen_c<false>(shape, g, pk, S, ps, s);
 }
 
 int screen_shapes() { return N_SCREEN_SHAPES; }
@@ -805,28 +1430,45 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     int npair = (g.nfrag + 1) / 2;
     hipLaunchKernelGGL(k_desc_mean, dim3(npair), dim3(256), 0, s, (const Frag *)g.frag, g.nfrag, (const float *)d.F,
                        (const int32_t *)d.valid, S.mean);
-    hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, d.pk, S.yq);
-    tmark("pack", s);
-    if ((e = launch_screen(false, shape, g, d.pk, S, s)) != hipSuccess) return e;
-    tmark("screen", s);
     if (shape < 0 || shape >= N_SCREEN_SHAPES) return hipErrorInvalidValue;
+    // descriptor-space row order: principal directions, Morton keys, one sort of (fragment, key)
+    hipLaunchKernelGGL(k_pca, dim3(npair), dim3(256), 0, s, (const Frag *)g.frag, g.nfrag, (const float *)d.F,
+                       (const int32_t *)d.valid, (const float *)S.mean, S.pca);
+    hipLaunchKernelGGL(k_mkey, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, (const float *)S.pca,
+                       S.key0, S.idx0);
+    size_t sb = S.sort_bytes;
+    if ((e = rocprim::radix_sort_pairs(S.sort_tmp, sb, S.key0, S.key1, S.idx0, (uint32_t *)S.perm, (size_t)g.ntot, 0,
+                                       sort_end_bit(g.nfrag), s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_rinv, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)S.perm, S.rinv);
+    hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, (const int32_t *)S.rinv,
+                       d.pk, S.yq);
+    if (SCREEN_SHAPES[shape].prune)
+        hipLaunchKernelGGL(k_chunk_stats, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag,
+                           (const Blk *)g.blk256, (const uint16_t *)d.pk, S.cpk, S.cst);
+    tmark("pack", s);
+    if ((e = launch_screen(false, shape, g, d.pk, S, ps, s)) != hipSuccess) return e;
+    tmark("screen", s);
     if (SCREEN_SHAPES[shape].t == 16)
         hipLaunchKernelGGL(k_rerank<16>, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
+                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.perm, (const int32_t *)S.c1,
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps, g.nblk256);
     else
         hipLaunchKernelGGL(k_rerank<32>, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.c1,
+                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.perm, (const int32_t *)S.c1,
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps, g.nblk256);
     tmark("rerank", s);
-    if ((e = launch_screen(true, shape, g, d.pk, S, s)) != hipSuccess) return e;
+    if ((e = launch_screen(true, shape, g, d.pk, S, ps, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rerank_list, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const float *)d.F, (const int32_t *)d.valid, (const int32_t *)S.fb_row,
                        (const int32_t *)S.fb_cnt, (const float *)S.thr, (const int32_t *)S.lst,
-                       (const int32_t *)S.lst_cnt, m.nn, m.dist, S.full_row, S.full_frag, S.full_cnt);
+                       (const int32_t *)S.lst_cnt, (const int32_t *)S.perm, m.nn, m.dist, S.full_row, S.full_frag,
+                       S.full_cnt);
     tmark("collect", s);
     unsigned grid = (unsigned)std::min<int64_t>(g.ntot, 2048);
     hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(256), 0, s, (const Frag *)g.frag, (const float *)d.F,

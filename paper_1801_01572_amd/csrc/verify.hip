@@ -102,6 +102,8 @@ __global__ void k_finalize(const Frag *frag, PairState *ps, int npairs, double d
     r.n_recip = (int64_t)S.n_recip;
     r.n_consistent = (int64_t)S.n_consistent;
     r.n_fallback_rows = (int64_t)S.n_fallback;
+    r.n_screen_chunks = (int64_t)S.scr_chunks;
+    r.n_screen_chunks_swept = (int64_t)S.scr_swept;
     r.iters = S.iters;
     if (S.status == LSR_DEGENERATE) r.status = LSR_DEGENERATE;
     else r.status = (r.n_consistent >= min_cons && r.inlier_ratio >= min_ratio) ? LSR_ACCEPTED : LSR_REJECTED;

@@ -9,6 +9,9 @@ DESC_RTOL = 1e-4          # descriptors: per-point relative L2 error
 POSE_TOL = 1e-5           # radians / metres
 NORMAL_TOL = 1e-10        # normals, FP64 on both sides, different eigen-solvers
 MARGIN = 1e-9             # decisions closer than this (bin units / dot) to a boundary are exempt
+# result fields that count the screen's work, not results: they differ between
+# precisions and launch-shape variants
+WORK_KEYS = ("n_fallback_rows", "n_screen_chunks", "n_screen_chunks_swept")
 
 
 def dev(a, dtype=None):

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import POSE_TOL, dev, pair, rot_err
+from gpu_helpers import POSE_TOL, WORK_KEYS, dev, pair, rot_err
 
 pytestmark = pytest.mark.gpu
 
@@ -59,7 +59,7 @@ def test_bf16_equals_fp32_end_to_end(L):
     a = L.register_pair(dev(pr.P), dev(pr.Q), L.default_params(precision=L.FP32))
     b = L.register_pair(dev(pr.P), dev(pr.Q), L.default_params(precision=L.BF16_SCREEN))
     for k in a:
-        if k != "n_fallback_rows":
+        if k not in WORK_KEYS:
             assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
 
 
@@ -111,6 +111,34 @@ def test_batch_tiny_fragments(L):
             for k in want[b]:
                 assert np.array_equal(np.asarray(got[b][k]), np.asarray(want[b][k])), (prec, sizes[b], k)
         print(prec, [g["status"] for g in got], flush=True)
+
+
+
+
+def test_pruned_screen_small_and_ragged(L):
+    """The pruned screen on fragments of 1-17 points, an empty Q, ragged and
+    equal sizes: bf16 == float32 in every result but the fallback count."""
+    sizes = [(1, 1), (3, 7), (15, 16), (17, 300), (300, 17), (100, 0), (2500, 2500), (9000, 700), (700, 9000)]
+    prs = [pair(2, 40 + k, (int(n1), max(int(n2), 1))) for k, (n1, n2) in enumerate(sizes)]
+    for pr, (_, n2) in zip(prs, sizes):
+        if n2 == 0:
+            pr.Q = pr.Q[:, :0].copy()
+    P, Q, offP, offQ = _batch(prs)
+    Pd, Qd = dev(P), dev(Q)
+    fp = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.FP32))
+    saved = L.get_tune()
+    try:
+        L.set_tune(L._lib.PRUNED_SCREEN, saved["consistency_shape"])
+        bf = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
+        bf2 = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
+    finally:
+        L.set_tune(saved["screen_shape"], saved["consistency_shape"])
+    for b in range(len(prs)):
+        for k in fp[b]:
+            if k not in WORK_KEYS:
+                assert np.array_equal(np.asarray(bf[b][k]), np.asarray(fp[b][k])), (sizes[b], k)
+            assert np.array_equal(np.asarray(bf2[b][k]), np.asarray(bf[b][k])), (sizes[b], k)
+    print("fallback rows", [r["n_fallback_rows"] for r in bf], flush=True)
 
 
 def test_deterministic(L):
@@ -216,7 +244,7 @@ def test_autotune_variants_agree(L):
                     ref = res
                 for b in range(len(prs)):
                     for k in ref[b]:
-                        if k != "n_fallback_rows":          # how many rows the screen certifies depends on its tiles
+                        if k not in WORK_KEYS:          # the screen's work depends on the variant
                             assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), (sv, cv, b, k)
         t = L.autotune(Pd, Qd, offP, offQ, prm, reps=1)
         assert 0 <= t["screen_shape"] < info["n_screen_shapes"]
@@ -228,7 +256,7 @@ def test_autotune_variants_agree(L):
         res = L.register_batch(Pd, Qd, offP, offQ, prm)
         for b in range(len(prs)):
             for k in ref[b]:
-                if k != "n_fallback_rows":
+                if k not in WORK_KEYS:
                     assert np.array_equal(np.asarray(res[b][k]), np.asarray(ref[b][k])), ("tuned", b, k)
         with pytest.raises(lib.LsrError):
             L.set_tune(info["n_screen_shapes"], 0)

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import synth
-from gpu_helpers import DESC_RTOL, POSE_TOL, desc_exempt, dev, rot_err
+from gpu_helpers import DESC_RTOL, POSE_TOL, WORK_KEYS, desc_exempt, dev, rot_err
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def _batch(prs, order):
     return P, Q, offP, offQ
 
 
-def _same(a, b, skip=("n_fallback_rows",)):
+def _same(a, b, skip=WORK_KEYS):
     for k in a:
         if k not in skip:
             assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
@@ -74,6 +74,34 @@ def test_benchmark_batch_256x50k(L, orc):
     for k in (0, 37):
         print(f"pair {k} vs oracle", flush=True)
         _vs_oracle(orc, bf[k], prs[k])
+
+
+def test_pruned_screen_64x50k(L):
+    """The screen variant that skips chunks by their centroid bounds, at the
+    benchmark's size: every pair bf16 == float32, and replays identical."""
+    prs = synth.make_batch(1, 64, n_points=50000)
+    P, Q, offP, offQ = _batch(prs, range(64))
+    Pd, Qd = dev(P), dev(Q)
+    fp = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.FP32))
+    saved = L.get_tune()
+    try:
+        L.set_tune(L._lib.PRUNED_SCREEN, saved["consistency_shape"])
+        bf = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
+        bf2 = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
+        L.set_tune(0, saved["consistency_shape"])
+        b0 = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
+    finally:
+        L.set_tune(saved["screen_shape"], saved["consistency_shape"])
+    for b in range(64):
+        _same(bf[b], fp[b])
+        _same(bf[b], bf2[b], skip=())
+        _same(bf[b], b0[b])
+        assert b0[b]["n_screen_chunks_swept"] == b0[b]["n_screen_chunks"] == bf[b]["n_screen_chunks"] > 0
+        assert fp[b]["n_screen_chunks"] == 0
+    swept = sum(r["n_screen_chunks_swept"] for r in bf) / sum(r["n_screen_chunks"] for r in bf)
+    print(f"fallback rows: pruned {sum(r['n_fallback_rows'] for r in bf)} plain "
+          f"{sum(r['n_fallback_rows'] for r in b0)}; pruned screen swept {swept:.3f} of the chunks", flush=True)
+    assert swept < 0.9
 
 
 def test_ragged_batch_with_negatives(L, orc):
