@@ -96,8 +96,9 @@ typedef struct {
     int64_t n_consistent;    /* correspondences kept by the consistency filter */
     int64_t n_inliers;
     int64_t n_fallback_rows; /* bf16 screen rows re-scanned exactly */
-    int64_t n_screen_chunks; /* bf16 screen: (256-query block, 128-row chunk) visits a full sweep makes (0: FP32) */
-    int64_t n_screen_chunks_swept; /* visits the screen made; below n_screen_chunks when it skips chunks */
+    int64_t n_screen_chunks; /* bf16 screen: (64-query group, 128-row chunk) visits a full sweep makes (0: FP32) */
+    int64_t n_screen_chunks_swept; /* visits the screen made (its centroid passes included); below
+                                      n_screen_chunks when it skips chunks */
     int32_t status;          /* LSR_ACCEPTED / LSR_REJECTED / LSR_DEGENERATE */
     int32_t iters;           /* pose iterations run */
 } lsr_result;

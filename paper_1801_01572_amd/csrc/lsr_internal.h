@@ -51,7 +51,7 @@ struct PairState {
     unsigned long long sum_d2_fixed;   // inlier squared distances, fixed point
     unsigned long long n_fallback;
     unsigned long long trials_passed;
-    unsigned long long scr_chunks;     // bf16 screen: (256-query block, 128-row chunk) visits of a full sweep
+    unsigned long long scr_chunks;     // bf16 screen: (64-query group, 128-row chunk) visits of a full sweep
     unsigned long long scr_swept;      // ... visits made (centroid passes included)
     double T[16];
     double energy, mu_final;

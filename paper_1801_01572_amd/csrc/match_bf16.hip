@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
     if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
         if (threadIdx.x == 0 && ps && Fq.pair >= 0) {
-            const unsigned long long nc = (unsigned long long)((Fc.n + PAD_ROWS - 1) / PAD_ROWS);
+            const unsigned long long nc = 4ull * (unsigned long long)((Fc.n + PAD_ROWS - 1) / PAD_ROWS);
             atomicAdd(&ps[Fq.pair].scr_chunks, nc);
             atomicAdd(&ps[Fq.pair].scr_swept, nc);
         }
@@ -746,13 +746,14 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS, "pruned screen shape");
     constexpr int CROWS = CH * 16;
     constexpr int U4 = CROWS * PK / 8;
+    static_assert(SW <= 4 && PR_NCH_MAX <= 4096 && SW * PR_NCH_MAX <= U4 * 16, "chunk entries: 12-bit index, wave mask");
     constexpr float MRG = 2.44140625e-4f;                       // 2^-12
     __shared__ __align__(16) uint4 ldsA[U4];
     __shared__ __align__(16) uint4 ldsB[U4];                    // between sweeps: chunk keys, then need flags
     __shared__ uint16_t seq[PR_NCH_MAX];                        // chunks of the current sweep
     __shared__ float redv[SW];
     __shared__ int redi[SW];
-    __shared__ int nseq;
+    __shared__ int nseq, nwsw;
     const int bi = (int)blockIdx.x;
     if (bi >= nblk) return;
     const Blk b = blk[bi];
@@ -831,10 +832,16 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
             for (int k = 0; k < SQB; ++k) c1[k] = up[k] ? tile : c1[k];
         }
     };
-    auto cid = [&](int c) { return prune ? (int)seq[c] : c; };
+    auto cid = [&](int c) { return prune ? (int)(seq[c] & 0xFFF) : c; };
+    auto swept_by_me = [&](int c) { return !prune || ((seq[c] >> (12 + wv)) & 1); };
     // one chunk of a sweep: start copying the next chunk into D, sweep the tiles of L
     auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) {
         if (c + 1 < len) stage(D, src + (int64_t)cid(c + 1) * U4);
+        if (!swept_by_me(c)) {                                    // wave-uniform
+            wait_copies();
+            __syncthreads();
+            return;
+        }
         const int tbase = cid(c) * CH;
         uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
 #pragma unroll 2
@@ -895,7 +902,8 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
         }
     };
 
-    int swept = nch;                                            // chunk visits made, centroid passes included
+    // (64-query group, 128-row chunk) visits made, centroid passes included
+    int swept = 4 * nch;
     if (!prune) {
         sweep(nch);
     } else {
@@ -935,7 +943,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
             if (threadIdx.x == 0) {
                 for (int w = 1; w < SW; ++w)
                     if (redv[w] < bv || (redv[w] == bv && redi[w] < bk)) { bv = redv[w]; bk = redi[w]; }
-                seq[r] = (uint16_t)bk;
+                seq[r] = (uint16_t)(bk | (((1u << SW) - 1u) << 12));  // every wavefront sweeps it
                 keys[bk] = __uint_as_float(0x7fffffffu);               // NaN: never the minimum again
             }
             __syncthreads();
@@ -952,10 +960,13 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
             const float dl = 7.8125e-3f * sqrtf(nq2[k] * D) + MRG * (nq2[k] + D) + 1.0e-7f;
             thn[k] = bq - dl;                                       // -inf when no row was screened
         }
-        uint8_t *need = (uint8_t *)ldsB;                            // 0 skip, 1 sweep, 2 already swept
-        for (int k = threadIdx.x; k < nch; k += SW * 64) need[k] = 0;
+        // need[w][k]: 0 wave w skips chunk k, 1 it sweeps it, 2 already swept
+        uint8_t *need = (uint8_t *)ldsB;
+        uint8_t *mine = need + wv * PR_NCH_MAX;
+        for (int k = threadIdx.x; k < SW * PR_NCH_MAX; k += SW * 64) need[k] = 0;
         __syncthreads();
-        if (threadIdx.x < k1) need[seq[threadIdx.x]] = 2;
+        if (threadIdx.x < k1)
+            for (int w = 0; w < SW; ++w) need[w * PR_NCH_MAX + (seq[threadIdx.x] & 0xFFF)] = 2;
         __syncthreads();
         cent_pass([&](const f32x4 *accs, int kc0) {
 #pragma unroll
@@ -964,7 +975,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
                 bool nd_any = false;
                 if (kc < nch) {
                     const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
-                    const bool done = need[kc] == 2;
+                    const bool done = mine[kc] == 2;
 #pragma unroll
                     for (int k = 0; k < SQB; ++k) {
                         if (!live[k] || st.x < 0.f) continue;        // dead query or empty chunk
@@ -978,27 +989,34 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
                     }
                 }
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(nd_any);
-                if (col == 0 && ((bal >> (16 * grp)) & 0xFFFFull)) need[kc] = 1;
+                if (col == 0 && ((bal >> (16 * grp)) & 0xFFFFull)) mine[kc] = 1;
             }
         });
-        // 3. the needed chunks, in index order
+        // 3. the chunks some wavefront needs, in index order, with the mask of
+        //    the wavefronts that need them in the entry's top bits (a
+        //    wavefront outside the mask stages the chunk but skips its MFMAs)
         if (wv == 0) {
-            int cnt = 0;
+            int cnt = 0, nw = 0;
             for (int base = 0; base < nch; base += 64) {
                 const int k = base + lane;
-                const bool f = k < nch && need[k] == 1;
+                uint32_t wm = 0;
+                if (k < nch)
+                    for (int w = 0; w < SW; ++w) wm |= (need[w * PR_NCH_MAX + k] == 1 ? 1u : 0u) << w;
+                const bool f = wm != 0;
                 const uint64_t m = __builtin_amdgcn_ballot_w64(f);
-                if (f) seq[cnt + (int)lanes_below_w(m)] = (uint16_t)k;
+                if (f) seq[cnt + (int)lanes_below_w(m)] = (uint16_t)(k | (wm << 12));
                 cnt += __popcll(m);
+                nw += __popc(wm);
             }
-            if (lane == 0) nseq = cnt;
+            for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, 64);
+            if (lane == 0) { nseq = cnt; nwsw = nw; }
         }
         __syncthreads();
         sweep(nseq);
-        swept = k1 + nseq + 2 * ((nch + CROWS - 1) / CROWS);
+        swept = (SW * k1 + nwsw + 2 * SW * ((nch + CROWS - 1) / CROWS)) * 4 / SW;
     }
     if (threadIdx.x == 0 && ps && Fq.pair >= 0) {
-        atomicAdd(&ps[Fq.pair].scr_chunks, (unsigned long long)nch);
+        atomicAdd(&ps[Fq.pair].scr_chunks, 4ull * (unsigned long long)nch);
         atomicAdd(&ps[Fq.pair].scr_swept, (unsigned long long)swept);
     }
 #pragma unroll
@@ -1157,7 +1175,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen32(const Frag *frag, const Bl
     if (prev_tile >= 0) epilogue(prev, prev_tile);
     if (!COLLECT) {
         if (threadIdx.x == 0 && ps && Fq.pair >= 0) {
-            const unsigned long long nc = (unsigned long long)((Fc.n + PAD_ROWS - 1) / PAD_ROWS);
+            const unsigned long long nc = 4ull * (unsigned long long)((Fc.n + PAD_ROWS - 1) / PAD_ROWS);
             atomicAdd(&ps[Fq.pair].scr_chunks, nc);
             atomicAdd(&ps[Fq.pair].scr_swept, nc);
         }
