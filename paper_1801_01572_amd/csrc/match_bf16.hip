@@ -754,7 +754,9 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ float redv[SW];
     __shared__ int redi[SW];
     __shared__ int nseq, nwsw;
-    const int bi = (int)blockIdx.x;
+    // XCD-aware order: consecutive blocks hold neighbouring queries in descriptor
+    // space, need mostly the same chunks, and then share one XCD's L2
+    const int bi = xcd_block(nblk);
     if (bi >= nblk) return;
     const Blk b = blk[bi];
     const Frag &Fq = frag[b.frag];
@@ -1390,7 +1392,7 @@ static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScr
                                nullptr, (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr,
                                S.lst, S.lst_cnt, nullptr);
         else if constexpr (PRUNE != 0)
-            hipLaunchKernelGGL((k_screen_pr<SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s, (const Frag *)g.frag,
+            hipLaunchKernelGGL((k_screen_pr<SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s, (const Frag *)g.frag,
                                (const Blk *)g.blk256, g.nblk256, pk, (const uint16_t *)S.cpk, (const float4 *)S.cst,
                                perm, S.c1, S.v2, S.v1, ps);
         else
