@@ -104,6 +104,28 @@ def test_pruned_screen_64x50k(L):
     assert swept < 0.9
 
 
+def test_pruned_screen_beyond_chunk_table(L):
+    """A 530,000-point fragment has more chunks (4141) than the pruned screen
+    tracks per block (4096): its partner's queries are swept exhaustively by
+    the same kernel, while its own queries are pruned against the 3,000-point
+    partner; bf16 == float32 either way."""
+    pr = synth.make_pair(1, 3, n_points=(530000, 3000))
+    Pd, Qd = dev(pr.P), dev(pr.Q)
+    offP = np.array([0, pr.P.shape[1]], np.int64)
+    offQ = np.array([0, pr.Q.shape[1]], np.int64)
+    fp = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.FP32))
+    saved = L.get_tune()
+    try:
+        L.set_tune(L._lib.PRUNED_SCREEN, saved["consistency_shape"])
+        bf = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
+    finally:
+        L.set_tune(saved["screen_shape"], saved["consistency_shape"])
+    _same(bf[0], fp[0])
+    print(f"swept {bf[0]['n_screen_chunks_swept']} of {bf[0]['n_screen_chunks']} visits, "
+          f"status {bf[0]['status']} recip {bf[0]['n_recip']}", flush=True)
+    assert bf[0]["n_recip"] > 0
+
+
 def test_ragged_batch_with_negatives(L, orc):
     prs = synth.make_batch(2, 24)
     P, Q, offP, offQ = _batch(prs, range(len(prs)))
