@@ -184,8 +184,10 @@ int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *c
 
 /* Launch-shape choice of a context (not a parameter of the method: every
  * variant computes the same bits).  screen_shape picks the bf16 screen's
- * waves per block, query blocks per wave and rows per LDS chunk;
- * consistency_shape picks the trial kernel's block width.  screen_ms and
+ * waves per block, query blocks per wave and rows per LDS chunk, and whether
+ * it skips the partner's 128-row chunks whose centroid bound shows they
+ * cannot matter (variant 5; the result's n_screen_chunks* fields count its
+ * work); consistency_shape picks the trial kernel's block width.  screen_ms and
  * consistency_ms: mean time of each variant in the last lsr_autotune call
  * (the whole bf16 matching stage, and the consistency stage), in ms. */
 typedef struct {
