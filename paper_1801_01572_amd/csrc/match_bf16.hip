@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 //     still covers every row the block does not screen;
 //  3. sweeps the chunks some live query needs.
 // Rows with a 2^24 key (invalid descriptors) sort last in each fragment.
-constexpr int PR_K = 4;
+constexpr int PR_K = 8;
 constexpr int PR_NCH_MAX = 4096;      // chunks one block can track (fragments up to 524288 rows); beyond: no pruning
 
 template <int SW, int SQB, int CH>
