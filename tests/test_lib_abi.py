@@ -56,3 +56,34 @@ def test_product_path_does_not_use_the_oracle():
 def test_oracle_library_builds():
     from oracle.build import build
     assert os.path.exists(build())
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of lsr_cloud, lsr_params, lsr_result and lsr_tune have
+    the header's sizes and field offsets (a mismatch would shift every field
+    the binding reads back)."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    from paper_1801_01572_amd import _lib
+    pairs = [("lsr_cloud", _lib.Cloud), ("lsr_params", _lib.Params), ("lsr_result", _lib.Result),
+             ("lsr_tune", _lib.Tune)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lsr.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
