@@ -1,15 +1,15 @@
 /*
  * lsr: global registration of two surface fragments on MI355X (gfx950).
  *
- * Problem (LoopSmart, Sec. III): given two fragments P and Q, each a set of
+ * Problem (LoopSmart, Sec. IV): given two fragments P and Q, each a set of
  * points with normals, return the rigid transform T_QP that aligns P to Q
  * (q ~ R p + t) if they can be aligned, starting from T_QP = I (Algorithm 1).
- * The path: radius neighbourhoods on a 3-D grid (Sec. III, eq. 1) ->
+ * The path: radius neighbourhoods on a 3-D grid (Sec. IV, eq. 1) ->
  * normals -> FPFH descriptors (the descriptor Algorithm 1 computes) ->
  * reciprocal nearest neighbours in descriptor space (Algorithm 1's
  * pre-matching cache, both directions) -> quadruple edge-ratio consistency
  * (Algorithm 1's pre-rejection, tau = 0.9) -> robust pose by graduated
- * non-convexity on the line-process energy of Sec. IV (eqs. 2-5: 6x6 normal
+ * non-convexity on the line-process energy of Sec. V (eqs. 2-5: 6x6 normal
  * equations with G = [-[p]x | I], solved in FP64) -> verification by inlier
  * ratio and fitness on the grid (Algorithm 1's hypothesis test) ->
  * accepted / rejected.
@@ -68,10 +68,10 @@ typedef struct {
 } lsr_cloud;
 
 typedef struct {
-    float r_normal;          /* normal-estimation radius, m (Sec. III uses 2x the leaf) */
-    float r_feature;         /* FPFH radius, m (Sec. III uses 5x the leaf) */
+    float r_normal;          /* normal-estimation radius, m (Sec. IV uses 2x the leaf) */
+    float r_feature;         /* FPFH radius, m (Sec. IV uses 5x the leaf) */
     float max_corr;          /* inlier distance delta and final kernel scale, m */
-    float tau;               /* polygon similarity threshold (Sec. III: 0.9) */
+    float tau;               /* polygon similarity threshold (Sec. IV: 0.9) */
     int64_t n_trials;        /* consistency trials per pair; <= 0: min(4e6, 100 N_P) */
     double gnc_div;          /* mu divisor of the non-convexity schedule */
     int32_t gnc_every;       /* iterations per mu step */
@@ -115,7 +115,7 @@ const char *lsr_last_error(const lsr_ctx *ctx);
 void lsr_default_params(lsr_params *p);
 
 /*
- * Register one fragment pair (Algorithm 1 and Sec. III's problem
+ * Register one fragment pair (Algorithm 1 and Sec. IV's problem
  * statement).  P and Q: device clouds with n >= 1 points.  d_out: device
  * pointer to one lsr_result.  Deterministic: the same inputs give the same
  * bits.
@@ -167,7 +167,7 @@ int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t n
 
 /*
  * Voxel downsampling of one cloud (Algorithm 1's first step, leaf size of
- * Sec. III): one output point per occupied voxel floor(coord / voxel) - the
+ * Sec. IV): one output point per occupied voxel floor(coord / voxel) - the
  * mean position and the normalised mean input normal (the first point's
  * normal when that mean vanishes) - ordered by ascending (kx, ky, kz).
  * out: six device arrays (x, y, z, nx, ny, nz) with room for c->n points;

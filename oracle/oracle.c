@@ -25,7 +25,7 @@ static inline double dist2(double xi, double yi, double zi, double xj, double yj
 }
 
 /* ------------------------------------------------------------------------ */
-/* O1: uniform grid over one cloud (Sec. III, eq. 1, with floor, cell >= r)  */
+/* O1: uniform grid over one cloud (Sec. IV, eq. 1, with floor, cell >= r)  */
 /* The grid is only an index: neighbour sets are the exact radius sets and   */
 /* are returned sorted by index, identical to the brute-force definition.    */
 /* ------------------------------------------------------------------------ */
@@ -173,7 +173,7 @@ int64_t orc_neighbors_brute(const float *x, const float *y, const float *z, int6
 }
 
 /* ------------------------------------------------------------------------ */
-/* O0: voxel downsample (Algorithm 1, first step; leaf size in Sec. III)     */
+/* O0: voxel downsample (Algorithm 1, first step; leaf size in Sec. IV)     */
 /* key = floor(coord / v) per axis; one output point per occupied voxel:     */
 /* the mean position (rounded to float) and the normalised mean normal;      */
 /* output ordered by ascending (kx, ky, kz).                                 */
@@ -224,7 +224,7 @@ int64_t orc_voxel(const float *x, const float *y, const float *z,
 
 /* ------------------------------------------------------------------------ */
 /* O2: normals by principal component analysis over N_rn(i) U {i}           */
-/* (normal estimation radius, Sec. III).  Symmetric 3x3 eigenproblem by      */
+/* (normal estimation radius, Sec. IV).  Symmetric 3x3 eigenproblem by      */
 /* cyclic Jacobi rotations; the eigenvector of the smallest eigenvalue,      */
 /* oriented to agree with the input normal.  Fewer than 3 points: the        */
 /* normalised input normal.                                                  */
@@ -549,14 +549,19 @@ void orc_tie_flags(const double *F, int64_t nP, const double *G, int64_t nQ,
 }
 
 /* ------------------------------------------------------------------------ */
-/* O6: quadruple consistency filter (Algorithm 1, hypothesis pre-rejection,  */
-/* tau = 0.9).  Counter-based randomness: the n-th output of SplitMix64      */
-/* (Steele, Lea and Flood, 2014) with the stated seed, n packed from         */
-/* (trial, slot, attempt).  The reciprocal correspondences C are listed in  */
-/* ascending P index; a slot draws c = ((r >> 32) |C|) >> 32, a uniform pick */
-/* from C, until it differs from the earlier slots (at most 64 attempts,     */
-/* else the trial is void).  The closed quadrilateral of the 4 points must   */
-/* have every edge ratio within tau in both directions.                      */
+/* O6: quadruple consistency filter (Section V, Algorithm 1: four points     */
+/* picked at random from P, their cached feature neighbours in Q, and the    */
+/* similar-polygon pre-rejection with tau = 0.9), used as a filter.          */
+/* Counter-based randomness: the n-th output r of SplitMix64 (Steele, Lea    */
+/* and Flood, 2014) with the stated seed, n = (trial << 8) | (slot << 6) |   */
+/* attempt.  A draw is the P index i = ((r >> 32) N_P) >> 32, uniform over  */
+/* [0, N_P); slot s keeps the first of at most 64 attempts whose i has a     */
+/* reciprocal correspondence and differs from the earlier slots, else the    */
+/* trial is void.  Keying the draws by P index keeps them local: whether one */
+/* point has a correspondence changes only the trials that draw that point. */
+/* The closed quadrilateral of the 4 points must have every squared edge     */
+/* ratio within tau^2 in both directions; a zero edge rejects.  Passing      */
+/* trials flag their 4 correspondences (an order-free OR).                   */
 /* ------------------------------------------------------------------------ */
 uint64_t orc_splitmix64(uint64_t seed, uint64_t n) {
     uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ULL;
@@ -570,14 +575,9 @@ int64_t orc_consistency(const float *px, const float *py, const float *pz, int64
                         const int32_t *nnQ, const uint8_t *mutual, int64_t n_trials,
                         float tau, uint64_t seed, uint8_t *flag) {
     double t2 = (double)tau * (double)tau;
-    memset(flag, 0, (size_t)nP);
+    memset(flag, 0, (size_t)(nP > 0 ? nP : 0));
     int64_t passed = 0;
     if (nP <= 0) return 0;
-    int64_t nC = 0;
-    for (int64_t i = 0; i < nP; ++i) nC += mutual[i] != 0;
-    if (nC == 0) return 0;
-    int64_t *Cl = (int64_t *)malloc(sizeof(int64_t) * (size_t)nC);
-    for (int64_t i = 0, c = 0; i < nP; ++i) if (mutual[i]) Cl[c++] = i;
     #pragma omp parallel for schedule(static) reduction(+ : passed)
     for (int64_t t = 0; t < n_trials; ++t) {
         int64_t id[4];
@@ -586,7 +586,8 @@ int64_t orc_consistency(const float *px, const float *py, const float *pz, int64
             int found = 0;
             for (int a = 0; a < 64; ++a) {
                 uint64_t r = orc_splitmix64(seed, ((uint64_t)t << 8) | ((uint64_t)s << 6) | (uint64_t)a);
-                int64_t i = Cl[(int64_t)(((r >> 32) * (uint64_t)nC) >> 32)];
+                int64_t i = (int64_t)(((r >> 32) * (uint64_t)nP) >> 32);
+                if (!mutual[i]) continue;
                 int dup = 0;
                 for (int u = 0; u < s; ++u) dup |= (id[u] == i);
                 if (dup) continue;
@@ -609,7 +610,6 @@ int64_t orc_consistency(const float *px, const float *py, const float *pz, int64
             flag[id[k]] = 1;
         }
     }
-    free(Cl);
     return passed;
 }
 
@@ -745,10 +745,18 @@ int32_t orc_gnc(const double *p, const double *q, int64_t m, const orc_params *p
     return status;
 }
 
+/* one row of a rigid transform applied to (x, y, z) with offset c, in the    */
+/* pinned order c + r0 x, then + r1 y, then + r2 z, each step one fma        */
+static inline double xform_row(const double *r, double x, double y, double z, double c) {
+    return fma(r[2], z, fma(r[1], y, fma(r[0], x, c)));
+}
+
 /* ------------------------------------------------------------------------ */
-/* O8: verification (Algorithm 1, hypothesis test: inlier ratio and         */
-/* fitness; 3D grid search of eq. 1).  Inlier: the nearest q within delta    */
-/* of T p (optionally with normal agreement).  ratio = inliers / N_P,        */
+/* O8: verification (Section V, Algorithm 1's hypothesis test: inlier      */
+/* ratio and fitness; 3D grid search of eq. 1).  Inlier: the nearest q       */
+/* within delta of T p (optionally with normal agreement (R n_p) . n_q >=    */
+/* cos).  T p and R n_p use the pinned fma order of xform_row, so the        */
+/* predicate is a function of the inputs alone.  ratio = inliers / N_P,      */
 /* fitness = RMS distance of inliers to their nearest q.                     */
 /* ------------------------------------------------------------------------ */
 void orc_verify(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
@@ -764,7 +772,7 @@ void orc_verify(const float *px, const float *py, const float *pz, const double 
         #pragma omp for schedule(dynamic, 256)
         for (int64_t i = 0; i < nP; ++i) {
             double p[3] = {px[i], py[i], pz[i]}, tp[3];
-            for (int a = 0; a < 3; ++a) tp[a] = T[4 * a] * p[0] + T[4 * a + 1] * p[1] + T[4 * a + 2] * p[2] + T[4 * a + 3];
+            for (int a = 0; a < 3; ++a) tp[a] = xform_row(T + 4 * a, p[0], p[1], p[2], T[4 * a + 3]);
             int64_t k = grid_query(&g, qx, qy, qz, tp[0], tp[1], tp[2], d2max, -1.0, tmp, cap);
             while (k > cap) { cap = 2 * k; tmp = (int64_t *)realloc(tmp, sizeof(int64_t) * cap);
                               k = grid_query(&g, qx, qy, qz, tp[0], tp[1], tp[2], d2max, -1.0, tmp, cap); }
@@ -774,8 +782,8 @@ void orc_verify(const float *px, const float *py, const float *pz, const double 
                 if (normal_check) {
                     const double *ni = nP_ + 3 * i, *nj = nQ_ + 3 * j;
                     double rn[3];
-                    for (int a = 0; a < 3; ++a) rn[a] = T[4 * a] * ni[0] + T[4 * a + 1] * ni[1] + T[4 * a + 2] * ni[2];
-                    if (rn[0] * nj[0] + rn[1] * nj[1] + rn[2] * nj[2] < cth) continue;
+                    for (int a = 0; a < 3; ++a) rn[a] = xform_row(T + 4 * a, ni[0], ni[1], ni[2], 0.0);
+                    if (fma(rn[2], nj[2], fma(rn[1], nj[1], rn[0] * nj[0])) < cth) continue;
                 }
                 double d2 = dist2(tp[0], tp[1], tp[2], qx[j], qy[j], qz[j]);
                 if (d2 < best) best = d2;

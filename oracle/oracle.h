@@ -1,7 +1,7 @@
 /*
  * CPU FP64 oracle for global registration of two surface fragments
- * (LoopSmart, Sec. III "Fast global point cloud registration on GPU",
- * Algorithm 1, and the robust line-process energy of Sec. IV, eqs. 2-5).
+ * (LoopSmart, Sec. IV "Fast global point cloud registration on GPU",
+ * Algorithm 1, and the robust line-process energy of Sec. V, eqs. 2-5).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
  * correct definition that the GPU path is checked against.  Only the test

@@ -1,4 +1,4 @@
-"""MI355X-native global registration of surface fragments (LoopSmart, Sec. III).
+"""MI355X-native global registration of surface fragments (LoopSmart, Sec. IV).
 
 Thin Python binding of the C ABI in ``include/lsr.h`` (``liblsr.so``, HIP for
 gfx950).  Argument marshalling only: every step of the path runs in the HIP

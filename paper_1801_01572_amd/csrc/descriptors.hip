@@ -1,7 +1,7 @@
 // Per-point geometry on the grid: normals, SPFH and FPFH.
 //
 // Normals: principal component analysis of the radius-r_normal neighbourhood
-// plus the point (normal estimation radius of Sec. III), FP64, oriented by
+// plus the point (normal estimation radius of Sec. IV), FP64, oriented by
 // the input normal; fewer than 3 points keep the normalised input normal.
 //
 // FPFH (the descriptor of Algorithm 1; definition from the cited FPFH work):

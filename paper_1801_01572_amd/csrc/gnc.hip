@@ -1,5 +1,5 @@
 // Robust pose by graduated non-convexity on the line-process energy of
-// Sec. IV restricted to one fragment pair:
+// Sec. V restricted to one fragment pair:
 //   E_mu(T, l) = sum_c l_c |R p_c + t - q_c|^2 + mu sum_c (sqrt(l_c) - 1)^2   (eqs. 2-4)
 // For fixed T the optimal weight is l_c = (mu / (mu + s_c))^2.  Each
 // iteration linearises with G_c = [ -[p'_c]x | I ] (eq. 5), p'_c = R p_c + t,

@@ -1,4 +1,4 @@
-// 3-D grid index over every fragment of a batch (Sec. III, eq. 1: cell index =
+// 3-D grid index over every fragment of a batch (Sec. IV, eq. 1: cell index =
 // (coordinate - origin) / cell length, taken with floor).  The cell edge is at
 // least the search radius, so a radius query visits the 27 cells around the
 // query's cell and finds the exact radius set.

@@ -1,4 +1,4 @@
-// Voxel downsampling (Algorithm 1's first step; leaf size of Sec. III).
+// Voxel downsampling (Algorithm 1's first step; leaf size of Sec. IV).
 //
 // key = (floor(x / v), floor(y / v), floor(z / v)) in double precision; one
 // output point per occupied voxel: the mean position (double sums in

@@ -1,7 +1,7 @@
 """Seeded synthetic fragment pairs for global registration tests and benchmarks.
 
 The paper evaluates on pairwise-registration fragments fused from augmented
-ICL-NUIM sequences (Sec. III, Table 1).  Those fragments are not available
+ICL-NUIM sequences (Sec. IV, Table 1).  Those fragments are not available
 here, so this module builds stand-ins with the same structure: indoor
 surfaces (planes, boxes, cylinders, spheres) sampled at sensor resolution,
 cropped into two partially overlapping fragments, perturbed by Gaussian noise,

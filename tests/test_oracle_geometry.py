@@ -1,5 +1,5 @@
 """Pins of the CPU oracle's geometric stages against brute force, closed forms
-and invariances (radius neighbourhoods of Sec. III eq. 1; normals; FPFH as
+and invariances (radius neighbourhoods of Sec. IV eq. 1; normals; FPFH as
 cited by Algorithm 1; voxel downsampling of Algorithm 1's first step)."""
 import os
 
@@ -160,6 +160,29 @@ def test_spfh_hand_example(orc):
         want[[int(t) for t in r[1:]]] = 1.0
         assert np.array_equal(S[i], want)
     assert (k == 1).all() and (kp == 1).all()
+
+
+def _star_4pt():
+    xyz = np.array([[0, 1 / 64, 0, -13 / 512], [0, 0, 3 / 128, 0], [0, 0, 0, 0]], np.float32)
+    nrm = np.array([[0, 0, 1.0], [0.6, 0, 0.8], [0, 0.8, 0.6], [1.0, 0, 0]])
+    return xyz, nrm, 0.027
+
+
+def test_fpfh_hand_example(orc):
+    """Four-point star with unequal distances, unequal neighbour SPFHs and one
+    skipped pair (k_A = 3 neighbours, 2 counted pairs): the hand-derived FPFH
+    of tests/golden/fpfh_star_4pt.txt."""
+    from fractions import Fraction
+    rows = [l.split() for l in open(os.path.join(GOLD, "fpfh_star_4pt.txt")) if not l.startswith("#")]
+    xyz, nrm, r = _star_4pt()
+    want = np.zeros((4, 33))
+    for i, c, v in rows:
+        want[int(i), int(c)] = float(Fraction(v))
+    S, k, kp, _ = orc.spfh(xyz, nrm, r)
+    assert list(k) == [3, 1, 1, 1] and list(kp) == [2, 1, 1, 0]
+    F, valid, _, _ = orc.fpfh(xyz, nrm, r)
+    assert valid.all()
+    assert np.abs(F - want).max() <= 1e-14
 
 
 def test_fpfh_plane_indicator(orc):

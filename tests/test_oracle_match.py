@@ -69,17 +69,17 @@ def test_splitmix64_published_vector(orc):
 
 def _drawn_quads(orc, nP, mutual, n_trials, seed):
     """The quadruples the sampler draws, reconstructed from its generator:
-    uniform picks from the reciprocal correspondences in ascending P order."""
+    uniform P indices, redrawn while the index has no reciprocal
+    correspondence or repeats an earlier slot (at most 64 attempts)."""
     quads = []
-    C = [i for i in range(nP) if mutual[i]]
     for t in range(n_trials):
         ids = []
         for s in range(4):
             got = None
             for a in range(64):
                 r = orc.splitmix64(seed, (t << 8) | (s << 6) | a)
-                i = C[((r >> 32) * len(C)) >> 32]
-                if i not in ids:
+                i = ((r >> 32) * nP) >> 32
+                if mutual[i] and i not in ids:
                     got = i
                     break
             if got is None:
@@ -152,3 +152,57 @@ def test_consistency_matches_enumeration(orc):
             npass += 1
             want[q] = True
     assert passed == npass and np.array_equal(f, want) and 0 < npass < T
+
+
+def test_consistency_draws_are_local(orc):
+    """Draws are keyed by P index: removing one correspondence changes only the
+    trials that draw its index, so the flags elsewhere follow from the trials
+    that never touch it.  Checked against the reconstructed draws: every
+    trial that avoids the removed index keeps its verdict."""
+    rng = np.random.default_rng(21)
+    n = 60
+    P = rng.uniform(0, 1, (3, n)).astype(np.float32)
+    Q = (P + rng.normal(0, 0.01, (3, n))).astype(np.float32)
+    nnQ = np.arange(n, dtype=np.int32)
+    mut = rng.random(n) < 0.5
+    k = int(np.nonzero(mut)[0][3])
+    mut2 = mut.copy()
+    mut2[k] = False
+    T, seed = 400, 7
+    qa = _drawn_quads(orc, n, mut, T, seed)
+    qb = _drawn_quads(orc, n, mut2, T, seed)
+    touched = [t for t in range(T) if (qa[t] is not None and k in qa[t]) or qa[t] != qb[t]]
+    for t in range(T):
+        if qa[t] is not None and k not in qa[t]:
+            assert qa[t] == qb[t]                           # a trial that avoids k draws the same points
+    assert 0 < len(touched) < T // 2
+    fa, _ = orc.consistency(P, Q, nnQ, mut, T, 0.9, seed)
+    fb, _ = orc.consistency(P, Q, nnQ, mut2, T, 0.9, seed)
+    assert not fb[k]
+    # a flag can only change at points that appear in a touched trial
+    pts = set()
+    for t in touched:
+        for q in (qa[t], qb[t]):
+            if q is not None:
+                pts.update(q)
+    diff = set(np.nonzero(fa != fb)[0].tolist())
+    assert diff <= pts
+
+
+def test_consistency_draw_distribution(orc):
+    """Each slot's accepted index is uniform over the points with a
+    correspondence (rejection sampling from a uniform P index): the slot-0
+    histogram over 20000 trials passes a chi-square test, and points without a
+    correspondence are never drawn."""
+    n = 50
+    mut = np.zeros(n, bool)
+    mut[::3] = True
+    counts = np.zeros(n)
+    for q in _drawn_quads(orc, n, mut, 20000, 3):
+        assert q is not None and all(mut[i] for i in q) and len(set(q)) == 4
+        counts[q[0]] += 1
+    c = counts[mut]
+    e = c.sum() / len(c)
+    chi2 = ((c - e) ** 2 / e).sum()
+    assert counts[~mut].sum() == 0
+    assert chi2 < 45                                        # 16 dof: p ~ 1e-4

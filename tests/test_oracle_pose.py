@@ -168,6 +168,51 @@ def test_verify_equals_brute_force(orc):
     assert abs(fit - np.sqrt(d2[inl].mean())) < 1e-12
 
 
+def test_verify_normal_check_equals_brute_force(orc):
+    """Inlier with the normal check: the nearest q within delta among those
+    whose normal agrees with R n_p (cosine >= the threshold).  Q is T P plus
+    noise with normals R n_p, except a third of them flipped: with the check
+    those points are outliers, without it inliers; a transposed rotation (large
+    angle) rejects most points.  Random clouds and normals are checked the same
+    way against brute force."""
+    rng = np.random.default_rng(16)
+    delta, cth = 0.006, 0.5
+    a = np.array([1.0, -2.0, 0.5]) / np.linalg.norm([1.0, -2.0, 0.5])
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    T = np.eye(4)
+    T[:3, :3] = np.eye(3) + np.sin(1.2) * K + (1 - np.cos(1.2)) * K @ K   # R^2 turns normals by 2.4 rad
+    T[:3, 3] = [0.03, -0.02, 0.04]
+    R = T[:3, :3]
+    cases = []
+    P = rng.uniform(0, 0.25, (3, 1200)).astype(np.float32)
+    nP = rng.normal(size=(1200, 3)); nP /= np.linalg.norm(nP, axis=1, keepdims=True)
+    Q = ((R @ P.astype(np.float64)) + T[:3, 3:4] + rng.normal(0, 0.001, (3, 1200))).astype(np.float32)
+    nQ = nP @ R.T
+    flip = rng.random(1200) < 1 / 3
+    nQ[flip] *= -1
+    cases.append((P, nP, Q, nQ, True))
+    P2 = rng.uniform(0, 0.25, (3, 1000)).astype(np.float32)
+    Q2 = rng.uniform(0, 0.25, (3, 2200)).astype(np.float32)
+    n1 = rng.normal(size=(1000, 3)); n1 /= np.linalg.norm(n1, axis=1, keepdims=True)
+    n2 = rng.normal(size=(2200, 3)); n2 /= np.linalg.norm(n2, axis=1, keepdims=True)
+    cases.append((P2, n1, Q2, n2, False))
+    d2max = np.float64(np.float32(delta)) ** 2
+    for P, nP, Q, nQ, constructed in cases:
+        ni, ratio, fit = orc.verify(P, nP, Q, nQ, T, delta, normal_check=1, normal_cos=cth)
+        tp = (R @ P.astype(np.float64)) + T[:3, 3:4]
+        d2 = ((tp[:, :, None] - Q.astype(np.float64)[:, None, :]) ** 2).sum(0)
+        agree = (nP @ R.T) @ nQ.T >= np.float64(np.float32(cth))
+        d2n = np.where(agree, d2, np.inf).min(1)
+        inl = d2n <= d2max
+        assert ni == inl.sum() and abs(ratio - inl.mean()) < 1e-15
+        assert abs(fit - np.sqrt(d2n[inl].mean())) < 1e-12
+        ni0, _, _ = orc.verify(P, nP, Q, nQ, T, delta, normal_check=0, normal_cos=cth)
+        assert ni0 == (d2.min(1) <= d2max).sum()
+        if constructed:
+            wrongR = (np.where((nP @ R) @ nQ.T >= cth, d2, np.inf).min(1) <= d2max).sum()
+            assert ni0 > 0.95 * len(flip) and abs(ni - (~flip).sum()) < 0.05 * len(flip) and wrongR < 0.8 * ni
+
+
 def _copy_pair(seed, n=20000, sigma=0.001):
     """P: a rigidly moved, re-noised subset of Q's samples (a controlled case
     with exact underlying correspondences)."""
