@@ -50,6 +50,8 @@ def lib():
         for f in ("orc_neighbors_grid", "orc_neighbors_brute", "orc_voxel", "orc_consistency"):
             getattr(_LIB, f).restype = C.c_int64
         _LIB.orc_gnc.restype = C.c_int32
+        _LIB.orc_rigid_fit.restype = C.c_int32
+        _LIB.orc_ransac.restype = C.c_int32
         _LIB.orc_register_pair.restype = C.c_int32
         _LIB.orc_align_loss.restype = C.c_double
     return _LIB
@@ -203,6 +205,38 @@ def verify(P, nrmP, Q, nrmQ, T, delta, normal_check=0, normal_cos=0.8660254):
                      _p(T), C.c_float(delta), C.c_int32(normal_check), C.c_float(normal_cos),
                      C.byref(ni), C.byref(ratio), C.byref(fit))
     return ni.value, ratio.value, fit.value
+
+
+class RansacInfo(C.Structure):
+    _fields_ = [("n_survivors", C.c_int64), ("n_fitted", C.c_int64), ("best", C.c_int64), ("second", C.c_int64),
+                ("n_inliers", C.c_int64), ("second_inliers", C.c_int64), ("ratio", C.c_double),
+                ("fitness", C.c_double), ("sum_d2", C.c_double), ("second_sum_d2", C.c_double)]
+
+
+def rigid_fit(p, q):
+    """Least-squares rigid transform of (m,3) pairs (q ~ R p + t): (ok, T 4x4)."""
+    p = _f64(p); q = _f64(q)
+    T = np.zeros(16)
+    ok = lib().orc_rigid_fit(_p(p), _p(q), C.c_int64(len(p)), _p(T))
+    return bool(ok), T.reshape(4, 4)
+
+
+def ransac(P, nrmP, Q, nrmQ, nnQ, n_hyp, tau=0.9, seed=0x1801015720, delta=0.015, normal_check=1,
+           normal_cos=0.8660254, min_ratio=0.15):
+    """RANSAC consensus (Algorithm 1) on the one-directional cache nnQ:
+    (status, T 4x4, info dict)."""
+    P = _f32(P); Q = _f32(Q)
+    nrmP = _f64(nrmP) if nrmP is not None else np.zeros((P.shape[1], 3))
+    nrmQ = _f64(nrmQ) if nrmQ is not None else np.zeros((Q.shape[1], 3))
+    nnQ = np.ascontiguousarray(nnQ, np.int32)
+    T = np.zeros(16)
+    info = RansacInfo()
+    st = lib().orc_ransac(_p(P[0]), _p(P[1]), _p(P[2]), _p(nrmP), C.c_int64(P.shape[1]),
+                          _p(Q[0]), _p(Q[1]), _p(Q[2]), _p(nrmQ), C.c_int64(Q.shape[1]),
+                          _p(nnQ), C.c_int64(n_hyp), C.c_float(tau), C.c_uint64(seed), C.c_float(delta),
+                          C.c_int32(normal_check), C.c_float(normal_cos), C.c_float(min_ratio), _p(T),
+                          C.byref(info))
+    return int(st), T.reshape(4, 4), {k: getattr(info, k) for k, _ in RansacInfo._fields_}
 
 
 def align_loss(p, q, T, mu, grad=True):

@@ -759,6 +759,33 @@ static inline double xform_row(const double *r, double x, double y, double z, do
 /* predicate is a function of the inputs alone.  ratio = inliers / N_P,      */
 /* fitness = RMS distance of inliers to their nearest q.                     */
 /* ------------------------------------------------------------------------ */
+/* Squared distance from T p_i to its nearest q_j within delta (with the
+ * normal check when asked), or INFINITY when there is none; g is Q's grid
+ * with cell >= delta. */
+static double inlier_d2(const ogrid *g, const float *px, const float *py, const float *pz, const double *nP_,
+                        int64_t i, const float *qx, const float *qy, const float *qz, const double *nQ_,
+                        const double *T, double d2max, int32_t normal_check, double cth,
+                        int64_t **tmp, int64_t *cap) {
+    double p[3] = {px[i], py[i], pz[i]}, tp[3];
+    for (int a = 0; a < 3; ++a) tp[a] = xform_row(T + 4 * a, p[0], p[1], p[2], T[4 * a + 3]);
+    int64_t k = grid_query(g, qx, qy, qz, tp[0], tp[1], tp[2], d2max, -1.0, *tmp, *cap);
+    while (k > *cap) { *cap = 2 * k; *tmp = (int64_t *)realloc(*tmp, sizeof(int64_t) * (size_t)*cap);
+                       k = grid_query(g, qx, qy, qz, tp[0], tp[1], tp[2], d2max, -1.0, *tmp, *cap); }
+    double best = INFINITY;
+    for (int64_t s = 0; s < k; ++s) {
+        int64_t j = (*tmp)[s];
+        if (normal_check) {
+            const double *ni = nP_ + 3 * i, *nj = nQ_ + 3 * j;
+            double rn[3];
+            for (int a = 0; a < 3; ++a) rn[a] = xform_row(T + 4 * a, ni[0], ni[1], ni[2], 0.0);
+            if (fma(rn[2], nj[2], fma(rn[1], nj[1], rn[0] * nj[0])) < cth) continue;
+        }
+        double d2 = dist2(tp[0], tp[1], tp[2], qx[j], qy[j], qz[j]);
+        if (d2 < best) best = d2;
+    }
+    return best <= d2max ? best : INFINITY;
+}
+
 void orc_verify(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
                 const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
                 const double *T, float delta, int32_t normal_check, float normal_cos,
@@ -771,23 +798,7 @@ void orc_verify(const float *px, const float *py, const float *pz, const double 
         int64_t cap = 4096; int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * cap);
         #pragma omp for schedule(dynamic, 256)
         for (int64_t i = 0; i < nP; ++i) {
-            double p[3] = {px[i], py[i], pz[i]}, tp[3];
-            for (int a = 0; a < 3; ++a) tp[a] = xform_row(T + 4 * a, p[0], p[1], p[2], T[4 * a + 3]);
-            int64_t k = grid_query(&g, qx, qy, qz, tp[0], tp[1], tp[2], d2max, -1.0, tmp, cap);
-            while (k > cap) { cap = 2 * k; tmp = (int64_t *)realloc(tmp, sizeof(int64_t) * cap);
-                              k = grid_query(&g, qx, qy, qz, tp[0], tp[1], tp[2], d2max, -1.0, tmp, cap); }
-            double best = INFINITY;
-            for (int64_t s = 0; s < k; ++s) {
-                int64_t j = tmp[s];
-                if (normal_check) {
-                    const double *ni = nP_ + 3 * i, *nj = nQ_ + 3 * j;
-                    double rn[3];
-                    for (int a = 0; a < 3; ++a) rn[a] = xform_row(T + 4 * a, ni[0], ni[1], ni[2], 0.0);
-                    if (fma(rn[2], nj[2], fma(rn[1], nj[1], rn[0] * nj[0])) < cth) continue;
-                }
-                double d2 = dist2(tp[0], tp[1], tp[2], qx[j], qy[j], qz[j]);
-                if (d2 < best) best = d2;
-            }
+            double best = inlier_d2(&g, px, py, pz, nP_, i, qx, qy, qz, nQ_, T, d2max, normal_check, cth, &tmp, &cap);
             if (best <= d2max) { cnt += 1; ss += best; }
         }
         free(tmp);
@@ -796,6 +807,192 @@ void orc_verify(const float *px, const float *py, const float *pz, const double 
     *n_inliers = cnt;
     *ratio = nP > 0 ? (double)cnt / (double)nP : 0.0;
     *fitness = cnt > 0 ? sqrt(ss / (double)cnt) : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* RANSAC consensus (Section IV, Algorithm 1), the paper's own pose stage.   */
+/* Hypothesis t draws four distinct points of P as the consistency filter   */
+/* does (same generator and counter layout), except that a point is eligible */
+/* when its descriptor has a nearest neighbour in Q (the one-directional     */
+/* pre-matching cache nnQ), not only a reciprocal one.  Its correspondences  */
+/* q_k = Q[nnQ(p_k)].  Pre-rejection: the similar-polygon test of O6.        */
+/* Survivors get the least-squares rigid transform of their 4 pairs (Horn's  */
+/* closed form with unit quaternions, 1987), then are tested on all of P:     */
+/* inliers as in O8 (with the normal check, which the paper moves from       */
+/* pre-rejection into this test), ratio = inliers / N_P.  The result is the  */
+/* hypothesis with the most inliers; equal counts go to the smaller sum of   */
+/* inlier squared distances (smaller RMS), then to the lower index.  It is   */
+/* accepted when its ratio reaches min_ratio.  A fit whose largest two       */
+/* quaternion eigenvalues are closer than 1e-9 of the largest magnitude      */
+/* (collinear or coincident points) is rejected.                             */
+/* ------------------------------------------------------------------------ */
+static void jacobi4(double A[4][4], double w[4], double V[4][4]) {
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) V[i][j] = (i == j);
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0, tr = 0;
+        for (int p = 0; p < 4; ++p) { tr += fabs(A[p][p]); for (int q = p + 1; q < 4; ++q) off += A[p][q] * A[p][q]; }
+        if (off == 0.0 || sqrt(off) <= 1e-18 * tr) break;
+        for (int p = 0; p < 3; ++p) for (int q = p + 1; q < 4; ++q) {
+            double apq = A[p][q];
+            if (apq == 0.0) continue;
+            double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+            double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+            for (int k = 0; k < 4; ++k) {
+                double akp = A[k][p], akq = A[k][q];
+                A[k][p] = c * akp - s * akq;
+                A[k][q] = s * akp + c * akq;
+            }
+            for (int k = 0; k < 4; ++k) {
+                double apk = A[p][k], aqk = A[q][k];
+                A[p][k] = c * apk - s * aqk;
+                A[q][k] = s * apk + c * aqk;
+            }
+            for (int k = 0; k < 4; ++k) {
+                double vkp = V[k][p], vkq = V[k][q];
+                V[k][p] = c * vkp - s * vkq;
+                V[k][q] = s * vkp + c * vkq;
+            }
+        }
+    }
+    for (int i = 0; i < 4; ++i) w[i] = A[i][i];
+}
+
+/* Least-squares rigid transform (R, t) with q_k ~ R p_k + t from m pairs
+ * (Horn 1987).  Returns 0 when the optimal rotation is not unique. */
+int32_t orc_rigid_fit(const double *p, const double *q, int64_t m, double *T) {
+    double pm[3] = {0, 0, 0}, qm[3] = {0, 0, 0};
+    for (int64_t k = 0; k < m; ++k) for (int a = 0; a < 3; ++a) { pm[a] += p[3 * k + a]; qm[a] += q[3 * k + a]; }
+    for (int a = 0; a < 3; ++a) { pm[a] /= (double)m; qm[a] /= (double)m; }
+    double S[3][3] = {{0}};
+    for (int64_t k = 0; k < m; ++k)
+        for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b)
+            S[a][b] += (p[3 * k + a] - pm[a]) * (q[3 * k + b] - qm[b]);
+    double N[4][4] = {
+        {S[0][0] + S[1][1] + S[2][2], S[1][2] - S[2][1], S[2][0] - S[0][2], S[0][1] - S[1][0]},
+        {S[1][2] - S[2][1], S[0][0] - S[1][1] - S[2][2], S[0][1] + S[1][0], S[2][0] + S[0][2]},
+        {S[2][0] - S[0][2], S[0][1] + S[1][0], -S[0][0] + S[1][1] - S[2][2], S[1][2] + S[2][1]},
+        {S[0][1] - S[1][0], S[2][0] + S[0][2], S[1][2] + S[2][1], -S[0][0] - S[1][1] + S[2][2]}};
+    double w[4], V[4][4];
+    jacobi4(N, w, V);
+    int i1 = 0;
+    for (int i = 1; i < 4; ++i) if (w[i] > w[i1]) i1 = i;
+    double w2 = -INFINITY, wmax = 0;
+    for (int i = 0; i < 4; ++i) { if (i != i1 && w[i] > w2) w2 = w[i]; if (fabs(w[i]) > wmax) wmax = fabs(w[i]); }
+    for (int i = 0; i < 16; ++i) T[i] = (i % 5 == 0);
+    if (!(w[i1] - w2 > 1e-9 * wmax)) return 0;
+    double qw = V[0][i1], qx = V[1][i1], qy = V[2][i1], qz = V[3][i1];
+    double nq = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= nq; qx /= nq; qy /= nq; qz /= nq;
+    double R[3][3] = {
+        {qw * qw + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+        {2 * (qy * qx + qw * qz), qw * qw - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - qw * qx)},
+        {2 * (qz * qx - qw * qy), 2 * (qz * qy + qw * qx), qw * qw - qx * qx - qy * qy + qz * qz}};
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) T[4 * a + b] = R[a][b];
+        T[4 * a + 3] = qm[a] - (R[a][0] * pm[0] + R[a][1] * pm[1] + R[a][2] * pm[2]);
+    }
+    return 1;
+}
+
+int32_t orc_ransac(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
+                   const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
+                   const int32_t *nnQ, int64_t n_hyp, float tau, uint64_t seed, float delta,
+                   int32_t normal_check, float normal_cos, float min_ratio,
+                   double *T, orc_ransac_info *info) {
+    memset(info, 0, sizeof *info);
+    info->best = info->second = -1;
+    for (int i = 0; i < 16; ++i) T[i] = (i % 5 == 0);
+    if (nP <= 0) return ORC_DEGENERATE;
+    double t2 = (double)tau * (double)tau, d2max = (double)delta * (double)delta, cth = (double)normal_cos;
+    /* hypotheses and pre-rejection */
+    int64_t *surv = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_hyp > 0 ? n_hyp : 1));
+    int64_t (*mem)[4] = malloc(sizeof(int64_t[4]) * (size_t)(n_hyp > 0 ? n_hyp : 1));
+    uint8_t *ok = (uint8_t *)calloc((size_t)(n_hyp > 0 ? n_hyp : 1), 1);
+    #pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < n_hyp; ++t) {
+        int64_t id[4];
+        int good = 1;
+        for (int s = 0; s < 4 && good; ++s) {
+            int found = 0;
+            for (int a = 0; a < 64; ++a) {
+                uint64_t r = orc_splitmix64(seed, ((uint64_t)t << 8) | ((uint64_t)s << 6) | (uint64_t)a);
+                int64_t i = (int64_t)(((r >> 32) * (uint64_t)nP) >> 32);
+                if (nnQ[i] < 0) continue;
+                int dup = 0;
+                for (int u = 0; u < s; ++u) dup |= (id[u] == i);
+                if (dup) continue;
+                id[s] = i; found = 1; break;
+            }
+            good = found;
+        }
+        for (int k = 0; k < 4 && good; ++k) {
+            int64_t i0 = id[k], i1 = id[(k + 1) & 3];
+            int64_t j0 = nnQ[i0], j1 = nnQ[i1];
+            double a = dist2(px[i0], py[i0], pz[i0], px[i1], py[i1], pz[i1]);
+            double b = dist2(qx[j0], qy[j0], qz[j0], qx[j1], qy[j1], qz[j1]);
+            if (a == 0.0 || b == 0.0 || a < t2 * b || b < t2 * a) good = 0;
+        }
+        if (good) { ok[t] = 1; for (int k = 0; k < 4; ++k) mem[t][k] = id[k]; }
+    }
+    int64_t ns = 0;
+    for (int64_t t = 0; t < n_hyp; ++t) if (ok[t]) surv[ns++] = t;
+    info->n_survivors = ns;
+    /* fit and test every survivor */
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    double *ssum = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
+    double *Ts = (double *)malloc(sizeof(double) * 16 * (size_t)(ns > 0 ? ns : 1));
+    ogrid g; grid_build(&g, qx, qy, qz, nQ, (double)delta);
+    int64_t nfit = 0;
+    #pragma omp parallel reduction(+ : nfit)
+    {
+        int64_t cap = 4096; int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * cap);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t h = 0; h < ns; ++h) {
+            const int64_t *id = mem[surv[h]];
+            double pp[12], qq[12];
+            for (int k = 0; k < 4; ++k) {
+                int64_t i = id[k], j = nnQ[i];
+                pp[3 * k] = px[i]; pp[3 * k + 1] = py[i]; pp[3 * k + 2] = pz[i];
+                qq[3 * k] = qx[j]; qq[3 * k + 1] = qy[j]; qq[3 * k + 2] = qz[j];
+            }
+            double *Th = Ts + 16 * h;
+            cnt[h] = -1; ssum[h] = 0;
+            if (!orc_rigid_fit(pp, qq, 4, Th)) continue;
+            ++nfit;
+            int64_t c = 0; double sd = 0;
+            for (int64_t i = 0; i < nP; ++i) {
+                double d2 = inlier_d2(&g, px, py, pz, nP_, i, qx, qy, qz, nQ_, Th, d2max, normal_check, cth, &tmp, &cap);
+                if (d2 <= d2max) { ++c; sd += d2; }
+            }
+            cnt[h] = c; ssum[h] = sd;
+        }
+        free(tmp);
+    }
+    grid_free(&g);
+    info->n_fitted = nfit;
+    /* best: most inliers, then smaller squared-distance sum, then lower index */
+    int64_t b1 = -1, b2 = -1;
+    for (int64_t h = 0; h < ns; ++h) {
+        if (cnt[h] < 0) continue;
+        int better1 = b1 < 0 || cnt[h] > cnt[b1] || (cnt[h] == cnt[b1] && ssum[h] < ssum[b1]);
+        if (better1) { b2 = b1; b1 = h; continue; }
+        int better2 = b2 < 0 || cnt[h] > cnt[b2] || (cnt[h] == cnt[b2] && ssum[h] < ssum[b2]);
+        if (better2) b2 = h;
+    }
+    int32_t status = ORC_DEGENERATE;
+    if (b1 >= 0) {
+        memcpy(T, Ts + 16 * b1, sizeof(double) * 16);
+        info->best = surv[b1];
+        info->n_inliers = cnt[b1];
+        info->ratio = (double)cnt[b1] / (double)nP;
+        info->fitness = cnt[b1] > 0 ? sqrt(ssum[b1] / (double)cnt[b1]) : 0.0;
+        info->sum_d2 = ssum[b1];
+        status = info->ratio >= (double)min_ratio ? ORC_ACCEPTED : ORC_REJECTED;
+        if (b2 >= 0) { info->second = surv[b2]; info->second_inliers = cnt[b2]; info->second_sum_d2 = ssum[b2]; }
+    }
+    free(surv); free(mem); free(ok); free(cnt); free(ssum); free(Ts);
+    return status;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -112,6 +112,23 @@ void orc_verify(const float *px, const float *py, const float *pz, const double 
                 const double *T, float delta, int32_t normal_check, float normal_cos,
                 int64_t *n_inliers, double *ratio, double *fitness);
 
+/* ---- RANSAC consensus (Algorithm 1's own pose stage) ---- */
+typedef struct {
+    int64_t n_survivors;     /* hypotheses that passed the polygon pre-rejection */
+    int64_t n_fitted;        /* survivors with a unique least-squares rotation */
+    int64_t best, second;    /* hypothesis indices of the best two (-1: none) */
+    int64_t n_inliers, second_inliers;
+    double ratio, fitness, sum_d2, second_sum_d2;
+} orc_ransac_info;
+/* Least-squares rigid transform of m point pairs (q ~ R p + t), row-major
+ * 4x4; returns 0 when the rotation is not unique. */
+int32_t orc_rigid_fit(const double *p, const double *q, int64_t m, double *T);
+int32_t orc_ransac(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
+                   const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
+                   const int32_t *nnQ, int64_t n_hyp, float tau, uint64_t seed, float delta,
+                   int32_t normal_check, float normal_cos, float min_ratio,
+                   double *T, orc_ransac_info *info);
+
 /* ---- O9: robust alignment energy and its adjoint ---- */
 double orc_align_loss(const double *p, const double *q, int64_t m, const double *T, double mu,
                       double *dp, double *dq, double *dxi);
