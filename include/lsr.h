@@ -103,8 +103,14 @@ typedef struct {
     int32_t iters;           /* pose iterations run */
 } lsr_result;
 
-/* Context for one device.  Returns LSR_OK and *ctx, or an error. */
-int lsr_create(lsr_ctx **ctx, int device);
+/* Context for one device.  workspace_cap_bytes bounds the device scratch the
+ * context holds at once (0: no bound).  Scratch is cached per call signature
+ * (sizes, addresses, parameters); when a call needs a new block and the cap
+ * would be exceeded, cached blocks are released, least recently used first
+ * (after a device synchronisation); a call whose own scratch exceeds the cap
+ * fails with LSR_ENOMEM and enqueues nothing.  Returns LSR_OK and *ctx, or an
+ * error (LSR_EINVAL: no such device). */
+int lsr_create(lsr_ctx **ctx, int device, size_t workspace_cap_bytes);
 void lsr_destroy(lsr_ctx *ctx);
 /* Text of the last error on this context (never NULL). */
 const char *lsr_last_error(const lsr_ctx *ctx);
@@ -136,6 +142,35 @@ int lsr_register_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q,
 int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all,
                        const int64_t *offP, const int64_t *offQ, int32_t n_pairs,
                        const lsr_params *prm, lsr_result *d_out, void *stream);
+
+/*
+ * Per-point intermediate results of a registration (Algorithm 1's feature
+ * neighbour cache, the reciprocal test and the polygon filter), in the
+ * caller's point order; device arrays, each may be NULL:
+ *   nnQ[i]        (total P points, int32) descriptor nearest neighbour of
+ *                 P point i in its pair's Q (index within that Q), -1 when
+ *                 the descriptor is invalid
+ *   nnP[j]        (total Q points, int32) likewise for Q points, in P
+ *   mutual[i]     (total P points, uint8) 1 when nnP[nnQ[i]] = i
+ *   consistent[i] (total P points, uint8) 1 when the correspondence of P
+ *                 point i was kept by the consistency filter
+ */
+typedef struct {
+    int32_t *nnQ;
+    int32_t *nnP;
+    uint8_t *mutual;
+    uint8_t *consistent;
+} lsr_trace;
+
+/*
+ * lsr_register_batch, then the per-point intermediate results of the run
+ * into *tr (which may not be NULL; its arrays may).  The results in d_out
+ * are those of lsr_register_batch.  For checks of a full run stage by stage.
+ */
+int lsr_register_batch_trace(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all,
+                             const int64_t *offP, const int64_t *offQ, int32_t n_pairs,
+                             const lsr_params *prm, lsr_result *d_out, const lsr_trace *tr,
+                             void *stream);
 
 /*
  * Robust alignment energy (eq. 2 with l eliminated, Psi of eq. 4):

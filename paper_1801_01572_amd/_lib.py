@@ -52,6 +52,10 @@ class Tune(C.Structure):
                 ("screen_ms", C.c_float * MAX_VARIANTS), ("consistency_ms", C.c_float * MAX_VARIANTS)]
 
 
+class Trace(C.Structure):
+    _fields_ = [("nnQ", C.c_void_p), ("nnP", C.c_void_p), ("mutual", C.c_void_p), ("consistent", C.c_void_p)]
+
+
 class Cloud(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("nx", C.c_void_p), ("ny", C.c_void_p), ("nz", C.c_void_p), ("n", C.c_int64)]
@@ -64,7 +68,7 @@ def lib():
             raise LsrError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
-        L.lsr_create.argtypes = [C.POINTER(vp), C.c_int]
+        L.lsr_create.argtypes = [C.POINTER(vp), C.c_int, C.c_size_t]
         L.lsr_destroy.argtypes = [vp]
         L.lsr_last_error.argtypes = [vp]
         L.lsr_last_error.restype = C.c_char_p
@@ -72,6 +76,8 @@ def lib():
         L.lsr_register_pair.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), C.POINTER(Params), vp, vp]
         L.lsr_register_batch.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32,
                                          C.POINTER(Params), vp, vp]
+        L.lsr_register_batch_trace.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32,
+                                               C.POINTER(Params), vp, C.POINTER(Trace), vp]
         L.lsr_align_loss.argtypes = [vp, vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, vp]
         L.lsr_align_loss_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.lsr_stage_normals.argtypes = [vp, C.POINTER(Cloud), C.c_float, vp, vp]
@@ -90,7 +96,8 @@ def lib():
         L.lsr_get_tune.argtypes = [vp, C.POINTER(Tune)]
         L.lsr_set_tune.argtypes = [vp, C.POINTER(Tune)]
         L.lsr_get_timing.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
-        for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch", "lsr_align_loss",
+        for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch",
+                  "lsr_register_batch_trace", "lsr_align_loss",
                   "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_voxel_downsample", "lsr_stage_match",
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify", "lsr_autotune", "lsr_get_tune",
                   "lsr_set_tune"):
@@ -112,9 +119,9 @@ def default_params(**kw) -> Params:
 class Context:
     """One lsr_ctx on one device (owns the library's scratch memory)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, workspace_cap: int = 0):
         h = C.c_void_p()
-        rc = lib().lsr_create(C.byref(h), int(device))
+        rc = lib().lsr_create(C.byref(h), int(device), int(workspace_cap))
         if rc != 0:
             raise LsrError(f"lsr_create({device}) failed with {rc}")
         self.h = h
@@ -172,9 +179,14 @@ def _parse_results(buf: torch.Tensor, n: int):
 
 
 def register_pair(P: torch.Tensor, Q: torch.Tensor, params: Params | None = None, ctx: Context | None = None,
-                  out: torch.Tensor | None = None, sync: bool = True):
+                  out: torch.Tensor | None = None, sync: bool = True, trace: bool = False):
     """Register one pair.  Returns a dict (after a stream sync) or, with
-    sync=False, the raw device result buffer."""
+    sync=False, the raw device result buffer.  trace=True runs the pair as a
+    batch of one with its per-point trace (lsr_register_batch_trace) and
+    returns (result, trace dict of numpy arrays)."""
+    if trace:
+        res, tr = register_batch(P, Q, [0, P.shape[1]], [0, Q.shape[1]], params, ctx=ctx, trace=True)
+        return res[0], {k: v.cpu().numpy() for k, v in tr.items()}
     ctx = ctx or get_context(P.device.index)
     prm = params or default_params()
     cp, cq = _cloud(P), _cloud(Q)
@@ -185,8 +197,11 @@ def register_pair(P: torch.Tensor, Q: torch.Tensor, params: Params | None = None
 
 
 def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params: Params | None = None,
-                   ctx: Context | None = None, out: torch.Tensor | None = None, sync: bool = True):
-    """Register len(offP) - 1 pairs: pair b's P is columns offP[b]:offP[b+1] of P_all."""
+                   ctx: Context | None = None, out: torch.Tensor | None = None, sync: bool = True,
+                   trace: bool = False):
+    """Register len(offP) - 1 pairs: pair b's P is columns offP[b]:offP[b+1] of P_all.
+    trace=True (lsr_register_batch_trace) also returns a dict of per-point
+    device tensors nnQ, nnP, mutual, consistent in the callers' point order."""
     ctx = ctx or get_context(P_all.device.index)
     prm = params or default_params()
     offP = np.ascontiguousarray(offP, np.int64)
@@ -197,6 +212,18 @@ def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params:
     cp, cq = _cloud(P_all), _cloud(Q_all)
     if out is None:
         out = torch.empty(max(n, 1) * RESULT_BYTES, dtype=torch.uint8, device=P_all.device)
+    if trace:
+        dev = P_all.device
+        nP, nQ = P_all.shape[1], Q_all.shape[1]
+        tr = {"nnQ": torch.full((nP,), -2, dtype=torch.int32, device=dev),
+              "nnP": torch.full((nQ,), -2, dtype=torch.int32, device=dev),
+              "mutual": torch.zeros(nP, dtype=torch.uint8, device=dev),
+              "consistent": torch.zeros(nP, dtype=torch.uint8, device=dev)}
+        t = Trace(*[_ptr(tr[k]) for k, _ in Trace._fields_])
+        ctx.check(lib().lsr_register_batch_trace(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
+                                                 offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), _ptr(out),
+                                                 C.byref(t), _stream()))
+        return (_parse_results(out, n) if sync else out), tr
     ctx.check(lib().lsr_register_batch(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
                                        offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), _ptr(out), _stream()))
     return _parse_results(out, n) if sync else out

@@ -46,6 +46,7 @@ enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALI
 struct FragIn {
     const float *src[6];
     int64_t n;
+    int64_t uoff;                  // first point in the caller's cloud
 };
 
 struct Plan {
@@ -119,6 +120,7 @@ void tmark(const char *name, hipStream_t s) {
 
 struct lsr_ctx {
     int device = 0;
+    size_t cap = 0;                // workspace cap in bytes (0: none)
     int tune_screen = 0;           // screen shape variant (autotuned)
     int tune_cons = 0;             // consistency block-width variant (autotuned)
     std::string err = "no error";
@@ -179,6 +181,34 @@ int add_plan(lsr_ctx *c, std::unique_ptr<Plan> p, Plan **out) {
     return LSR_OK;
 }
 
+// Device memory of a new plan under the context's workspace cap: cached plans
+// are dropped, least recently used first, until the new block fits; a block
+// larger than the cap on its own is LSR_ENOMEM.
+int plan_malloc(lsr_ctx *c, Plan *P, size_t bytes) {
+    if (c->cap) {
+        if (bytes > c->cap)
+            return fail(c, LSR_ENOMEM, "workspace of %zu bytes exceeds the context's cap of %zu bytes", bytes, c->cap);
+        size_t used = 0;
+        for (auto &q : c->plans) used += q->dbytes;
+        if (used + bytes > c->cap) {
+            HIPCHK(c, hipDeviceSynchronize());
+            while (!c->plans.empty() && used + bytes > c->cap) {
+                used -= c->plans.front()->dbytes;
+                c->plans.erase(c->plans.begin());
+            }
+        }
+    }
+    hipError_t e = hipMalloc((void **)&P->dmem, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        P->dmem = nullptr;
+        return fail(c, e == hipErrorOutOfMemory ? LSR_ENOMEM : LSR_EHIP, "hipMalloc(%zu): %s", bytes,
+                    hipGetErrorString(e));
+    }
+    P->dbytes = bytes;
+    return LSR_OK;
+}
+
 int64_t cells_for(int64_t n) { return 4 * n + 4096; }
 
 // Lay out and allocate a fragment-batch plan.  frags[f] are the inputs;
@@ -199,6 +229,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
         std::memset(&F, 0, sizeof F);
         for (int a = 0; a < 6; ++a) F.src[a] = frags[f].src[a];
         F.off = ntot;
+        F.uoff = frags[f].uoff;
         F.n = (int32_t)frags[f].n;
         F.partner = paired ? (f ^ 1) : (nf == 2 ? (f ^ 1) : -1);
         F.pair = paired ? f / 2 : -1;
@@ -231,6 +262,8 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->g.nblk256 = (int)b256.size();
     P->g.nblk512 = (int)b512.size();
     P->g.pk_rows = pk_rows;
+    P->g.max_np = 0;
+    for (int f = 0; f < nf; f += 2) P->g.max_np = std::max(P->g.max_np, hf[f].n);
     P->ntb = (int)tb.size();
 
     // host tables (pinned), copied once
@@ -252,7 +285,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     for (int a = 0; a < 3; ++a) o_n[a] = D.add(8 * n1);
     size_t o_spfh = D.add(16 * SPR * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
     size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
-    size_t o_cpack = D.add(32 * n1);
+    size_t o_cpack = D.add(32 * n1), o_cwords = D.add(sizeof(uint2) * corr_words(ntot, nf));
     size_t o_nn = D.add(4 * n1), o_dist = D.add(4 * n1), o_mut = D.add(n1), o_flag = D.add(4 * n1),
            o_kpos = D.add(4 * n1), o_kp = D.add(12 * n1), o_kq = D.add(12 * n1), o_ki = D.add(4 * n1);
     size_t o_ps = D.add(sizeof(PairState) * (size_t)std::max(npairs, 1));
@@ -265,8 +298,8 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     if (capturing(s)) return fail(c, LSR_ENOMEM, "a new plan would allocate while the stream is being captured");
     HIPCHK(c, hipHostMalloc((void **)&P->hmem, std::max<size_t>(H.total, 256), hipHostMallocDefault));
     P->hbytes = H.total;
-    HIPCHK(c, hipMalloc((void **)&P->dmem, D.total));
-    P->dbytes = D.total;
+    int rc0 = plan_malloc(c, P.get(), D.total);
+    if (rc0) return rc0;
     char *hb = P->hmem, *db = P->dmem;
     std::memcpy(hb + h_frag, hf.data(), sizeof(Frag) * nf);
     if (!b256.empty()) std::memcpy(hb + h_b256, b256.data(), sizeof(Blk) * b256.size());
@@ -297,6 +330,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->m.dist = (float *)(db + o_dist);
     P->m.mutual = (uint8_t *)(db + o_mut);
     P->m.cpack = (float4 *)(db + o_cpack);
+    P->m.cwords = (uint2 *)(db + o_cwords);
     P->m.flag = (int32_t *)(db + o_flag);
     P->m.kpos = (int32_t *)(db + o_kpos);
     P->m.kp = (float *)(db + o_kp);
@@ -341,6 +375,7 @@ FragIn frag_of(const lsr_cloud *c, int64_t off, int64_t n) {
     const float *a[6] = {c->x, c->y, c->z, c->nx, c->ny, c->nz};
     for (int k = 0; k < 6; ++k) f.src[k] = a[k] ? a[k] + off : nullptr;
     f.n = n;
+    f.uoff = off;
     return f;
 }
 
@@ -403,6 +438,26 @@ __global__ void k_passed_out(const PairState *ps, int64_t *out) { *out = (int64_
 
 __global__ void k_fallback_out(const PairState *ps, int64_t *out) { *out = (int64_t)ps->n_fallback; }
 
+// Per-point intermediate results of a paired plan, scattered to the caller's
+// point order: P points get their descriptor neighbour in Q, the reciprocal
+// flag and the consistency flag; Q points their neighbour in P.
+__global__ void __launch_bounds__(256) k_trace_out(const Frag *frag, const Blk *blk, const int32_t *nn,
+                                                   const uint8_t *mutual, const int32_t *flag, int32_t *nnQ,
+                                                   int32_t *nnP, uint8_t *mut, uint8_t *cons) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    const int i = b.start + threadIdx.x;
+    if (i >= F.n || F.partner < 0) return;
+    const int64_t g = F.off + i, u = F.uoff + i;
+    if (b.frag & 1) {
+        if (nnP) nnP[u] = nn[g];
+    } else {
+        if (nnQ) nnQ[u] = nn[g];
+        if (mut) mut[u] = mutual[g];
+        if (cons) cons[u] = flag[g] ? 1 : 0;
+    }
+}
+
 unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
 }  // namespace
@@ -457,7 +512,7 @@ void lsr_default_params(lsr_params *p) {
     p->seed = 0x1801015720ULL;
 }
 
-int lsr_create(lsr_ctx **ctx, int device) {
+int lsr_create(lsr_ctx **ctx, int device, size_t workspace_cap_bytes) {
     if (!ctx) return LSR_EINVAL;
     *ctx = nullptr;
     int n = 0;
@@ -465,6 +520,7 @@ int lsr_create(lsr_ctx **ctx, int device) {
     if (hipSetDevice(device) != hipSuccess) return LSR_EHIP;
     lsr_ctx *c = new lsr_ctx;
     c->device = device;
+    c->cap = workspace_cap_bytes;
     *ctx = c;
     return LSR_OK;
 }
@@ -557,8 +613,13 @@ int time_ms(lsr_ctx *c, hipStream_t s, int reps, Fn &&fn, float *ms) {
 
 extern "C" {
 
-int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
-                       const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out, void *stream) {
+}  // extern "C"
+
+namespace {
+// lsr_register_batch; *used receives the plan that ran.
+int register_batch_plan(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                        const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out, void *stream,
+                        Plan **used) {
     if (!ctx) return LSR_EINVAL;
     int rc;
     std::vector<FragIn> fr;
@@ -571,9 +632,10 @@ int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_
     put(key, (int)K_PAIRS + 100);
     put(key, *prm);
     put(key, d_out);
-    for (auto &f : fr) { put(key, f.n); for (int a = 0; a < 6; ++a) put(key, f.src[a]); }
+    for (auto &f : fr) { put(key, f.n); put(key, f.uoff); for (int a = 0; a < 6; ++a) put(key, f.src[a]); }
     Plan *pl = find_plan(ctx, key);
     if (!pl && (rc = make_batch_plan(ctx, fr, true, prm, key, s, &pl))) return rc;
+    if (used) *used = pl;
     if (!s || capturing(s) || g_timing.on) return run_pairs(ctx, pl, *prm, d_out, s);   // eager
     if (!pl->gexec) {
         HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -586,6 +648,30 @@ int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_
         HIPCHK(ctx, hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0));
     }
     HIPCHK(ctx, hipGraphLaunch(pl->gexec, s));
+    return LSR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                       const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out, void *stream) {
+    return register_batch_plan(ctx, P_all, Q_all, offP, offQ, n_pairs, prm, d_out, stream, nullptr);
+}
+
+int lsr_register_batch_trace(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
+                             const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, lsr_result *d_out,
+                             const lsr_trace *tr, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (!tr) return fail(ctx, LSR_EINVAL, "NULL trace");
+    Plan *pl = nullptr;
+    int rc = register_batch_plan(ctx, P_all, Q_all, offP, offQ, n_pairs, prm, d_out, stream, &pl);
+    if (rc || !pl || pl->g.nblk256 == 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_trace_out, dim3(pl->g.nblk256), dim3(256), 0, s, (const Frag *)pl->g.frag,
+                       (const Blk *)pl->g.blk256, (const int32_t *)pl->m.nn, (const uint8_t *)pl->m.mutual,
+                       (const int32_t *)pl->m.flag, tr->nnQ, tr->nnP, tr->mutual, tr->consistent);
+    HIPCHK(ctx, hipGetLastError());
     return LSR_OK;
 }
 
@@ -823,7 +909,7 @@ int lsr_stage_gnc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m,
         auto P = std::make_unique<Plan>();
         P->key = key;
         if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
-        HIPCHK(ctx, hipMalloc((void **)&P->dmem, sizeof(PairState)));
+        if ((rc = plan_malloc(ctx, P.get(), sizeof(PairState)))) return rc;
         P->ps = (PairState *)P->dmem;
         if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
     }
@@ -891,16 +977,16 @@ int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *c
         P->key = key;
         size_t ws = voxel_ws_bytes(c->n);
         if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
-        HIPCHK(ctx, hipMalloc((void **)&P->dmem, ws + 256));
+        if ((rc = plan_malloc(ctx, P.get(), ws + 256))) return rc;
         HIPCHK(ctx, hipHostMalloc((void **)&P->hmem, 256, hipHostMallocDefault));
-        P->dbytes = ws;
         std::memcpy(P->hmem, src, sizeof(src));
         std::memcpy(P->hmem + 64, out, 6 * sizeof(float *));
         HIPCHK(ctx, hipMemcpyAsync(P->dmem + ws, P->hmem, 128, hipMemcpyHostToDevice, s));
         if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
     }
-    const float *const *src_dev = (const float *const *)(pl->dmem + pl->dbytes);
-    float *const *out_dev = (float *const *)(pl->dmem + pl->dbytes + 64);
+    const size_t ws = voxel_ws_bytes(c->n);
+    const float *const *src_dev = (const float *const *)(pl->dmem + ws);
+    float *const *out_dev = (float *const *)(pl->dmem + ws + 64);
     HIPCHK(ctx, launch_voxel(src_dev, src, c->n, voxel, out_dev, d_count, pl->dmem, voxel_sort_bytes(c->n), s));
     return LSR_OK;
 }
@@ -940,7 +1026,8 @@ static int align_common(lsr_ctx *ctx, bool bwd, const float *const P_xyz[3], int
         size_t o_tabs = D.add(H.total), o_part = D.add(sizeof(double) * 6 * (size_t)std::max<int64_t>(nb, 1));
         if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
         HIPCHK(ctx, hipHostMalloc((void **)&P->hmem, H.total, hipHostMallocDefault));
-        HIPCHK(ctx, hipMalloc((void **)&P->dmem, D.total));
+        int rc1 = plan_malloc(ctx, P.get(), D.total);
+        if (rc1) return rc1;
         std::memcpy(P->hmem + h_tab, tab.data(), tab.size());
         std::memcpy(P->hmem + h_pb, pblk.data(), sizeof(int64_t) * pblk.size());
         P->atab = P->dmem + o_tabs + h_tab;

@@ -31,6 +31,7 @@ struct Frag {
     int64_t pk_off;             // first packed screen row (rows padded to a multiple of 128)
     int32_t blk256_first;       // index of the fragment's first entry in the 256-point block table
     int32_t pad0;
+    int64_t uoff;               // first point of the fragment in the caller's concatenated cloud
     // filled on the device by the grid kernels
     float ox, oy, oz, cell;     // grid origin (bounding-box minimum) and cell edge
     int32_t gx, gy, gz, pad;    // grid dimensions
@@ -122,6 +123,7 @@ struct GridBufs {              // built per batch by build_grids()
     Blk *blk512; int nblk512;  // 512 points per block
     int64_t *frag_off;         // nfrag + 1 internal offsets (device)
     int64_t pk_rows;           // packed screen rows (each fragment padded to a multiple of 128)
+    int32_t max_np;            // largest P fragment of the batch (host copy)
 };
 
 struct DescBufs {
@@ -138,6 +140,7 @@ struct MatchBufs {
     float *dist;
     uint8_t *mutual;           // original order
     float4 *cpack;             // reciprocal correspondences packed per pair: (px, py, pz, qx), (qy, qz, i, 0)
+    uint2 *cwords;             // per 32 P points: bits of those with a correspondence, packed position of the first
     int32_t *flag;             // consistency flags, original order (int32 for the scan)
     int32_t *kpos;             // exclusive scan of flags over the batch
     float *kp, *kq;            // consistent correspondences, compacted: xyz of p and q (3 floats each)
@@ -162,6 +165,7 @@ hipError_t launch_fpfh(const GridBufs &g, float r_feature, DescBufs &d, PairStat
 hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStream_t s);
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
                               float tau, uint64_t seed, int shape, int32_t *scan_tmp, hipStream_t s);
+size_t corr_words(int64_t ntot, int nfrag);
 hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);
 hipError_t launch_gnc(const GridBufs &g, const MatchBufs &m, PairState *ps, int npairs, const lsr_params &prm,
                       hipStream_t s);

@@ -1,6 +1,8 @@
 // Verification of the returned pose (Algorithm 1's hypothesis test on the
 // final transform): p is an inlier when some q lies within delta of T p
-// (optionally with normal agreement), found on Q's 3-D grid; inlier ratio =
+// (optionally with normal agreement (R n_p) . n_q >= cos), found on Q's 3-D
+// grid, with T p, R n_p and the dot product in one fixed fma order, so that the
+// predicate is a function of the inputs alone; inlier ratio =
 // inliers / N_P, fitness = RMS distance of inliers to their nearest q.  The
 // pair is accepted when the solve succeeded, at least min_consistent
 // correspondences survived the consistency filter and the ratio reaches
@@ -10,6 +12,10 @@
 namespace lsr {
 
 constexpr double FIX_SCALE = 1099511627776.0;   // 2^40: inlier d^2 / delta^2 in fixed point
+
+__device__ __forceinline__ double xform_row(const double *r, double x, double y, double z, double c) {
+    return __fma_rn(r[2], z, __fma_rn(r[1], y, __fma_rn(r[0], x, c)));
+}
 
 __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk, const int32_t *cstart,
                                                 const int32_t *ccount, const float4 *sp, const double *nxa, const double *nya,
@@ -28,15 +34,16 @@ __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk
         const double *T = S.T;
         const float4 ps4 = sp[s];
         double px = ps4.x, py = ps4.y, pz = ps4.z;
-        double x = T[0] * px + T[1] * py + T[2] * pz + T[3];
-        double y = T[4] * px + T[5] * py + T[6] * pz + T[7];
-        double z = T[8] * px + T[9] * py + T[10] * pz + T[11];
+        // T p and R n_p: each row c + r0 x, then + r1 y, then + r2 z, one fma per step
+        double x = xform_row(T, px, py, pz, T[3]);
+        double y = xform_row(T + 4, px, py, pz, T[7]);
+        double z = xform_row(T + 8, px, py, pz, T[11]);
         double rnx = 0, rny = 0, rnz = 0;
         if (normal_check) {
             double a = nxa[s], bb = nya[s], c = nza[s];
-            rnx = T[0] * a + T[1] * bb + T[2] * c;
-            rny = T[4] * a + T[5] * bb + T[6] * c;
-            rnz = T[8] * a + T[9] * bb + T[10] * c;
+            rnx = xform_row(T, a, bb, c, 0.0);
+            rny = xform_row(T + 4, a, bb, c, 0.0);
+            rnz = xform_row(T + 8, a, bb, c, 0.0);
         }
         // cells that can hold a point within delta: 3 per axis, or 2 (p's cell and the
         // neighbour on the side of p's half) when delta is at most half a cell
@@ -56,7 +63,7 @@ __global__ void __launch_bounds__(256) k_verify(const Frag *frag, const Blk *blk
                     int64_t row = Q.cell_off + ((int64_t)zz * Q.gy + yy) * Q.gx;
                     int32_t kb = cstart[row + x0], ke = cstart[row + x1] + ccount[row + x1];
                     for (int32_t k = kb; k < ke; ++k) {
-                        if (normal_check && rnx * nxa[k] + rny * nya[k] + rnz * nza[k] < ncos) continue;
+                        if (normal_check && __fma_rn(rnz, nza[k], __fma_rn(rny, nya[k], rnx * nxa[k])) < ncos) continue;
                         const float4 q = sp[k];
                         double d2 = pdist2(x, y, z, (double)q.x, (double)q.y, (double)q.z);
                         best = fmin(best, d2);

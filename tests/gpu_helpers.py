@@ -45,3 +45,78 @@ def desc_exempt(orc, cloud, nrm, gap, ori, r_f):
             nxt[idx[off[i]:off[i + 1]]] = True
         touch = nxt
     return F, v, (dm < MARGIN) | touch
+
+
+def orc_params(orc, prm):
+    """The oracle's parameters for a GPU parameter block."""
+    return orc.default_params(r_normal=prm.r_normal, r_feature=prm.r_feature, max_corr=prm.max_corr,
+                              tau=prm.tau, n_trials=prm.n_trials, gnc_div=prm.gnc_div,
+                              gnc_every=prm.gnc_every, gnc_max_iter=prm.gnc_max_iter,
+                              polish_iter=prm.polish_iter, min_inlier_ratio=prm.min_inlier_ratio,
+                              min_consistent=prm.min_consistent, seed=prm.seed)
+
+
+def check_chain(orc, P, Q, r, tr, prm, label=""):
+    """Stage-by-stage parity of one pair of a full GPU run against the oracle.
+
+    r: the GPU's result; tr: its per-point trace (numpy nnQ, nnP, mutual,
+    consistent of this pair).  Each GPU stage is checked on the GPU's own
+    input to that stage, so that a legitimate near-tie flip upstream cannot
+    hide a later mismatch:
+      descriptor neighbours equal the oracle's outside the tie margin (both
+      directions); the reciprocal flags follow from the GPU's neighbours;
+      the consistency flags equal the oracle's filter run on the GPU's
+      correspondences, bit for bit; the pose is within POSE_TOL of the
+      oracle's robust solve on the GPU's consistent set; the inlier count of
+      the GPU's pose equals the oracle's verification of that pose, and the
+      status follows from it.  Returns a summary (the number of
+      correspondences that differ from the oracle's own, the tie-exempt
+      share, the pose error)."""
+    nP, nQ = P.shape[1], Q.shape[1]
+    nrmP, *_ = orc.normals(P, prm.r_normal)
+    nrmQ, *_ = orc.normals(Q, prm.r_normal)
+    F, vF, _, _ = orc.fpfh(P[:3], nrmP, prm.r_feature)
+    G, vG, _, _ = orc.fpfh(Q[:3], nrmQ, prm.r_feature)
+    assert (r["n_valid_P"], r["n_valid_Q"]) == (int(vF.sum()), int(vG.sum())), label
+    m = orc.match(F, vF, G, vG)
+    tP, tQ = orc.tie_flags(F, G, m)
+    nnQ, nnP = tr["nnQ"].astype(np.int64), tr["nnP"].astype(np.int64)
+    badQ = np.nonzero((nnQ != m["nnQ"]) & ~tP)[0]
+    badP = np.nonzero((nnP != m["nnP"]) & ~tQ)[0]
+    assert len(badQ) == 0 and len(badP) == 0, (label, "neighbours outside the tie margin", badQ[:5], badP[:5])
+    mut = orc.mutual(nnQ, nnP)
+    assert np.array_equal(tr["mutual"].astype(bool), mut), label
+    assert r["n_recip"] == int(mut.sum()), label
+    mut_o = orc.mutual(m["nnQ"], m["nnP"])
+    cg = set(zip(np.nonzero(mut)[0].tolist(), nnQ[mut].tolist()))
+    co = set(zip(np.nonzero(mut_o)[0].tolist(), m["nnQ"][mut_o].tolist()))
+    n_cdiff = len(cg ^ co)
+    T_trials = prm.n_trials if prm.n_trials > 0 else orc.default_trials(nP)
+    want, _ = orc.consistency(P[:3], Q[:3], nnQ.astype(np.int32), mut, T_trials, prm.tau, prm.seed)
+    assert np.array_equal(tr["consistent"].astype(bool), want), (label, "consistency flags")
+    K = int(want.sum())
+    assert r["n_consistent"] == K, label
+    idx = np.nonzero(want)[0]
+    p = P[:3, idx].T.astype(np.float64)
+    q = Q[:3, nnQ[idx]].T.astype(np.float64)
+    st, To, _, _, _ = orc.gnc(p, q, orc_params(orc, prm))
+    out = {"n_c_diff": n_cdiff, "tie_exempt_P": float(tP[vF == 1].mean()) if vF.any() else 0.0,
+           "K": K, "pose_err": None}
+    if st == orc.DEGENERATE:
+        assert r["status"] == orc.DEGENERATE, label
+        return out
+    ang, tr_err = rot_err(r["T"], To)
+    assert ang <= POSE_TOL and tr_err <= POSE_TOL, (label, ang, tr_err)
+    out["pose_err"] = (ang, tr_err)
+    ni, ratio, _ = orc.verify(P, None, Q, None, r["T"], prm.max_corr)
+    assert r["n_inliers"] == ni, (label, r["n_inliers"], ni)
+    ok = K >= prm.min_consistent and ratio >= np.float64(np.float32(prm.min_inlier_ratio))
+    assert r["status"] == (orc.ACCEPTED if ok else orc.REJECTED), (label, r["status"], ratio, K)
+    return out
+
+
+def trace_slice(tr, offP, offQ, b):
+    """Pair b's part of a batch trace, as numpy arrays."""
+    sP, sQ = slice(int(offP[b]), int(offP[b + 1])), slice(int(offQ[b]), int(offQ[b + 1]))
+    return {"nnQ": tr["nnQ"][sP].cpu().numpy(), "nnP": tr["nnP"][sQ].cpu().numpy(),
+            "mutual": tr["mutual"][sP].cpu().numpy(), "consistent": tr["consistent"][sP].cpu().numpy()}

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import synth
-from gpu_helpers import DESC_RTOL, POSE_TOL, WORK_KEYS, desc_exempt, dev, rot_err
+from gpu_helpers import DESC_RTOL, WORK_KEYS, check_chain, desc_exempt, dev, trace_slice
 
 pytestmark = pytest.mark.gpu
 
@@ -40,17 +40,13 @@ def _same(a, b, skip=WORK_KEYS):
             assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
 
 
-def _vs_oracle(orc, r, pr):
-    o, _, _ = orc.register_pair(pr.P, pr.Q)
-    d = orc.result_dict(o)
-    assert r["n_valid_P"] == d["n_valid_P"] and r["n_valid_Q"] == d["n_valid_Q"]
-    print(f"  gpu recip {r['n_recip']} K {r['n_consistent']} status {r['status']} | oracle recip {d['n_recip']} "
-          f"K {d['n_consistent']} status {d['status']}", flush=True)
-    if r["n_recip"] == d["n_recip"] and r["n_consistent"] == d["n_consistent"]:
-        assert r["status"] == d["status"]
-        if d["status"] != orc.DEGENERATE:
-            ang, tr = rot_err(r["T"], d["T"])
-            assert ang <= POSE_TOL and tr <= POSE_TOL, (ang, tr)
+def _vs_oracle(orc, r, tr, pr, prm, label):
+    """One pair of a batch run checked stage by stage against the oracle."""
+    c = check_chain(orc, pr.P, pr.Q, r, tr, prm, label)
+    print(f"  {label}: gpu recip {r['n_recip']} K {r['n_consistent']} status {r['status']} inliers "
+          f"{r['n_inliers']}; C differs from the oracle's in {c['n_c_diff']} correspondences "
+          f"({c['tie_exempt_P']:.3f} of P rows tie-exempt); pose vs the oracle's solve {c['pose_err']}", flush=True)
+    return c
 
 
 def test_benchmark_batch_256x50k(L, orc):
@@ -61,9 +57,10 @@ def test_benchmark_batch_256x50k(L, orc):
     Pd, Qd = dev(P), dev(Q)
     print("batch 256 x 50k/50k", flush=True)
     side = torch.cuda.Stream()
+    prm = L.default_params(precision=L.BF16_SCREEN)
     with torch.cuda.stream(side):
-        bf = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))
-        bf2 = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.BF16_SCREEN))   # graph replay
+        bf = L.register_batch(Pd, Qd, offP, offQ, prm)
+        bf2, tr = L.register_batch(Pd, Qd, offP, offQ, prm, trace=True)   # graph replay, then the trace
     torch.cuda.synchronize()
     fp = L.register_batch(Pd, Qd, offP, offQ, L.default_params(precision=L.FP32))
     for b in range(256):
@@ -71,9 +68,9 @@ def test_benchmark_batch_256x50k(L, orc):
         _same(bf[b], bf2[b], skip=())
         _same(bf[b], bf[b % distinct], skip=())
     assert sum(r["status"] == L.ACCEPTED for r in bf) > 0
-    for k in (0, 37):
+    for k in (0, 37, 100):
         print(f"pair {k} vs oracle", flush=True)
-        _vs_oracle(orc, bf[k], prs[k])
+        _vs_oracle(orc, bf2[k], trace_slice(tr, offP, offQ, k), prs[k % distinct], prm, f"pair {k}")
 
 
 def test_pruned_screen_64x50k(L):
@@ -131,7 +128,7 @@ def test_ragged_batch_with_negatives(L, orc):
     P, Q, offP, offQ = _batch(prs, range(len(prs)))
     print(f"ragged batch sizes {[p.P.shape[1] for p in prs]}", flush=True)
     prm = L.default_params(precision=L.BF16_SCREEN)
-    res = L.register_batch(dev(P), dev(Q), offP, offQ, prm)
+    res, tr = L.register_batch(dev(P), dev(Q), offP, offQ, prm, trace=True)
     neg = [k for k, p in enumerate(prs) if p.meta["negative"]]
     assert neg, "the recipe has negatives"
     # disjoint crops of one room share its floor and walls: a plane-on-plane
@@ -140,9 +137,9 @@ def test_ragged_batch_with_negatives(L, orc):
     print(f"negatives {neg}: accepted {[k for k in neg if res[k]['status'] == L.ACCEPTED]}", flush=True)
     for k in (0, 3, neg[0], len(prs) - 1):
         _same(res[k], L.register_pair(dev(prs[k].P), dev(prs[k].Q), prm), skip=())
-    for k in (1, neg[0]):
+    for k in sorted({1, 2, neg[0]}):
         print(f"pair {k} vs oracle", flush=True)
-        _vs_oracle(orc, res[k], prs[k])
+        _vs_oracle(orc, res[k], trace_slice(tr, offP, offQ, k), prs[k], prm, f"pair {k}")
 
 
 def test_building_scale_500k(L, orc):

@@ -221,6 +221,25 @@ def test_consistency_small_c(L, orc, nC):
             assert npass == 0 and not want.any()
 
 
+def test_consistency_large_fragment(L, orc):
+    """A 230,000-point P: its correspondence words exceed what a block keeps in
+    LDS, so the draws read them from global memory; flags and passing-trial
+    count still bit-exact."""
+    rng = np.random.default_rng(5)
+    n = 230000
+    P = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+    Q = (P * 1.01 + rng.normal(0, 0.005, (3, n))).astype(np.float32)
+    Q[:, ::4] = rng.uniform(-1, 1, (3, Q[:, ::4].shape[1]))
+    nnQ = rng.permutation(n).astype(np.int32)
+    Q = Q[:, np.argsort(nnQ)].copy()                  # q of P point i sits at nnQ[i]
+    mut = (rng.random(n) < 0.2).astype(np.uint8)
+    for T, seed in ((70001, 3), (4096, 12345)):
+        want, npass = orc.consistency(P, Q, nnQ, mut, T, 0.9, seed)
+        flag, passed = L.stage_consistency(dev(P), dev(Q), dev(nnQ), dev(mut), T, 0.9, seed)
+        assert np.array_equal(flag.cpu().numpy().astype(bool), want)
+        assert int(passed.cpu()[0]) == npass and npass > 0
+
+
 def _corr(rng, n, frac_out=0.5, noise=0.003):
     a = rng.normal(size=3)
     a /= np.linalg.norm(a)
@@ -266,8 +285,40 @@ def test_verify_parity(L, orc, normal_check):
         ni, ratio, fit = orc.verify(pr.P, nP, pr.Q, nQ, T, 0.015, normal_check)
         info = L.stage_verify(dev(pr.P[:3]), dev(nP), dev(pr.Q[:3]), dev(nQ), dev(T), 0.015,
                               normal_check).cpu().numpy()
-        assert abs(info[0] - ni) <= 2                 # decisions at |Tp - q| = delta within rounding
+        assert info[0] == ni                          # one fma order on both sides: exact counts
         assert abs(info[2] - fit) <= 1e-6 * (1 + fit)
+
+
+@pytest.mark.parametrize("normal_check", [0, 1])
+def test_verify_at_the_radius(L, orc, normal_check):
+    """Every q placed at distance delta from T p (float32 rounding puts about
+    half just inside, half just outside): the exact inlier count, so the
+    predicate at the boundary is the oracle's, bit for bit."""
+    rng = np.random.default_rng(11)
+    n = 20000
+    P = rng.uniform(-1, 1, (3, n))
+    a = rng.normal(size=3)
+    a /= np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    th = 0.7
+    R = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = [0.1, -0.2, 0.3]
+    u = rng.normal(size=(3, n))
+    u /= np.linalg.norm(u, axis=0)
+    delta = 0.015
+    Pf = P.astype(np.float32)
+    Q = (R @ Pf.astype(np.float64) + T[:3, 3:4] + delta * u).astype(np.float32)
+    nP = rng.normal(size=(n, 3))
+    nP /= np.linalg.norm(nP, axis=1, keepdims=True)
+    nQ = nP @ R.T + rng.normal(0, 0.3, (n, 3))
+    nQ /= np.linalg.norm(nQ, axis=1, keepdims=True)
+    ni, _, _ = orc.verify(Pf, nP, Q, nQ, T, delta, normal_check)
+    info = L.stage_verify(dev(Pf), dev(nP), dev(Q), dev(nQ), dev(T), delta, normal_check).cpu().numpy()
+    print(f"normal_check={normal_check}: oracle {ni} gpu {int(info[0])} inliers of {n}", flush=True)
+    assert 0.2 * n < ni < 0.8 * n or normal_check
+    assert info[0] == ni
 
 
 @pytest.mark.parametrize("cfg,idx,n,v", [(0, 0, None, 0.01), (5, 0, 60000, 0.02), (1, 1, 9000, 0.05)])

@@ -42,7 +42,7 @@ def test_defaults_and_create_without_device():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
-    assert L.lib().lsr_create(ctypes.byref(h), 0) != 0          # no device: an error code, not a crash
+    assert L.lib().lsr_create(ctypes.byref(h), 0, 0) != 0       # no device: an error code, not a crash
 
 
 def test_product_path_does_not_use_the_oracle():
@@ -70,7 +70,7 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     from paper_1801_01572_amd import _lib
     pairs = [("lsr_cloud", _lib.Cloud), ("lsr_params", _lib.Params), ("lsr_result", _lib.Result),
-             ("lsr_tune", _lib.Tune)]
+             ("lsr_tune", _lib.Tune), ("lsr_trace", _lib.Trace)]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lsr.h"', "int main(void) {"]
     for cname, cls in pairs:
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
