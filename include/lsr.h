@@ -154,12 +154,18 @@ int lsr_register_batch(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_
  *   mutual[i]     (total P points, uint8) 1 when nnP[nnQ[i]] = i
  *   consistent[i] (total P points, uint8) 1 when the correspondence of P
  *                 point i was kept by the consistency filter
+ *   desc_P/desc_Q, valid_P/valid_Q: the descriptors the matcher compared
  */
 typedef struct {
     int32_t *nnQ;
     int32_t *nnP;
     uint8_t *mutual;
     uint8_t *consistent;
+    float *desc_P;               /* (total P points x 33 float32) FPFH descriptor of each P point, row-major,
+                                    zero for an invalid descriptor */
+    float *desc_Q;               /* (total Q points x 33) likewise */
+    int32_t *valid_P;            /* (total P points) 1 when the descriptor is valid */
+    int32_t *valid_Q;            /* (total Q points) likewise */
 } lsr_trace;
 
 /*
@@ -212,6 +218,76 @@ int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t n
  */
 int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *const out[6],
                          int64_t *d_count, void *stream);
+
+/* ---- RANSAC consensus (Algorithm 1's own pose stage) ---- */
+
+/*
+ * Section IV, Algorithm 1: hypotheses of four random P points, each paired
+ * with its descriptor nearest neighbour in Q (the one-directional
+ * pre-matching cache); hypothesis t fills slot s = 0..3 with the first of up
+ * to 64 draws i = ((r >> 32) N_P) >> 32, r the n-th SplitMix64 output of the
+ * seed for n = (t << 8) | (s << 6) | attempt, whose point has a neighbour and
+ * differs from the earlier slots (a slot without one voids the hypothesis).
+ * Pre-rejection: every edge k -> k+1 of the closed quadrilateral must have
+ * squared lengths in P and Q within tau^2 of each other (a zero edge
+ * rejects).  Survivors get the least-squares rigid fit of their four pairs
+ * (Horn's quaternion form; refused when the rotation is not unique) and are
+ * tested on all of P: inliers have a q within max_corr of T p on Q's 3-D
+ * grid (eq. 1), with the normal check (R n_p) . n_q >= normal_cos when
+ * normal_check is set (the paper moves that check into hypothesis testing).
+ * The best hypothesis has the most inliers, then the smaller sum of squared
+ * inlier distances, then the lower index; it is accepted when inliers / N_P
+ * reaches min_inlier_ratio.
+ */
+typedef struct {
+    double T[16];            /* best hypothesis, row-major 4x4 (identity when none) */
+    double inlier_ratio;     /* its inliers / N_P */
+    double fitness;          /* RMS distance of its inliers */
+    double sum_d2;           /* sum of its inliers' squared distances */
+    int64_t n_hypotheses;    /* hypotheses drawn */
+    int64_t n_survivors;     /* hypotheses that passed the polygon pre-rejection */
+    int64_t n_fitted;        /* survivors with a unique least-squares rotation */
+    int64_t best;            /* index of the best hypothesis, -1 when none */
+    int64_t n_inliers;       /* its inlier count */
+    int64_t n_valid_P, n_valid_Q;   /* lsr_ransac_pair: points with a valid descriptor (0 in the stage call) */
+    int32_t status;          /* LSR_ACCEPTED / LSR_REJECTED / LSR_DEGENERATE (no survivor with a unique fit) */
+    int32_t pad;
+} lsr_ransac_result;
+
+/* Optional per-survivor record (device arrays of `capacity` entries each, any
+ * may be NULL; survivors beyond capacity are not recorded), in no particular
+ * order.  n_inliers: -1 when the fit is not unique, -2 when testing stopped
+ * early because the hypothesis could no longer reach the largest count
+ * completed (it cannot be chosen); such counts are not final. */
+typedef struct {
+    int64_t capacity;
+    int64_t *hyp;            /* hypothesis index t */
+    int32_t *members;        /* 4 P indices per survivor, slot order */
+    int32_t *n_inliers;
+    double *sum_d2;
+    double *T;               /* 16 per survivor, row-major */
+} lsr_ransac_trace;
+
+/*
+ * Algorithm 1 on one pair: 3-D grid, normals, FPFH, the descriptor nearest
+ * neighbour of every P point in Q (prm->precision as in registration), then
+ * the RANSAC consensus above with n_hyp hypotheses (<= 0: min(4e6, 100 N_P);
+ * the paper uses 4e6).  Parameters used: r_normal, r_feature, precision,
+ * tau, seed, max_corr, normal_check, normal_cos, min_inlier_ratio.
+ * d_out: device pointer to one lsr_ransac_result.  Deterministic.
+ */
+int lsr_ransac_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, const lsr_params *prm, int64_t n_hyp,
+                    lsr_ransac_result *d_out, void *stream);
+
+/*
+ * The RANSAC consensus alone on injected inputs: d_nnQ (device, P->n int32)
+ * the descriptor neighbour of each P point in Q (-1: none); normals (device
+ * n x 3 doubles) only when prm->normal_check (else may be NULL).  Q's grid
+ * uses cells of at least max_corr.  tr (may be NULL) receives the survivors.
+ */
+int lsr_stage_ransac(lsr_ctx *ctx, const lsr_cloud *P, const double *d_nrmP, const lsr_cloud *Q,
+                     const double *d_nrmQ, const int32_t *d_nnQ, int64_t n_hyp, const lsr_params *prm,
+                     lsr_ransac_result *d_out, const lsr_ransac_trace *tr, void *stream);
 
 /* ---- autotuning of the batch driver's launch shapes ---- */
 

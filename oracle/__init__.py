@@ -221,6 +221,19 @@ def rigid_fit(p, q):
     return bool(ok), T.reshape(4, 4)
 
 
+def ransac_hypotheses(P, Q, nnQ, n_hyp, tau=0.9, seed=0x1801015720):
+    """Hypotheses of the RANSAC consensus and their polygon pre-rejection:
+    (ok bool[n_hyp], members int64[n_hyp, 4]; rows of survivors only)."""
+    P = _f32(P); Q = _f32(Q)
+    nnQ = np.ascontiguousarray(nnQ, np.int32)
+    ok = np.zeros(n_hyp, np.uint8)
+    mem = np.full((n_hyp, 4), -1, np.int64)
+    lib().orc_ransac_hypotheses(_p(P[0]), _p(P[1]), _p(P[2]), C.c_int64(P.shape[1]), _p(Q[0]), _p(Q[1]),
+                                _p(Q[2]), _p(nnQ), C.c_int64(n_hyp), C.c_float(tau), C.c_uint64(seed),
+                                _p(ok), _p(mem))
+    return ok.astype(bool), mem
+
+
 def ransac(P, nrmP, Q, nrmQ, nnQ, n_hyp, tau=0.9, seed=0x1801015720, delta=0.015, normal_check=1,
            normal_cos=0.8660254, min_ratio=0.15):
     """RANSAC consensus (Algorithm 1) on the one-directional cache nnQ:

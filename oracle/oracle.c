@@ -895,20 +895,14 @@ int32_t orc_rigid_fit(const double *p, const double *q, int64_t m, double *T) {
     return 1;
 }
 
-int32_t orc_ransac(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
-                   const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
-                   const int32_t *nnQ, int64_t n_hyp, float tau, uint64_t seed, float delta,
-                   int32_t normal_check, float normal_cos, float min_ratio,
-                   double *T, orc_ransac_info *info) {
-    memset(info, 0, sizeof *info);
-    info->best = info->second = -1;
-    for (int i = 0; i < 16; ++i) T[i] = (i % 5 == 0);
-    if (nP <= 0) return ORC_DEGENERATE;
-    double t2 = (double)tau * (double)tau, d2max = (double)delta * (double)delta, cth = (double)normal_cos;
-    /* hypotheses and pre-rejection */
-    int64_t *surv = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_hyp > 0 ? n_hyp : 1));
-    int64_t (*mem)[4] = malloc(sizeof(int64_t[4]) * (size_t)(n_hyp > 0 ? n_hyp : 1));
-    uint8_t *ok = (uint8_t *)calloc((size_t)(n_hyp > 0 ? n_hyp : 1), 1);
+/* Hypotheses and their pre-rejection: ok[t] = 1 when hypothesis t filled
+ * its four slots and passed the polygon test, its P indices in mem[4 t ..]. */
+void orc_ransac_hypotheses(const float *px, const float *py, const float *pz, int64_t nP,
+                           const float *qx, const float *qy, const float *qz, const int32_t *nnQ,
+                           int64_t n_hyp, float tau, uint64_t seed, uint8_t *ok, int64_t *mem) {
+    double t2 = (double)tau * (double)tau;
+    memset(ok, 0, (size_t)(n_hyp > 0 ? n_hyp : 0));
+    if (nP <= 0) return;
     #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < n_hyp; ++t) {
         int64_t id[4];
@@ -933,8 +927,25 @@ int32_t orc_ransac(const float *px, const float *py, const float *pz, const doub
             double b = dist2(qx[j0], qy[j0], qz[j0], qx[j1], qy[j1], qz[j1]);
             if (a == 0.0 || b == 0.0 || a < t2 * b || b < t2 * a) good = 0;
         }
-        if (good) { ok[t] = 1; for (int k = 0; k < 4; ++k) mem[t][k] = id[k]; }
+        if (good) { ok[t] = 1; for (int k = 0; k < 4; ++k) mem[4 * t + k] = id[k]; }
     }
+}
+
+int32_t orc_ransac(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
+                   const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
+                   const int32_t *nnQ, int64_t n_hyp, float tau, uint64_t seed, float delta,
+                   int32_t normal_check, float normal_cos, float min_ratio,
+                   double *T, orc_ransac_info *info) {
+    memset(info, 0, sizeof *info);
+    info->best = info->second = -1;
+    for (int i = 0; i < 16; ++i) T[i] = (i % 5 == 0);
+    if (nP <= 0) return ORC_DEGENERATE;
+    double d2max = (double)delta * (double)delta, cth = (double)normal_cos;
+    /* hypotheses and pre-rejection */
+    int64_t *surv = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_hyp > 0 ? n_hyp : 1));
+    int64_t (*mem)[4] = malloc(sizeof(int64_t[4]) * (size_t)(n_hyp > 0 ? n_hyp : 1));
+    uint8_t *ok = (uint8_t *)calloc((size_t)(n_hyp > 0 ? n_hyp : 1), 1);
+    orc_ransac_hypotheses(px, py, pz, nP, qx, qy, qz, nnQ, n_hyp, tau, seed, ok, &mem[0][0]);
     int64_t ns = 0;
     for (int64_t t = 0; t < n_hyp; ++t) if (ok[t]) surv[ns++] = t;
     info->n_survivors = ns;

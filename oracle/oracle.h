@@ -123,6 +123,12 @@ typedef struct {
 /* Least-squares rigid transform of m point pairs (q ~ R p + t), row-major
  * 4x4; returns 0 when the rotation is not unique. */
 int32_t orc_rigid_fit(const double *p, const double *q, int64_t m, double *T);
+/* Hypothesis t: four P indices drawn as in O6 (eligible: nnQ >= 0) and the
+ * polygon test; ok[t] (n_hyp bytes) = 1 when it survives, mem[4 t .. 4 t + 3]
+ * its P indices (n_hyp x 4, set for survivors only). */
+void orc_ransac_hypotheses(const float *px, const float *py, const float *pz, int64_t nP,
+                           const float *qx, const float *qy, const float *qz, const int32_t *nnQ,
+                           int64_t n_hyp, float tau, uint64_t seed, uint8_t *ok, int64_t *mem);
 int32_t orc_ransac(const float *px, const float *py, const float *pz, const double *nP_, int64_t nP,
                    const float *qx, const float *qy, const float *qz, const double *nQ_, int64_t nQ,
                    const int32_t *nnQ, int64_t n_hyp, float tau, uint64_t seed, float delta,

@@ -53,7 +53,8 @@ class Tune(C.Structure):
 
 
 class Trace(C.Structure):
-    _fields_ = [("nnQ", C.c_void_p), ("nnP", C.c_void_p), ("mutual", C.c_void_p), ("consistent", C.c_void_p)]
+    _fields_ = [("nnQ", C.c_void_p), ("nnP", C.c_void_p), ("mutual", C.c_void_p), ("consistent", C.c_void_p),
+                ("desc_P", C.c_void_p), ("desc_Q", C.c_void_p), ("valid_P", C.c_void_p), ("valid_Q", C.c_void_p)]
 
 
 class Cloud(C.Structure):
@@ -201,7 +202,8 @@ def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params:
                    trace: bool = False):
     """Register len(offP) - 1 pairs: pair b's P is columns offP[b]:offP[b+1] of P_all.
     trace=True (lsr_register_batch_trace) also returns a dict of per-point
-    device tensors nnQ, nnP, mutual, consistent in the callers' point order."""
+    device tensors nnQ, nnP, mutual, consistent, desc_P, desc_Q, valid_P,
+    valid_Q in the callers' point order."""
     ctx = ctx or get_context(P_all.device.index)
     prm = params or default_params()
     offP = np.ascontiguousarray(offP, np.int64)
@@ -218,7 +220,11 @@ def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params:
         tr = {"nnQ": torch.full((nP,), -2, dtype=torch.int32, device=dev),
               "nnP": torch.full((nQ,), -2, dtype=torch.int32, device=dev),
               "mutual": torch.zeros(nP, dtype=torch.uint8, device=dev),
-              "consistent": torch.zeros(nP, dtype=torch.uint8, device=dev)}
+              "consistent": torch.zeros(nP, dtype=torch.uint8, device=dev),
+              "desc_P": torch.zeros((nP, 33), dtype=torch.float32, device=dev),
+              "desc_Q": torch.zeros((nQ, 33), dtype=torch.float32, device=dev),
+              "valid_P": torch.full((nP,), -1, dtype=torch.int32, device=dev),
+              "valid_Q": torch.full((nQ,), -1, dtype=torch.int32, device=dev)}
         t = Trace(*[_ptr(tr[k]) for k, _ in Trace._fields_])
         ctx.check(lib().lsr_register_batch_trace(ctx.h, C.byref(cp), C.byref(cq), offP.ctypes.data_as(C.c_void_p),
                                                  offQ.ctypes.data_as(C.c_void_p), n, C.byref(prm), _ptr(out),

@@ -41,7 +41,7 @@ using namespace lsr;
 
 namespace {
 
-enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN, K_VOXEL };
+enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN, K_VOXEL, K_RANSAC, K_RANSAC_STAGE };
 
 struct FragIn {
     const float *src[6];
@@ -66,6 +66,7 @@ struct Plan {
     double *nrm_orig = nullptr;    // stage calls: normals in original order (3 per point)
     int64_t *cnt64 = nullptr;      // small device scalars for stage outputs
     void *mscratch = nullptr;      // matcher scratch
+    void *extra = nullptr;         // stage-specific scratch (RANSAC hypotheses)
     int64_t pk_rows = 0;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -214,7 +215,7 @@ int64_t cells_for(int64_t n) { return 4 * n + 4096; }
 // Lay out and allocate a fragment-batch plan.  frags[f] are the inputs;
 // pairs pair fragment 2b with 2b+1 when `paired`.
 int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, const lsr_params *prm,
-                    std::vector<char> key, hipStream_t s, Plan **out) {
+                    std::vector<char> key, hipStream_t s, Plan **out, size_t extra_bytes = 0) {
     auto P = std::make_unique<Plan>();
     P->key = std::move(key);
     const int nf = (int)frags.size();
@@ -294,6 +295,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     size_t o_cnt = D.add(8 * 16);
     size_t msz = precision == LSR_BF16_SCREEN ? match_bf16_scratch(P->g, pk_rows) : 0;
     size_t o_msc = D.add(std::max<size_t>(msz, 256));
+    size_t o_extra = D.add(std::max<size_t>(extra_bytes, 256));
 
     if (capturing(s)) return fail(c, LSR_ENOMEM, "a new plan would allocate while the stream is being captured");
     HIPCHK(c, hipHostMalloc((void **)&P->hmem, std::max<size_t>(H.total, 256), hipHostMallocDefault));
@@ -341,6 +343,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->nrm_orig = (double *)(db + o_nrm);
     P->cnt64 = (int64_t *)(db + o_cnt);
     P->mscratch = db + o_msc;
+    P->extra = db + o_extra;
     HIPCHK(c, hipMemcpyAsync(tabs, hb, H.total, hipMemcpyHostToDevice, s));
     return add_plan(c, std::move(P), out);
 }
@@ -439,22 +442,29 @@ __global__ void k_passed_out(const PairState *ps, int64_t *out) { *out = (int64_
 __global__ void k_fallback_out(const PairState *ps, int64_t *out) { *out = (int64_t)ps->n_fallback; }
 
 // Per-point intermediate results of a paired plan, scattered to the caller's
-// point order: P points get their descriptor neighbour in Q, the reciprocal
+// point order: every point gets its descriptor (33 floats, zero when invalid)
+// and validity; P points get their descriptor neighbour in Q, the reciprocal
 // flag and the consistency flag; Q points their neighbour in P.
 __global__ void __launch_bounds__(256) k_trace_out(const Frag *frag, const Blk *blk, const int32_t *nn,
-                                                   const uint8_t *mutual, const int32_t *flag, int32_t *nnQ,
-                                                   int32_t *nnP, uint8_t *mut, uint8_t *cons) {
+                                                   const uint8_t *mutual, const int32_t *flag, const float *F,
+                                                   const int32_t *valid, lsr_trace tr) {
     const Blk b = blk[blockIdx.x];
-    const Frag &F = frag[b.frag];
+    const Frag &Fr = frag[b.frag];
     const int i = b.start + threadIdx.x;
-    if (i >= F.n || F.partner < 0) return;
-    const int64_t g = F.off + i, u = F.uoff + i;
-    if (b.frag & 1) {
-        if (nnP) nnP[u] = nn[g];
+    if (i >= Fr.n || Fr.partner < 0) return;
+    const int64_t g = Fr.off + i, u = Fr.uoff + i;
+    const bool q = b.frag & 1;
+    float *desc = q ? tr.desc_Q : tr.desc_P;
+    int32_t *val = q ? tr.valid_Q : tr.valid_P;
+    if (desc)
+        for (int c = 0; c < FD; ++c) desc[u * FD + c] = F[g * FD + c];
+    if (val) val[u] = valid[g];
+    if (q) {
+        if (tr.nnP) tr.nnP[u] = nn[g];
     } else {
-        if (nnQ) nnQ[u] = nn[g];
-        if (mut) mut[u] = mutual[g];
-        if (cons) cons[u] = flag[g] ? 1 : 0;
+        if (tr.nnQ) tr.nnQ[u] = nn[g];
+        if (tr.mutual) tr.mutual[u] = mutual[g];
+        if (tr.consistent) tr.consistent[u] = flag[g] ? 1 : 0;
     }
 }
 
@@ -670,7 +680,7 @@ int lsr_register_batch_trace(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_clo
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_trace_out, dim3(pl->g.nblk256), dim3(256), 0, s, (const Frag *)pl->g.frag,
                        (const Blk *)pl->g.blk256, (const int32_t *)pl->m.nn, (const uint8_t *)pl->m.mutual,
-                       (const int32_t *)pl->m.flag, tr->nnQ, tr->nnP, tr->mutual, tr->consistent);
+                       (const int32_t *)pl->m.flag, (const float *)pl->d.F, (const int32_t *)pl->d.valid, *tr);
     HIPCHK(ctx, hipGetLastError());
     return LSR_OK;
 }
@@ -988,6 +998,80 @@ int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *c
     const float *const *src_dev = (const float *const *)(pl->dmem + ws);
     float *const *out_dev = (float *const *)(pl->dmem + ws + 64);
     HIPCHK(ctx, launch_voxel(src_dev, src, c->n, voxel, out_dev, d_count, pl->dmem, voxel_sort_bytes(c->n), s));
+    return LSR_OK;
+}
+
+static int64_t ransac_hyp_count(int64_t n_hyp, int64_t nP) {
+    return n_hyp > 0 ? n_hyp : std::min<int64_t>(4000000, 100 * nP);
+}
+
+int lsr_ransac_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, const lsr_params *prm, int64_t n_hyp,
+                    lsr_ransac_result *d_out, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_params(ctx, prm)) || (rc = check_cloud(ctx, P, "P", true)) || (rc = check_cloud(ctx, Q, "Q", true)))
+        return rc;
+    if (!d_out) return fail(ctx, LSR_EINVAL, "d_out is NULL");
+    if (n_hyp > ((int64_t)1 << 31) - 1) return fail(ctx, LSR_EINVAL, "n_hyp %lld too large", (long long)n_hyp);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nh = ransac_hyp_count(n_hyp, P->n);
+    std::vector<FragIn> fr = {frag_of(P, 0, P->n), frag_of(Q, 0, Q->n)};
+    std::vector<char> key;
+    put(key, (int)K_RANSAC);
+    put(key, *prm);
+    put(key, nh);
+    for (auto &f : fr) { put(key, f.n); for (int a = 0; a < 6; ++a) put(key, f.src[a]); }
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, prm, key, s, &pl, ransac_bytes(nh)))) return rc;
+    const float r_cell = std::max(std::max(prm->r_normal, prm->r_feature), prm->max_corr);
+    HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
+    HIPCHK(ctx, build_grids(pl->g, r_cell, s));
+    HIPCHK(ctx, launch_normals(pl->g, prm->r_normal, pl->d, nullptr, s));
+    HIPCHK(ctx, launch_spfh(pl->g, prm->r_feature, pl->d, s));
+    HIPCHK(ctx, launch_fpfh(pl->g, prm->r_feature, pl->d, pl->ps, s));
+    if (prm->precision == LSR_BF16_SCREEN)
+        HIPCHK(ctx, launch_match_bf16(pl->g, pl->d, pl->m, pl->ps, pl->mscratch, ctx->tune_screen, s));
+    else
+        HIPCHK(ctx, launch_match_fp32(pl->g, pl->d, pl->m, s));
+    tmark("match", s);
+    HIPCHK(ctx, launch_ransac(pl->g, pl->d, pl->m, pl->ps, ransac_carve(pl->extra, nh), nh, *prm, pl->scan_tmp, d_out,
+                              nullptr, s));
+    tmark("ransac", s);
+    return LSR_OK;
+}
+
+int lsr_stage_ransac(lsr_ctx *ctx, const lsr_cloud *P, const double *d_nrmP, const lsr_cloud *Q,
+                     const double *d_nrmQ, const int32_t *d_nnQ, int64_t n_hyp, const lsr_params *prm,
+                     lsr_ransac_result *d_out, const lsr_ransac_trace *tr, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_params(ctx, prm)) || (rc = check_cloud(ctx, P, "P", false)) || (rc = check_cloud(ctx, Q, "Q", false)))
+        return rc;
+    if (!d_out || (P->n > 0 && !d_nnQ) || (prm->normal_check && (!d_nrmP || !d_nrmQ)))
+        return fail(ctx, LSR_EINVAL, "bad ransac arguments");
+    if (n_hyp > ((int64_t)1 << 31) - 1) return fail(ctx, LSR_EINVAL, "n_hyp %lld too large", (long long)n_hyp);
+    if (tr && tr->capacity < 0) return fail(ctx, LSR_EINVAL, "negative trace capacity");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nh = ransac_hyp_count(n_hyp, P->n);
+    std::vector<FragIn> fr = {frag_of(P, 0, P->n), frag_of(Q, 0, Q->n)};
+    std::vector<char> key;
+    put(key, (int)K_RANSAC_STAGE);
+    put(key, nh);
+    for (auto &f : fr) put(key, f);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, nullptr, key, s, &pl, ransac_bytes(nh)))) return rc;
+    HIPCHK(ctx, fill<uint32_t>((uint32_t *)pl->ps, 0u, (int64_t)(sizeof(PairState) / 4), s));
+    HIPCHK(ctx, build_grids(pl->g, prm->max_corr, s));
+    if (prm->normal_check) {
+        HIPCHK(ctx, copy<double>(pl->nrm_orig, d_nrmP, 3 * P->n, s));
+        HIPCHK(ctx, copy<double>(pl->nrm_orig + 3 * P->n, d_nrmQ, 3 * Q->n, s));
+        HIPCHK(ctx, launch_normals_inject(pl->g, pl->nrm_orig, pl->d, s));
+    }
+    HIPCHK(ctx, copy<int32_t>(pl->m.nn, d_nnQ, P->n, s));
+    HIPCHK(ctx, launch_ransac(pl->g, pl->d, pl->m, pl->ps, ransac_carve(pl->extra, nh), nh, *prm, pl->scan_tmp, d_out,
+                              tr, s));
     return LSR_OK;
 }
 

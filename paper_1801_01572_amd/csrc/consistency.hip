@@ -50,25 +50,14 @@ hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStre
     return hipGetLastError();
 }
 
-// SplitMix64 (Steele, Lea and Flood 2014): the n-th output for a seed is the
-// finaliser applied to the state seed + (n + 1) * golden-gamma.  Consecutive
-// attempts of one slot only add the gamma to the state; only the upper 32
-// bits of the output are used (the index draw below).
-constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
-
-__device__ __forceinline__ uint32_t splitmix64_hi(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return (uint32_t)((z ^ (z >> 31)) >> 32);
-}
-
 constexpr int TPB = 8192;    // trials per block (the trial table's granularity)
 constexpr int CONS_THREADS[] = {256, 128, 512};   // block widths the autotuner picks from
 constexpr int N_CONS_SHAPES = sizeof(CONS_THREADS) / sizeof(CONS_THREADS[0]);
 constexpr int RING = 128;    // drawn quadruples parked per wavefront before their edge tests
 constexpr int LDS_WORDS = 6144;   // correspondence words a block keeps in LDS (P fragments <= 196,608 points)
 
-// usable[g] = 1 for a P point with a reciprocal correspondence inside Q (scan input).
+// usable[g] = 1 for a P point with a reciprocal correspondence inside Q, or
+// with any descriptor neighbour inside Q when mutual is NULL (scan input).
 __global__ void __launch_bounds__(256) k_corr_usable(const Frag *frag, const Blk *blk, const int32_t *nn,
                                                      const uint8_t *mutual, int32_t *usable) {
     const Blk b = blk[blockIdx.x];
@@ -76,16 +65,12 @@ __global__ void __launch_bounds__(256) k_corr_usable(const Frag *frag, const Blk
     int i = b.start + threadIdx.x;
     if (i >= P.n) return;
     bool u = false;
-    if ((b.frag & 1) == 0 && P.partner >= 0 && mutual[P.off + i]) {
+    if ((b.frag & 1) == 0 && P.partner >= 0 && (!mutual || mutual[P.off + i])) {
         int32_t j = nn[P.off + i];
         u = j >= 0 && j < frag[P.partner].n;
     }
     usable[P.off + i] = u ? 1 : 0;
 }
-
-// First correspondence word of fragment f: words of 32 points, fragment
-// ranges kept apart by one spare word per fragment.
-__device__ __forceinline__ int64_t word_off(const Frag &F, int f) { return (F.off >> 5) + f; }
 
 // C packed in ascending P index at the scanned slots, one trial slot reading 32
 // contiguous bytes: (p_i, q_nnQ(i)) and i; the pair's list start and length.
@@ -123,13 +108,6 @@ __global__ void __launch_bounds__(256) k_corr_pack(const Frag *frag, const Blk *
 // correspondences' P points when it passes.  The edges are tested in order
 // and a correspondence is fetched only while every edge so far holds: the
 // verdict is that of the full test, with fewer random gathers.
-__device__ __forceinline__ bool edge_ok(const float4 &a0, const float4 &a1, const float4 &b0, const float4 &b1,
-                                        double t2) {
-    double a = pdist2(a0.x, a0.y, a0.z, b0.x, b0.y, b0.z);
-    double c = pdist2(a0.w, a1.x, a1.y, b0.w, b1.x, b1.y);
-    return !(a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a);
-}
-
 __device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, int32_t *flag) {
     const float4 p0 = cp[2 * e.x], p1 = cp[2 * e.y], q0 = cp[2 * e.x + 1], q1 = cp[2 * e.y + 1];
     if (!edge_ok(p0, q0, p1, q1, t2)) return 0;
@@ -271,15 +249,23 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
 
 size_t corr_words(int64_t ntot, int nfrag) { return (size_t)(ntot >> 5) + (size_t)nfrag + 1; }
 
-hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
-                              float tau, uint64_t seed, int shape, int32_t *scan_tmp, hipStream_t s) {
+hipError_t launch_corr_pack(const GridBufs &g, MatchBufs &m, PairState *ps, bool one_way, int32_t *scan_tmp,
+                            hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_corr_usable, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)m.nn, (const uint8_t *)m.mutual, m.flag);
+                       (const int32_t *)m.nn, one_way ? nullptr : (const uint8_t *)m.mutual, m.flag);
     hipError_t e = exclusive_scan_i32(m.flag, m.kpos, g.ntot, scan_tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_corr_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const int32_t *)m.nn, (const int32_t *)m.flag, (const int32_t *)m.kpos, m.cpack, m.cwords, ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
+                              float tau, uint64_t seed, int shape, int32_t *scan_tmp, hipStream_t s) {
+    if (g.ntot == 0) return hipSuccess;
+    hipError_t e = launch_corr_pack(g, m, ps, false, scan_tmp, s);
+    if (e != hipSuccess) return e;
     if ((e = fill<int32_t>(m.flag, 0, g.ntot, s)) != hipSuccess || ntb == 0) return e;
     double t2 = (double)tau * (double)tau;
     const Frag *fr = (const Frag *)g.frag;

@@ -69,6 +69,33 @@ __device__ __forceinline__ double pdist2(double xi, double yi, double zi, double
     return __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
 }
 
+// SplitMix64 (Steele, Lea and Flood 2014): the n-th output for a seed is the
+// finaliser applied to the state seed + (n + 1) * golden-gamma.  Consecutive
+// attempts of one draw slot only add the gamma to the state; the index draws
+// use the upper 32 bits of the output.
+constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint32_t splitmix64_hi(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)((z ^ (z >> 31)) >> 32);
+}
+
+// First correspondence word of fragment f: words of 32 points, fragment
+// ranges kept apart by one spare word per fragment.
+__device__ __forceinline__ int64_t word_off(const Frag &F, int f) { return (F.off >> 5) + f; }
+
+// Similar-polygon test of one edge (Algorithm 1's pre-rejection): packed
+// correspondences (p.xyz, q.x), (q.y, q.z, ...) of the edge's two ends; the
+// squared lengths in P and in Q must each be at least tau^2 times the other
+// (FP64 on the float inputs, pinned fma order); a zero edge fails.
+__device__ __forceinline__ bool edge_ok(const float4 &a0, const float4 &a1, const float4 &b0, const float4 &b1,
+                                        double t2) {
+    double a = pdist2(a0.x, a0.y, a0.z, b0.x, b0.y, b0.z);
+    double c = pdist2(a0.w, a1.x, a1.y, b0.w, b1.x, b1.y);
+    return !(a == 0.0 || c == 0.0 || a < t2 * c || c < t2 * a);
+}
+
 // XCD-aware block order.  The device hands workgroups to its 8 XCDs
 // round-robin (workgroup w runs on XCD w % 8), so consecutive entries of a
 // block table (neighbouring points, or one fragment's blocks) would run on
@@ -147,6 +174,16 @@ struct MatchBufs {
     int32_t *ki;               // compacted P index of each consistent correspondence
 };
 
+struct RansacBufs {            // one pair's RANSAC hypotheses (capacity cap)
+    unsigned long long *ctr;   // [0] survivors appended, [1] fitted, [2] largest completed inlier count
+    int4 *pos;                 // packed correspondence positions of the four members
+    int32_t *t;                // hypothesis index
+    double *T;                 // fitted [R | t], 12 per survivor
+    int32_t *cnt;              // inliers; -1: no unique fit; -2: stopped, cannot be chosen
+    double *ss;                // sum of the inliers' squared nearest distances
+    int64_t cap;
+};
+
 struct TrialBlk {              // consistency trials handled by one block
     int32_t pair;
     int32_t pad;
@@ -166,7 +203,18 @@ hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStre
 hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, const TrialBlk *tb, int ntb,
                               float tau, uint64_t seed, int shape, int32_t *scan_tmp, hipStream_t s);
 size_t corr_words(int64_t ntot, int nfrag);
+// Packs the correspondences of every P point (reciprocal ones, or every valid
+// descriptor neighbour when one_way) in ascending P index into m.cpack, the
+// per-32-point words into m.cwords, and each pair's list into ps (c_off,
+// c_cnt).  Uses m.flag and m.kpos as scratch.
+hipError_t launch_corr_pack(const GridBufs &g, MatchBufs &m, PairState *ps, bool one_way, int32_t *scan_tmp,
+                            hipStream_t s);
 hipError_t launch_compact(const GridBufs &g, MatchBufs &m, PairState *ps, int32_t *scan_tmp, hipStream_t s);
+size_t ransac_bytes(int64_t cap);
+RansacBufs ransac_carve(void *mem, int64_t cap);
+hipError_t launch_ransac(const GridBufs &g, const DescBufs &d, MatchBufs &m, PairState *ps, RansacBufs R,
+                         int64_t n_hyp, const lsr_params &prm, int32_t *scan_tmp, lsr_ransac_result *out,
+                         const lsr_ransac_trace *tr, hipStream_t s);
 hipError_t launch_gnc(const GridBufs &g, const MatchBufs &m, PairState *ps, int npairs, const lsr_params &prm,
                       hipStream_t s);
 hipError_t launch_gnc_direct(const double *p, const double *q, int64_t m, const lsr_params &prm, PairState *ps,

@@ -60,30 +60,41 @@ def check_chain(orc, P, Q, r, tr, prm, label=""):
     """Stage-by-stage parity of one pair of a full GPU run against the oracle.
 
     r: the GPU's result; tr: its per-point trace (numpy nnQ, nnP, mutual,
-    consistent of this pair).  Each GPU stage is checked on the GPU's own
-    input to that stage, so that a legitimate near-tie flip upstream cannot
-    hide a later mismatch:
-      descriptor neighbours equal the oracle's outside the tie margin (both
-      directions); the reciprocal flags follow from the GPU's neighbours;
-      the consistency flags equal the oracle's filter run on the GPU's
-      correspondences, bit for bit; the pose is within POSE_TOL of the
+    consistent, desc_P, desc_Q, valid_P, valid_Q of this pair).  Each GPU
+    stage is checked on the GPU's own input to that stage, so that a
+    legitimate difference upstream (a descriptor decision within MARGIN of a
+    bin edge, a near-tie) cannot hide a later mismatch:
+      validity flags exact, descriptors within DESC_RTOL of the oracle's
+      except the oracle's exempt points; descriptor neighbours equal the
+      oracle's matcher run on the GPU's descriptors outside the tie margin
+      (both directions); the reciprocal flags follow from the GPU's
+      neighbours; the consistency flags equal the oracle's filter run on the
+      GPU's correspondences, bit for bit; the pose is within POSE_TOL of the
       oracle's robust solve on the GPU's consistent set; the inlier count of
       the GPU's pose equals the oracle's verification of that pose, and the
       status follows from it.  Returns a summary (the number of
       correspondences that differ from the oracle's own, the tie-exempt
       share, the pose error)."""
     nP, nQ = P.shape[1], Q.shape[1]
-    nrmP, *_ = orc.normals(P, prm.r_normal)
-    nrmQ, *_ = orc.normals(Q, prm.r_normal)
-    F, vF, _, _ = orc.fpfh(P[:3], nrmP, prm.r_feature)
-    G, vG, _, _ = orc.fpfh(Q[:3], nrmQ, prm.r_feature)
+    nrmP, gP, oP = orc.normals(P, prm.r_normal)[:3]
+    nrmQ, gQ, oQ = orc.normals(Q, prm.r_normal)[:3]
+    F, vF, exP = desc_exempt(orc, P, nrmP, gP, oP, prm.r_feature)
+    G, vG, exQ = desc_exempt(orc, Q, nrmQ, gQ, oQ, prm.r_feature)
+    assert np.array_equal(tr["valid_P"], vF) and np.array_equal(tr["valid_Q"], vG), label
     assert (r["n_valid_P"], r["n_valid_Q"]) == (int(vF.sum()), int(vG.sum())), label
+    for Fo, Fg, ex, side in ((F, tr["desc_P"], exP, "P"), (G, tr["desc_Q"], exQ, "Q")):
+        err = np.linalg.norm(Fg - Fo, axis=1) / np.maximum(np.linalg.norm(Fo, axis=1), 1e-30)
+        bad = np.nonzero((err > DESC_RTOL) & ~ex)[0]
+        assert len(bad) == 0, (label, "descriptors", side, bad[:5], err[bad[:5]])
+    FG, GG = tr["desc_P"].astype(np.float32), tr["desc_Q"].astype(np.float32)
+    mg = orc.match(FG, tr["valid_P"], GG, tr["valid_Q"])
+    tP, tQ = orc.tie_flags(FG, GG, mg)
+    nnQ, nnP = tr["nnQ"].astype(np.int64), tr["nnP"].astype(np.int64)
+    badQ = np.nonzero((nnQ != mg["nnQ"]) & ~tP)[0]
+    badP = np.nonzero((nnP != mg["nnP"]) & ~tQ)[0]
+    assert len(badQ) == 0 and len(badP) == 0, (label, "neighbours outside the tie margin", badQ[:5], badP[:5])
     m = orc.match(F, vF, G, vG)
     tP, tQ = orc.tie_flags(F, G, m)
-    nnQ, nnP = tr["nnQ"].astype(np.int64), tr["nnP"].astype(np.int64)
-    badQ = np.nonzero((nnQ != m["nnQ"]) & ~tP)[0]
-    badP = np.nonzero((nnP != m["nnP"]) & ~tQ)[0]
-    assert len(badQ) == 0 and len(badP) == 0, (label, "neighbours outside the tie margin", badQ[:5], badP[:5])
     mut = orc.mutual(nnQ, nnP)
     assert np.array_equal(tr["mutual"].astype(bool), mut), label
     assert r["n_recip"] == int(mut.sum()), label
@@ -119,4 +130,6 @@ def trace_slice(tr, offP, offQ, b):
     """Pair b's part of a batch trace, as numpy arrays."""
     sP, sQ = slice(int(offP[b]), int(offP[b + 1])), slice(int(offQ[b]), int(offQ[b + 1]))
     return {"nnQ": tr["nnQ"][sP].cpu().numpy(), "nnP": tr["nnP"][sQ].cpu().numpy(),
-            "mutual": tr["mutual"][sP].cpu().numpy(), "consistent": tr["consistent"][sP].cpu().numpy()}
+            "mutual": tr["mutual"][sP].cpu().numpy(), "consistent": tr["consistent"][sP].cpu().numpy(),
+            "desc_P": tr["desc_P"][sP].cpu().numpy(), "desc_Q": tr["desc_Q"][sQ].cpu().numpy(),
+            "valid_P": tr["valid_P"][sP].cpu().numpy(), "valid_Q": tr["valid_Q"][sQ].cpu().numpy()}
