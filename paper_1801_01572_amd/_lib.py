@@ -57,6 +57,18 @@ class Trace(C.Structure):
                 ("desc_P", C.c_void_p), ("desc_Q", C.c_void_p), ("valid_P", C.c_void_p), ("valid_Q", C.c_void_p)]
 
 
+class RansacResult(C.Structure):
+    _fields_ = [("T", C.c_double * 16), ("inlier_ratio", C.c_double), ("fitness", C.c_double),
+                ("sum_d2", C.c_double), ("n_hypotheses", C.c_int64), ("n_survivors", C.c_int64),
+                ("n_fitted", C.c_int64), ("best", C.c_int64), ("n_inliers", C.c_int64),
+                ("n_valid_P", C.c_int64), ("n_valid_Q", C.c_int64), ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+class RansacTrace(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("hyp", C.c_void_p), ("members", C.c_void_p), ("n_inliers", C.c_void_p),
+                ("sum_d2", C.c_void_p), ("T", C.c_void_p)]
+
+
 class Cloud(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("nx", C.c_void_p), ("ny", C.c_void_p), ("nz", C.c_void_p), ("n", C.c_int64)]
@@ -91,6 +103,9 @@ def lib():
         L.lsr_stage_gnc.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, vp, vp]
         L.lsr_stage_verify.argtypes = [vp, C.POINTER(Cloud), vp, C.POINTER(Cloud), vp, vp, C.c_float, i32,
                                        C.c_float, vp, vp]
+        L.lsr_ransac_pair.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), C.POINTER(Params), i64, vp, vp]
+        L.lsr_stage_ransac.argtypes = [vp, C.POINTER(Cloud), vp, C.POINTER(Cloud), vp, vp, i64, C.POINTER(Params),
+                                       vp, C.POINTER(RansacTrace), vp]
         L.lsr_set_timing.argtypes = [vp, C.c_int]
         L.lsr_autotune.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32, C.POINTER(Params), i32,
                                    C.POINTER(Tune), vp]
@@ -101,7 +116,7 @@ def lib():
                   "lsr_register_batch_trace", "lsr_align_loss",
                   "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_voxel_downsample", "lsr_stage_match",
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify", "lsr_autotune", "lsr_get_tune",
-                  "lsr_set_tune"):
+                  "lsr_set_tune", "lsr_ransac_pair", "lsr_stage_ransac"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -417,3 +432,57 @@ def stage_verify(P, nrmP, Q, nrmQ, T, delta, normal_check=0, normal_cos=0.866025
                                      _ptr(T.contiguous()), C.c_float(delta), int(normal_check),
                                      C.c_float(normal_cos), _ptr(info), _stream()))
     return info
+
+
+RANSAC_RESULT_BYTES = C.sizeof(RansacResult)
+
+
+def _parse_ransac(buf: torch.Tensor) -> dict:
+    r = RansacResult.from_buffer_copy(buf.cpu().numpy().tobytes()[:RANSAC_RESULT_BYTES])
+    d = {name: getattr(r, name) for name, _ in RansacResult._fields_ if name not in ("T", "pad")}
+    d["T"] = np.array(r.T[:]).reshape(4, 4)
+    return d
+
+
+def ransac_pair(P: torch.Tensor, Q: torch.Tensor, params: Params | None = None, n_hyp: int = 0,
+                ctx: Context | None = None, out: torch.Tensor | None = None, sync: bool = True):
+    """Algorithm 1 on one pair (lsr_ransac_pair): descriptors, the one-way
+    descriptor neighbour cache, RANSAC consensus.  Returns a dict (or the raw
+    device result when sync=False)."""
+    ctx = ctx or get_context(P.device.index)
+    prm = params or default_params()
+    cp, cq = _cloud(P), _cloud(Q)
+    if out is None:
+        out = torch.empty(RANSAC_RESULT_BYTES, dtype=torch.uint8, device=P.device)
+    ctx.check(lib().lsr_ransac_pair(ctx.h, C.byref(cp), C.byref(cq), C.byref(prm), int(n_hyp), _ptr(out),
+                                    _stream()))
+    return _parse_ransac(out) if sync else out
+
+
+def stage_ransac(P, Q, nnQ, params=None, n_hyp=0, nrmP=None, nrmQ=None, trace_capacity=0, ctx=None):
+    """RANSAC consensus on injected inputs (lsr_stage_ransac).  P, Q: (3|6, N)
+    float32 CUDA tensors; nnQ: int32 CUDA tensor (P's descriptor neighbours in
+    Q, -1 none); nrmP/nrmQ: (N,3) float64 CUDA tensors when the normal check is
+    on.  Returns (result dict, trace dict of numpy arrays or None)."""
+    ctx = ctx or get_context(P.device.index)
+    prm = params or default_params()
+    cp, cq = _cloud(P, normals=False), _cloud(Q, normals=False)
+    out = torch.empty(RANSAC_RESULT_BYTES, dtype=torch.uint8, device=P.device)
+    tr = None
+    trs = None
+    if trace_capacity > 0:
+        dev, c = P.device, int(trace_capacity)
+        tr = {"hyp": torch.full((c,), -1, dtype=torch.int64, device=dev),
+              "members": torch.full((c, 4), -1, dtype=torch.int32, device=dev),
+              "n_inliers": torch.full((c,), -3, dtype=torch.int32, device=dev),
+              "sum_d2": torch.zeros(c, dtype=torch.float64, device=dev),
+              "T": torch.zeros((c, 16), dtype=torch.float64, device=dev)}
+        trs = RansacTrace(c, *[_ptr(tr[k]) for k in ("hyp", "members", "n_inliers", "sum_d2", "T")])
+    ctx.check(lib().lsr_stage_ransac(ctx.h, C.byref(cp), _ptr(nrmP), C.byref(cq), _ptr(nrmQ),
+                                     _ptr(nnQ.contiguous()), int(n_hyp), C.byref(prm), _ptr(out),
+                                     C.byref(trs) if trs is not None else None, _stream()))
+    res = _parse_ransac(out)
+    if tr is not None:
+        n = min(res["n_survivors"], trace_capacity)
+        tr = {k: v[:n].cpu().numpy() for k, v in tr.items()}
+    return res, tr

@@ -70,7 +70,8 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     from paper_1801_01572_amd import _lib
     pairs = [("lsr_cloud", _lib.Cloud), ("lsr_params", _lib.Params), ("lsr_result", _lib.Result),
-             ("lsr_tune", _lib.Tune), ("lsr_trace", _lib.Trace)]
+             ("lsr_tune", _lib.Tune), ("lsr_trace", _lib.Trace), ("lsr_ransac_result", _lib.RansacResult),
+             ("lsr_ransac_trace", _lib.RansacTrace)]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lsr.h"', "int main(void) {"]
     for cname, cls in pairs:
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
