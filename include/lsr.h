@@ -365,6 +365,20 @@ int lsr_stage_consistency(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q,
 int lsr_stage_gnc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m,
                   const lsr_params *prm, double *d_T, double *d_info, void *stream);
 
+/* lsr_stage_gnc for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same results, and no allocation of any kind.  The
+ * solver's state (one 1 KiB block per GPU, a static device array held until
+ * the process ends) is shared by every call on that GPU; calls that overlap
+ * on one GPU (different streams, or different host threads) race and must be
+ * serialised by the caller.  The state is written in full by each solve,
+ * so no call depends on an earlier one; its size does not depend on m (the
+ * correspondences are read from the caller's arrays), so no input size is
+ * refused for lack of scratch.  LSR_EHIP if the array's device address
+ * could not be obtained when the context was created. */
+int lsr_stage_gnc_noalloc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m,
+                          const lsr_params *prm, double *d_T, double *d_info, void *stream);
+
 /* Verification of pose d_T (device 16 doubles): d_info = {n_inliers, ratio,
  * fitness} as doubles.  Normals (device n x 3 doubles) may be NULL when the
  * normal check is off. */

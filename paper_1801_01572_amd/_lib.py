@@ -101,6 +101,7 @@ def lib():
         L.lsr_stage_consistency.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i64, C.c_float,
                                             C.c_uint64, vp, vp, vp]
         L.lsr_stage_gnc.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, vp, vp]
+        L.lsr_stage_gnc_noalloc.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, vp, vp]
         L.lsr_stage_verify.argtypes = [vp, C.POINTER(Cloud), vp, C.POINTER(Cloud), vp, vp, C.c_float, i32,
                                        C.c_float, vp, vp]
         L.lsr_ransac_pair.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), C.POINTER(Params), i64, vp, vp]
@@ -116,7 +117,7 @@ def lib():
                   "lsr_register_batch_trace", "lsr_align_loss",
                   "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_voxel_downsample", "lsr_stage_match",
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify", "lsr_autotune", "lsr_get_tune",
-                  "lsr_set_tune", "lsr_ransac_pair", "lsr_stage_ransac"):
+                  "lsr_set_tune", "lsr_ransac_pair", "lsr_stage_ransac", "lsr_stage_gnc_noalloc"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -422,6 +423,15 @@ def stage_gnc(p, q, params=None, ctx=None):
     ctx.check(lib().lsr_stage_gnc(ctx.h, _ptr(p.contiguous()), _ptr(q.contiguous()), p.shape[0], C.byref(prm),
                                   _ptr(T), _ptr(info), _stream()))
     return T.view(4, 4), info
+
+
+def stage_gnc_noalloc(p, q, T, info, params=None, ctx=None):
+    """lsr_stage_gnc_noalloc into caller-provided T (16 float64) and info (4
+    float64) CUDA tensors: p, q (m,3) float64 CUDA tensors."""
+    ctx = ctx or get_context(p.device.index)
+    prm = params or default_params()
+    ctx.check(lib().lsr_stage_gnc_noalloc(ctx.h, _ptr(p), _ptr(q), p.shape[0], C.byref(prm), _ptr(T), _ptr(info),
+                                          _stream()))
 
 
 def stage_verify(P, nrmP, Q, nrmQ, T, delta, normal_check=0, normal_cos=0.8660254, ctx=None):

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,8 @@ void tmark(const char *name, hipStream_t s) {
 
 struct lsr_ctx {
     int device = 0;
+    void *scratch = nullptr;       // this device's address of the allocation-free solve's state (or NULL)
+    hipError_t scratch_err = hipSuccess;
     size_t cap = 0;                // workspace cap in bytes (0: none)
     int tune_screen = 0;           // screen shape variant (autotuned)
     int tune_cons = 0;             // consistency block-width variant (autotuned)
@@ -522,6 +525,38 @@ void lsr_default_params(lsr_params *p) {
     p->seed = 0x1801015720ULL;
 }
 
+}  // extern "C"
+
+// State of the allocation-free pose solve (lsr_stage_gnc_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel: it uses the device
+// address hipGetSymbolAddress returns for the current device, looked up once
+// per device when the first context on it is created.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 1024;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static_assert(sizeof(PairState) <= NOALLOC_SCRATCH_BYTES, "the solve's state must fit the static scratch");
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_addr;     // per device; NULL until looked up
+
+// The calling thread's current device must be `device`.
+hipError_t scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize(device + 1, nullptr);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) { (void)hipGetLastError(); *out = nullptr; return e; }
+        g_scratch_addr[device] = ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
 int lsr_create(lsr_ctx **ctx, int device, size_t workspace_cap_bytes) {
     if (!ctx) return LSR_EINVAL;
     *ctx = nullptr;
@@ -531,6 +566,7 @@ int lsr_create(lsr_ctx **ctx, int device, size_t workspace_cap_bytes) {
     lsr_ctx *c = new lsr_ctx;
     c->device = device;
     c->cap = workspace_cap_bytes;
+    c->scratch_err = scratch_address(device, &c->scratch);
     *ctx = c;
     return LSR_OK;
 }
@@ -925,6 +961,24 @@ int lsr_stage_gnc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m,
     }
     HIPCHK(ctx, launch_gnc_direct(d_p, d_q, m, *prm, pl->ps, s));
     hipLaunchKernelGGL(k_gnc_info, dim3(1), dim3(64), 0, s, (const PairState *)pl->ps, d_T, d_info);
+    HIPCHK(ctx, hipGetLastError());
+    return LSR_OK;
+}
+
+int lsr_stage_gnc_noalloc(lsr_ctx *ctx, const double *d_p, const double *d_q, int64_t m, const lsr_params *prm,
+                          double *d_T, double *d_info, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_params(ctx, prm))) return rc;
+    if (m < 0 || (m > 0 && (!d_p || !d_q)) || !d_T || !d_info) return fail(ctx, LSR_EINVAL, "bad gnc arguments");
+    if (!ctx->scratch)
+        return fail(ctx, LSR_EHIP, "static scratch of device %d unavailable: hipGetSymbolAddress: %s", ctx->device,
+                    hipGetErrorString(ctx->scratch_err));
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    PairState *st = (PairState *)ctx->scratch;      // every output field is written by the solve
+    HIPCHK(ctx, launch_gnc_direct(d_p, d_q, m, *prm, st, s));
+    hipLaunchKernelGGL(k_gnc_info, dim3(1), dim3(64), 0, s, (const PairState *)st, d_T, d_info);
     HIPCHK(ctx, hipGetLastError());
     return LSR_OK;
 }
