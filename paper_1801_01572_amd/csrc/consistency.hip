@@ -53,8 +53,10 @@ hipError_t launch_mutual(const GridBufs &g, MatchBufs &m, PairState *ps, hipStre
 constexpr int TPB = 8192;    // trials per block (the trial table's granularity)
 constexpr int CONS_THREADS[] = {256, 128, 512};   // block widths the autotuner picks from
 constexpr int N_CONS_SHAPES = sizeof(CONS_THREADS) / sizeof(CONS_THREADS[0]);
-constexpr int RING = 128;    // drawn quadruples parked per wavefront before their edge tests
-constexpr int LDS_WORDS = 6144;   // correspondence words a block keeps in LDS (P fragments <= 196,608 points)
+constexpr int CH = 512;      // draw jobs (trial, slot) per result buffer; a wavefront owns two buffers
+constexpr uint32_t VOID = 0xFFFFFFFFu;
+constexpr int UNR = 4;       // draw attempts a lane makes per step (divides 64)
+constexpr size_t LDS_CAP = 65536; // dynamic LDS a consistency block may take
 
 // usable[g] = 1 for a P point with a reciprocal correspondence inside Q, or
 // with any descriptor neighbour inside Q when mutual is NULL (scan input).
@@ -104,6 +106,21 @@ __global__ void __launch_bounds__(256) k_corr_pack(const Frag *frag, const Blk *
     cpack[2 * c + 1] = make_float4(Q.src[1][j], Q.src[2][j], __int_as_float(i), 0.f);
 }
 
+// Correspondence words of a pair: for 32 consecutive P points the bits of
+// those with a correspondence and the packed position of the first.  In LDS
+// the two halves sit in separate arrays (a draw reads only the bits, with
+// consecutive words in consecutive banks); in global memory as pairs.
+struct LdsWords {
+    const uint32_t *bits, *base;
+    __device__ uint32_t b(uint32_t w) const { return bits[w]; }
+    __device__ uint32_t p(uint32_t w) const { return base[w]; }
+};
+struct GlobalWords {
+    const uint2 *w;
+    __device__ uint32_t b(uint32_t k) const { return w[k].x; }
+    __device__ uint32_t p(uint32_t k) const { return w[k].y; }
+};
+
 // Edge test of one drawn quadruple (positions in the packed C); flags the
 // correspondences' P points when it passes.  The edges are tested in order
 // and a correspondence is fetched only while every edge so far holds: the
@@ -122,104 +139,145 @@ __device__ __forceinline__ int quad_test(const float4 *cp, int4 e, double t2, in
     return 1;
 }
 
-// One wavefront's trials [t, t_end).  Every lane runs draws without waiting
-// for the others: a lane holds one trial (slot s, attempt state z, the P
-// indices and packed positions accepted so far) and takes one draw per step;
-// a lane whose trial completes or is void takes the wavefront's next trial
-// (ballot + mbcnt).  Complete quadruples are parked in the wavefront's LDS
-// ring and edge-tested 64 at a time, so that the gathers of the test run
-// with every lane busy.  Words: the pair's correspondence words (LDS or
-// global memory).
-template <class WordPtr>
-__device__ int wave_trials(WordPtr words, uint32_t nP, int64_t t, int64_t t_end, uint64_t seed, const float4 *cp,
-                           int4 *ring, double t2, int32_t *fl) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ uint64_t slot_state(uint64_t seed, int64_t t, int s) {
+    return seed + ((((uint64_t)t << 8) | ((uint64_t)s << 6)) + 1ull) * GAMMA;
+}
+
+// Slot s of trial t drawn from its first attempt, skipping P points without
+// a correspondence and the earlier slots' points x, y, w: the definition of
+// a slot's draw.  The bulk draws below take the first eligible point and
+// leave repeats (rare: about s in |C| per slot) to this.
+template <class W>
+__device__ uint32_t redraw(const W &words, uint32_t nP, uint64_t seed, int64_t t, int s, uint32_t x, uint32_t y,
+                           uint32_t w) {
+    uint64_t z = slot_state(seed, t, s);
+    for (int a = 0; a < 64; ++a, z += GAMMA) {
+        const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z) * nP) >> 32);
+        if (((words.b(i >> 5) >> (i & 31)) & 1u) && i != x && i != y && i != w) return i;
+    }
+    return VOID;
+}
+
+// Trials whose four slot draws are complete: repeats redrawn in slot order,
+// a void slot voids the trial, then the edge test.  r: the draws of trial
+// u at r[4u .. 4u + 3]; lanes take trials lane, lane + 64, ...
+template <class W>
+__device__ int finish_trials(const W &words, uint32_t nP, uint64_t seed, int64_t t_first, int ntr,
+                             const uint32_t *r, const float4 *cp, double t2, int32_t *fl) {
     int passed = 0;
-    int head = 0, cnt = 0;                       // ring (wave-uniform)
-    int64_t next = t;                            // wave's next unclaimed trial (wave-uniform)
+    for (int u = threadIdx.x & 63; u < ntr; u += 64) {
+        const uint4 d = *(const uint4 *)(r + 4 * u);
+        uint32_t i0 = d.x, i1 = d.y, i2 = d.z, i3 = d.w;
+        if (i0 == VOID || i1 == VOID || i2 == VOID || i3 == VOID) continue;
+        const int64_t t = t_first + u;
+        if (i1 == i0) i1 = redraw(words, nP, seed, t, 1, i0, i0, i0);
+        if (i1 == VOID) continue;
+        if (i2 == i0 || i2 == i1) i2 = redraw(words, nP, seed, t, 2, i0, i1, i1);
+        if (i2 == VOID) continue;
+        if (i3 == i0 || i3 == i1 || i3 == i2) i3 = redraw(words, nP, seed, t, 3, i0, i1, i2);
+        if (i3 == VOID) continue;
+        auto pos = [&](uint32_t i) {
+            const uint32_t k = i >> 5;
+            return (int)(words.p(k) + (uint32_t)__popc(words.b(k) & ((1u << (i & 31)) - 1u)));
+        };
+        passed += quad_test(cp, make_int4(pos(i0), pos(i1), pos(i2), pos(i3)), t2, fl);
+    }
+    return passed;
+}
+
+// One wavefront's trials [t0, t1), as 4 (t1 - t0) draw jobs (trial, slot) in
+// trial-major order.  A lane holds one job (its SplitMix64 state and attempt
+// count) and makes UNR attempts per step: the first attempt whose point has a
+// correspondence ends the job (its point goes to the result buffer), as does
+// the 64th (void).  A lane without a job claims the next in lane order
+// (ballot + mbcnt), so lanes stay busy whatever their jobs' lengths.  Jobs
+// fill two buffers of CH results; when every job of the older buffer has
+// ended, the wavefront finishes its trials and the buffer is reused.  Job
+// counters are per wavefront (fewer than 2^31 jobs: at most 4 TPB).
+template <class W>
+__device__ int wave_trials(const W &words, uint32_t nP, int64_t t0, int64_t t1, uint64_t seed, const float4 *cp,
+                           uint32_t *res, double t2, int32_t *fl) {
+    const int njobs = (int)(4 * (t1 - t0));
+    int passed = 0;
+    int next = 0;                  // next unclaimed job (wave-uniform)
+    int oldest = 0;                // first job of the older buffer (wave-uniform, multiple of CH)
+    int done_old = 0, done_new = 0;    // ended jobs in the older / newer buffer (wave-uniform)
     bool live = false;
-    int s = 0, a = 0;
-    uint32_t id0 = 0, id1 = 0, id2 = 0;
-    int4 pos = make_int4(0, 0, 0, 0);
-    uint64_t zs = 0, z = 0;
+    int j = 0, a = 0;
+    uint64_t z = 0;
     for (;;) {
-        // lanes without a trial claim the next ones in lane order
+        const int limit = min(njobs, oldest + 2 * CH);
         const unsigned long long need = __ballot(!live);
-        if (need && next < t_end) {
+        if (need && next < limit) {
             if (!live) {
-                const int64_t k = next + (int64_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                const int k = next + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-                if (k < t_end) {
+                if (k < limit) {
                     live = true;
-                    s = 0;
+                    j = k;
                     a = 0;
-                    zs = seed + (((uint64_t)k << 8) + 1ull) * GAMMA;
-                    z = zs;
+                    z = slot_state(seed, t0 + (k >> 2), k & 3);
                 }
             }
-            next += __popcll(need);
+            next = min(limit, next + (int)__popcll(need));
         }
-        bool done = false;
+        bool fin = false;
         if (live) {
-            const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z) * nP) >> 32);
-            const uint2 w = words[i >> 5];
-            const uint32_t below = w.x & ((1u << (i & 31)) - 1u);
-            const bool ok = ((w.x >> (i & 31)) & 1u) && !(s > 0 && i == id0) && !(s > 1 && i == id1) &&
-                            !(s > 2 && i == id2);
-            if (ok) {
-                const int p = (int)(w.y + (uint32_t)__popc(below));
-                if (s == 0) { id0 = i; pos.x = p; }
-                else if (s == 1) { id1 = i; pos.y = p; }
-                else if (s == 2) { id2 = i; pos.z = p; }
-                else { pos.w = p; done = true; }
-                ++s;
-                a = 0;
-                zs += 64ull * GAMMA;
-                z = zs;
-            } else if (++a == 64) {
-                live = false;                    // void trial
-            } else {
-                z += GAMMA;
+            // attempts a .. a + UNR - 1 (a multiple of UNR, 64 too): the first with a correspondence wins
+            uint32_t pick = VOID;
+#pragma unroll
+            for (int u = UNR - 1; u >= 0; --u) {
+                const uint32_t i = (uint32_t)(((uint64_t)splitmix64_hi(z + (uint64_t)u * GAMMA) * nP) >> 32);
+                if ((words.b(i >> 5) >> (i & 31)) & 1u) pick = i;
             }
-            if (done) live = false;
+            if (pick != VOID || a == 64 - UNR) {
+                res[j & (2 * CH - 1)] = pick;
+                live = false;
+                fin = true;
+            } else {
+                a += UNR;
+                z += (uint64_t)UNR * GAMMA;
+            }
         }
-        // park complete quadruples
-        const unsigned long long put = __ballot(done);
-        if (done) {
-            const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(put >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)put, 0u));
-            ring[(head + cnt + r) & (RING - 1)] = pos;
+        const unsigned long long f_all = __ballot(fin);
+        if (f_all) {
+            const int n_old = __popcll(__ballot(fin && j < oldest + CH));
+            done_old += n_old;
+            done_new += __popcll(f_all) - n_old;
         }
-        cnt += __popcll(put);
-        const bool any_live = __ballot(live) != 0ull;
-        const bool more = any_live || next < t_end;
-        if (cnt >= 64 || (!more && cnt > 0)) {
+        const int old_sz = min(CH, njobs - oldest);
+        if (done_old == old_sz) {
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int take = cnt < 64 ? cnt : 64;
-            if (lane < take) passed += quad_test(cp, ring[(head + lane) & (RING - 1)], t2, fl);
-            head = (head + take) & (RING - 1);
-            cnt -= take;
+            passed += finish_trials(words, nP, seed, t0 + (oldest >> 2), old_sz >> 2, res + (oldest & (2 * CH - 1)),
+                                    cp, t2, fl);
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            oldest += CH;
+            done_old = done_new;
+            done_new = 0;
+            if (oldest >= njobs) break;
         }
-        if (!more && cnt == 0) break;
     }
     return passed;
 }
 
 // Block b takes trials [first, first + TPB) of its pair, split into
-// contiguous ranges per wavefront.  Dynamic LDS: the wavefronts' rings, then
-// room for lds_words correspondence words; the pair's words go there when
-// they fit, else the draws read them from global memory.  Fewer than four
-// points with a correspondence: no trial can fill its four slots, none
-// passes.
+// contiguous ranges per wavefront.  Dynamic LDS: each wavefront's two result
+// buffers, then room for lds_words correspondence words (bits, then
+// positions); the pair's words go there when they fit, else the draws read
+// them from global memory.  Fewer than four points with a correspondence: no
+// trial can fill its four slots, none passes.
 template <int CT>
 __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const TrialBlk *tb, const float4 *cpack,
                                                     const uint2 *cwords, int32_t *flag, double t2, uint64_t seed,
                                                     PairState *ps, int lds_words) {
-    extern __shared__ int4 dyn[];
-    int4 *ring = dyn + (threadIdx.x >> 6) * RING;
-    uint2 *sw = (uint2 *)(dyn + (CT / 64) * RING);
+    extern __shared__ uint4 dyn[];
+    uint32_t *res = (uint32_t *)dyn + (threadIdx.x >> 6) * (2 * CH);
+    uint32_t *sbits = (uint32_t *)dyn + (CT / 64) * (2 * CH);
+    uint32_t *sbase = sbits + lds_words;
     const TrialBlk b = tb[blockIdx.x];
     const Frag &P = frag[2 * b.pair];
     const uint32_t nC = (uint32_t)ps[b.pair].c_cnt;
@@ -230,7 +288,11 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
     const uint2 *gw = cwords + word_off(P, 2 * b.pair);
     const bool in_lds = nw <= lds_words;
     if (in_lds) {
-        for (int k = threadIdx.x; k < nw; k += CT) sw[k] = gw[k];
+        for (int k = threadIdx.x; k < nw; k += CT) {
+            const uint2 w = gw[k];
+            sbits[k] = w.x;
+            sbase[k] = w.y;
+        }
         __syncthreads();
     }
     const int wave = threadIdx.x >> 6;
@@ -239,8 +301,8 @@ __global__ void __launch_bounds__(CT) k_consistency(const Frag *frag, const Tria
     int passed = 0;
     if (t0 < t1) {
         int32_t *fl = flag + P.off;
-        if (in_lds) passed = wave_trials<const uint2 *>(sw, nP, t0, t1, seed, cpack, ring, t2, fl);
-        else passed = wave_trials<const uint2 *>(gw, nP, t0, t1, seed, cpack, ring, t2, fl);
+        if (in_lds) passed = wave_trials(LdsWords{sbits, sbase}, nP, t0, t1, seed, cpack, res, t2, fl);
+        else passed = wave_trials(GlobalWords{gw}, nP, t0, t1, seed, cpack, res, t2, fl);
     }
     // passing-trial count per pair (integer, order independent)
     for (int o = 32; o > 0; o >>= 1) passed += __shfl_xor(passed, o, 64);
@@ -271,15 +333,20 @@ hipError_t launch_consistency(const GridBufs &g, MatchBufs &m, PairState *ps, co
     const Frag *fr = (const Frag *)g.frag;
     const float4 *cp = (const float4 *)m.cpack;
     const uint2 *cw = (const uint2 *)m.cwords;
-    const int lw = (int)std::min<int64_t>(((int64_t)g.max_np + 31) >> 5, LDS_WORDS);
-    auto lds = [&](int ct) { return (size_t)(ct / 64) * RING * sizeof(int4) + (size_t)lw * sizeof(uint2); };
+    // words kept in LDS per block width: the pair's words when they fit beside the result buffers
+    auto res_bytes = [](int ct) { return (size_t)(ct / 64) * 2 * CH * sizeof(uint32_t); };
+    auto lw = [&](int ct) {
+        return (int)std::min<int64_t>(((int64_t)g.max_np + 31) >> 5,
+                                      (int64_t)((LDS_CAP - res_bytes(ct)) / (2 * sizeof(uint32_t))));
+    };
+    auto lds = [&](int ct) { return res_bytes(ct) + (size_t)lw(ct) * 2 * sizeof(uint32_t); };
     switch (shape) {
     case 0: hipLaunchKernelGGL(k_consistency<CONS_THREADS[0]>, dim3(ntb), dim3(CONS_THREADS[0]), lds(CONS_THREADS[0]),
-                               s, fr, tb, cp, cw, m.flag, t2, seed, ps, lw); break;
+                               s, fr, tb, cp, cw, m.flag, t2, seed, ps, lw(CONS_THREADS[0])); break;
     case 1: hipLaunchKernelGGL(k_consistency<CONS_THREADS[1]>, dim3(ntb), dim3(CONS_THREADS[1]), lds(CONS_THREADS[1]),
-                               s, fr, tb, cp, cw, m.flag, t2, seed, ps, lw); break;
+                               s, fr, tb, cp, cw, m.flag, t2, seed, ps, lw(CONS_THREADS[1])); break;
     case 2: hipLaunchKernelGGL(k_consistency<CONS_THREADS[2]>, dim3(ntb), dim3(CONS_THREADS[2]), lds(CONS_THREADS[2]),
-                               s, fr, tb, cp, cw, m.flag, t2, seed, ps, lw); break;
+                               s, fr, tb, cp, cw, m.flag, t2, seed, ps, lw(CONS_THREADS[2])); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
