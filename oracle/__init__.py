@@ -37,6 +37,25 @@ class Result(C.Structure):
     ]
 
 
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32), ("z_min", C.c_double), ("z_max", C.c_double)]
+
+
+class Edge(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("T", C.c_double * 16)]
+
+
+class LoopParams(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("tau", C.c_double), ("l_min", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int32)]
+
+
+class LoopResult(C.Structure):
+    _fields_ = [("l", C.c_double), ("f_loop", C.c_double), ("energy", C.c_double), ("mu", C.c_double),
+                ("status", C.c_int32), ("iters", C.c_int32)]
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -54,6 +73,8 @@ def lib():
         _LIB.orc_ransac.restype = C.c_int32
         _LIB.orc_register_pair.restype = C.c_int32
         _LIB.orc_align_loss.restype = C.c_double
+        _LIB.orc_surfel_correct.restype = C.c_int64
+        _LIB.orc_loop_solve.restype = C.c_int32
     return _LIB
 
 
@@ -280,3 +301,67 @@ def result_dict(r: Result) -> dict:
     d = {k: getattr(r, k) for k, _ in Result._fields_ if k != "T"}
     d["T"] = np.array(r.T[:]).reshape(4, 4)
     return d
+
+
+def surfel_correct(S, t0, tu, T_old, T_new, t_kf, cam):
+    """Dense surface correction of Sec. VI, eq. 7 (see surfel.c).
+
+    S: (6, n) float32 surfels (x y z nx ny nz); t0, tu: (n,) int32 window;
+    T_old, T_new: (K, 4, 4) camera-to-world poses; t_kf: (K,) int32;
+    cam: dict of fx fy cx cy width height z_min z_max.
+    Returns (kept (6, m) float32, new_index (n,), k_obs (n,))."""
+    S = _f32(S)
+    n = S.shape[1]
+    t0 = np.ascontiguousarray(t0, np.int32); tu = np.ascontiguousarray(tu, np.int32)
+    To = _f64(T_old).reshape(-1, 16); Tn = _f64(T_new).reshape(-1, 16)
+    tk = np.ascontiguousarray(t_kf, np.int32)
+    out = np.zeros((6, n), np.float32)
+    idx = np.zeros(n, np.int32); k = np.zeros(n, np.int32)
+    cm = Camera(**cam)
+    m = lib().orc_surfel_correct(*[_p(S[r]) for r in range(6)], _p(t0), _p(tu), C.c_int64(n), _p(To), _p(Tn),
+                                 _p(tk), C.c_int32(len(tk)), C.byref(cm), *[_p(out[r]) for r in range(6)],
+                                 _p(idx), _p(k))
+    return out[:, :m].copy(), idx, k
+
+
+def loop_params(**kw) -> LoopParams:
+    """Loop-verification parameters: the paper's lambda = 1000, tau = 0.2 m,
+    l < 0.25 rejects (Sec. V); tol 1e-12, at most 100 iterations."""
+    p = LoopParams(lambda_=1000.0, tau=0.2, l_min=0.25, tol=1e-12, max_iter=100)
+    for k, v in kw.items():
+        setattr(p, "lambda_" if k == "lambda" else k, v)
+    return p
+
+
+def _edges(E):
+    arr = (Edge * max(len(E), 1))()
+    for k, (i, j, T) in enumerate(E):
+        arr[k].i, arr[k].j = int(i), int(j)
+        arr[k].T[:] = [float(x) for x in np.asarray(T, np.float64).reshape(16)]
+    return arr
+
+
+def edge_info(Pi, Pj, A, eps=0.05):
+    """(Lambda (6, 6), |K|) of an edge whose transform A maps fragment i into j."""
+    Pi = _f32(Pi); Pj = _f32(Pj)
+    L = np.zeros(36); cnt = C.c_int64()
+    lib().orc_edge_info(_p(Pi[0]), _p(Pi[1]), _p(Pi[2]), C.c_int64(Pi.shape[1]), _p(Pj[0]), _p(Pj[1]),
+                        _p(Pj[2]), C.c_int64(Pj.shape[1]), _p(_f64(A).reshape(16)), C.c_float(eps), _p(L),
+                        C.byref(cnt))
+    return L.reshape(6, 6), cnt.value
+
+
+def loop_solve(T_init, odo, L_odo, loop, L_loop, count_loop, params=None):
+    """One loop candidate against a chain.  odo: list of (i, j, A) for the
+    n - 1 odometry edges, L_odo (n - 1, 6, 6); loop: (i, j, A).  Returns
+    (result dict, optimised poses (n, 4, 4))."""
+    T_init = _f64(T_init).reshape(-1, 16)
+    n = T_init.shape[0]
+    prm = params or loop_params()
+    out = np.zeros((n, 16))
+    res = LoopResult()
+    lo = _f64(L_odo).reshape(-1, 36) if n > 1 else np.zeros((1, 36))
+    lib().orc_loop_solve(C.c_int32(n), _p(T_init), _edges(odo), _p(lo), _edges([loop]), _p(_f64(L_loop).reshape(36)),
+                         C.c_int64(int(count_loop)), C.byref(prm), _p(out), C.byref(res))
+    d = {k: getattr(res, k) for k, _ in LoopResult._fields_}
+    return d, out.reshape(n, 4, 4)

@@ -10,12 +10,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
+SOURCES = ["oracle.c", "surfel.c", "posegraph.c"]
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=gnu11", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
            "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
-           os.path.join(HERE, "oracle.c"), "-o", LIB + ".tmp", "-lm"]
+           *[os.path.join(HERE, f) for f in SOURCES], "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

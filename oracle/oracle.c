@@ -549,7 +549,7 @@ void orc_tie_flags(const double *F, int64_t nP, const double *G, int64_t nQ,
 }
 
 /* ------------------------------------------------------------------------ */
-/* O6: quadruple consistency filter (Section V, Algorithm 1: four points     */
+/* O6: quadruple consistency filter (Section IV, Algorithm 1: four points    */
 /* picked at random from P, their cached feature neighbours in Q, and the    */
 /* similar-polygon pre-rejection with tau = 0.9), used as a filter.          */
 /* Counter-based randomness: the n-th output r of SplitMix64 (Steele, Lea    */
@@ -752,7 +752,7 @@ static inline double xform_row(const double *r, double x, double y, double z, do
 }
 
 /* ------------------------------------------------------------------------ */
-/* O8: verification (Section V, Algorithm 1's hypothesis test: inlier      */
+/* O8: verification (Section IV, Algorithm 1's hypothesis test: inlier     */
 /* ratio and fitness; 3D grid search of eq. 1).  Inlier: the nearest q       */
 /* within delta of T p (optionally with normal agreement (R n_p) . n_q >=    */
 /* cos).  T p and R n_p use the pinned fma order of xform_row, so the        */
@@ -807,6 +807,25 @@ void orc_verify(const float *px, const float *py, const float *pz, const double 
     *n_inliers = cnt;
     *ratio = nP > 0 ? (double)cnt / (double)nP : 0.0;
     *fitness = cnt > 0 ? sqrt(ss / (double)cnt) : 0.0;
+}
+
+/* Per-point inlier flags of O8 without the normal check: flag[i] = 1 when
+ * some q lies within delta of T p_i (used by the loop verification's edge
+ * correspondences, Sec. V). */
+void orc_inliers(const float *px, const float *py, const float *pz, int64_t nP,
+                 const float *qx, const float *qy, const float *qz, int64_t nQ,
+                 const double *T, float delta, uint8_t *flag) {
+    ogrid g; grid_build(&g, qx, qy, qz, nQ, (double)delta);
+    double d2max = (double)delta * (double)delta;
+    #pragma omp parallel
+    {
+        int64_t cap = 4096; int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * cap);
+        #pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < nP; ++i)
+            flag[i] = inlier_d2(&g, px, py, pz, NULL, i, qx, qy, qz, NULL, T, d2max, 0, 0.0, &tmp, &cap) <= d2max;
+        free(tmp);
+    }
+    grid_free(&g);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -145,6 +145,68 @@ int32_t orc_register_pair(const float *const *P, int64_t nP, const float *const 
                           const orc_params *prm, orc_result *out,
                           int32_t *nnQ_out, uint8_t *consistent_out);
 
+/* Dense surface correction (Sec. VI, eq. 7; surfel.c).  Pinhole camera
+ * shared by the keyframes; poses are row-major 4x4 camera-to-world. */
+typedef struct {
+    double fx, fy, cx, cy;   /* intrinsics, pixels */
+    int32_t width, height;   /* image size, pixels */
+    double z_min, z_max;     /* depth range of an observation, m */
+} orc_camera;
+
+/* Moves each surfel by the mean pose correction of the keyframes that observe
+ * it inside its time window t0 < t_kf < tu, rotates its normal likewise, and
+ * removes the surfels no keyframe of their window observes.  Outputs are
+ * compacted in input order (room for n); new_index[s] is the output slot of
+ * surfel s or -1; k_obs[s] = |F|.  Returns the number kept. */
+int64_t orc_surfel_correct(const float *x, const float *y, const float *z, const float *nx, const float *ny,
+                           const float *nz, const int32_t *t0, const int32_t *tu, int64_t n,
+                           const double *T_old, const double *T_new, const int32_t *t_kf, int32_t n_kf,
+                           const orc_camera *cam, float *ox, float *oy, float *oz, float *onx, float *ony,
+                           float *onz, int32_t *new_index, int32_t *k_obs);
+
+/* Per-point inlier flags of the verification predicate (no normal check):
+ * flag[i] = 1 when some q lies within delta of T p_i. */
+void orc_inliers(const float *px, const float *py, const float *pz, int64_t nP,
+                 const float *qx, const float *qy, const float *qz, int64_t nQ,
+                 const double *T, float delta, uint8_t *flag);
+
+/* Loop verification by a line-process pose graph (Sec. V, eqs. 2-5;
+ * posegraph.c).  An edge: T maps fragment i's frame into fragment j's. */
+typedef struct {
+    int32_t i, j;
+    double T[16];
+} orc_edge;
+
+typedef struct {
+    double lambda;           /* odometry weight (paper: 1000) */
+    double tau;              /* distance threshold, m (paper: 0.2); mu = tau^2 |K_loop| */
+    double l_min;            /* reject when l < l_min (paper: 0.25) */
+    double tol;              /* stop when |delta|_inf < tol */
+    int32_t max_iter;
+} orc_loop_params;
+
+typedef struct {
+    double l;                /* line process of the loop edge at the returned poses */
+    double f_loop;           /* loop-edge energy xi^T Lambda xi there */
+    double energy;           /* E(T) with l eliminated */
+    double mu;
+    int32_t status;          /* accepted (l >= l_min), rejected, degenerate (singular system) */
+    int32_t iters;
+} orc_loop_result;
+
+/* Lambda (36 doubles, row-major) = sum of G_p^T G_p over the points p of
+ * fragment i with a point of fragment j within eps of A p; count = |K|. */
+void orc_edge_info(const float *ix, const float *iy, const float *iz, int64_t ni, const float *jx, const float *jy,
+                   const float *jz, int64_t nj, const double *A, float eps, double *Lambda, int64_t *count);
+
+/* One loop candidate against a chain of n fragments: odometry edges odo[s]
+ * (n - 1, edge s joins s and s + 1 in either direction) with information
+ * L_odo (36 each), the loop edge with L_loop and its correspondence count.
+ * T_out: the n optimised poses (node 0 fixed at T_init[0]). */
+int32_t orc_loop_solve(int32_t n, const double *T_init, const orc_edge *odo, const double *L_odo,
+                       const orc_edge *loop, const double *L_loop, int64_t count_loop, const orc_loop_params *prm,
+                       double *T_out, orc_loop_result *res);
+
 #ifdef __cplusplus
 }
 #endif
