@@ -198,13 +198,34 @@ int lsr_align_loss(lsr_ctx *ctx, const float *const P_xyz[3], int64_t nP,
  *   dP[i] += dE 2 l_c R^T r_c, dQ[j] += -dE 2 l_c r_c     (float32, device SoA, caller zeroes)
  *   d_dxi[6 k ...] = dE sum_c 2 l_c [p'_c x r_c ; r_c]     (left se(3) perturbation
  *                                                          T <- Exp(xi) T, xi = (omega, v))
- * Points repeated across correspondences accumulate by atomic addition.
+ * A point shared by several correspondences receives the FP64 sum of their
+ * contributions in ascending correspondence order, rounded once: results do
+ * not depend on scheduling.
  */
 int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t nP,
                             const float *const Q_xyz[3], int64_t nQ, const int32_t *d_corr, const int64_t *coff, int32_t n_problems,
                             const double *d_T, const double *d_mu, const double *d_dE,
                             float *const dP_xyz[3], float *const dQ_xyz[3], double *d_dxi,
                             void *stream);
+
+/*
+ * The pose retraction T <- [Rod(w) | v] T (xi = (w, v), Rod the rotation of
+ * the rotation vector w) under which lsr_align_loss_backward's d_dxi is the
+ * gradient at xi = 0, for n poses: d_T_out[16 k ..] = Exp(xi_k) d_T[16 k ..]
+ * (device, row-major 4x4 doubles; d_xi device n x 6).
+ */
+int lsr_se3_retract(lsr_ctx *ctx, int32_t n, const double *d_xi, const double *d_T, double *d_T_out, void *stream);
+
+/*
+ * Chain rule through the retraction: given d_g_left (device n x 6), the
+ * gradient of an energy with respect to a left perturbation of
+ * Exp(xi) T (lsr_align_loss_backward's d_dxi at that pose), writes d_g_xi
+ * (device n x 6), the gradient with respect to xi itself:
+ * dE/dw = J_l(w)^T (g_w - v x g_v), dE/dv = g_v, with J_l the left Jacobian
+ * of SO(3) (Rod(w + dw) = Rod(J_l(w) dw) Rod(w) to first order).
+ */
+int lsr_se3_retract_grad(lsr_ctx *ctx, int32_t n, const double *d_xi, const double *d_g_left, double *d_g_xi,
+                         void *stream);
 
 /*
  * Voxel downsampling of one cloud (Algorithm 1's first step, leaf size of
@@ -288,6 +309,115 @@ int lsr_ransac_pair(lsr_ctx *ctx, const lsr_cloud *P, const lsr_cloud *Q, const 
 int lsr_stage_ransac(lsr_ctx *ctx, const lsr_cloud *P, const double *d_nrmP, const lsr_cloud *Q,
                      const double *d_nrmQ, const int32_t *d_nnQ, int64_t n_hyp, const lsr_params *prm,
                      lsr_ransac_result *d_out, const lsr_ransac_trace *tr, void *stream);
+
+/* ---- dense surface correction after a loop closure (Sec. VI) ---- */
+
+/* Pinhole camera shared by the keyframes. */
+typedef struct {
+    double fx, fy, cx, cy;   /* intrinsics, pixels */
+    int32_t width, height;   /* image size, pixels */
+    double z_min, z_max;     /* depth range of an observation, m */
+} lsr_camera;
+
+/*
+ * Sec. VI, eq. 7: every surfel moves by the mean of the pose corrections
+ * T_new(f) T_old(f)^-1 of the keyframes f that observe it inside its fusion
+ * window t0 < t_kf(f) < tu; its normal becomes the normalised sum of
+ * R_new(f) R_old(f)^-1 n (unchanged if that sum vanishes).  Surfels that no
+ * keyframe of their window observes are removed; the rest keep their order.
+ * A keyframe observes a surfel when its position in the keyframe's old camera
+ * frame, c = R_old^T (p - t_old), has z_min <= c_z <= z_max and projects
+ * into the image (0 <= fx c_x + cx c_z < width c_z, likewise y with height):
+ * FP64 in a fixed operation order, so the decision depends on the inputs
+ * only.  No occlusion test.
+ *
+ * surfels: six device float arrays (x, y, z, nx, ny, nz) of n entries;
+ * d_t0, d_tu: device int32 windows (first and last update, frames).
+ * Keyframes (host, read before the call returns): h_T_old, h_T_new n_kf
+ * row-major 4x4 camera-to-world poses (doubles, 16 each), h_t_kf n_kf time
+ * stamps in non-decreasing order (LSR_EINVAL otherwise).  out: six device
+ * float arrays with room for n surfels, filled with the kept surfels in
+ * input order; d_new_index (device n int32, may be NULL): each surfel's
+ * output slot or -1; d_k_obs (device n int32, may be NULL): |F| per surfel;
+ * *d_n_kept (device int64): surfels kept.  0 <= n < 2^31, 0 <= n_kf <= 2^20.
+ * Not for stream capture (copies the keyframes from host memory).
+ */
+int lsr_surfel_correct(lsr_ctx *ctx, const float *const surfels[6], const int32_t *d_t0, const int32_t *d_tu,
+                       int64_t n, const double *h_T_old, const double *h_T_new, const int32_t *h_t_kf,
+                       int32_t n_kf, const lsr_camera *cam, float *const out[6], int32_t *d_new_index,
+                       int32_t *d_k_obs, int64_t *d_n_kept, void *stream);
+
+/* ---- loop verification by a line-process pose graph (Sec. V) ---- */
+
+/* An edge of a fragment chain: T (row-major 4x4) maps fragment i's frame
+ * into fragment j's (an odometry measurement, or a loop candidate's
+ * registration: lsr_register_pair(P = fragment i, Q = fragment j)). */
+typedef struct {
+    int32_t i, j;
+    double T[16];
+} lsr_edge;
+
+typedef struct {
+    double lambda;           /* odometry weight (Sec. V: 1000) */
+    double tau;              /* distance threshold, m (Sec. V: 0.2); mu = tau^2 |K_loop| */
+    double l_min;            /* a loop with l < l_min is rejected (Sec. V: 0.25) */
+    double tol;              /* Gauss-Newton stops when |step|_inf < tol */
+    float eps;               /* correspondence distance of an edge, m (Sec. V: 0.05) */
+    int32_t max_iter;        /* Gauss-Newton iterations at most */
+} lsr_loop_params;
+
+typedef struct {
+    double l;                /* line process of the loop edge at the returned poses */
+    double f_loop;           /* the loop edge's energy xi^T Lambda xi there */
+    double energy;           /* lambda sum f_odometry + mu f_loop / (mu + f_loop) */
+    double mu;               /* tau^2 |K_loop| */
+    int64_t n_corr;          /* |K_loop| */
+    int32_t status;          /* LSR_ACCEPTED (l >= l_min), LSR_REJECTED (also: no correspondences),
+                                LSR_DEGENERATE (singular normal equations) */
+    int32_t iters;
+} lsr_loop_result;
+
+/* Defaults: lambda 1000, tau 0.2, l_min 0.25, tol 1e-12, eps 0.05, max_iter 100. */
+void lsr_default_loop_params(lsr_loop_params *p);
+
+/*
+ * Edge information (Sec. V, eq. 5) of n_edges edges between the fragments
+ * frags[0 .. n_frags) (host array of device clouds; normals unused, may be
+ * NULL): K = the points p of fragment i with a point of fragment j within
+ * eps of T p (FP64, fixed operation order, on j's 3-D grid), Lambda =
+ * sum_{p in K} G_p^T G_p with G_p = [-[p]x | I] (p in fragment i's frame).
+ * h_edges: host, read before the call returns.  d_info: device n_edges x 36
+ * doubles (row-major 6x6 each); d_count: device n_edges int64 (|K|).
+ */
+int lsr_edge_info(lsr_ctx *ctx, const lsr_cloud *frags, int32_t n_frags, const lsr_edge *h_edges,
+                  int32_t n_edges, float eps, double *d_info, int64_t *d_count, void *stream);
+
+/*
+ * Sec. V, eqs. 2-5, for each of n_loops loop candidates independently: the
+ * chain's poses T (n_nodes, fragment -> world, initial values h_T_init,
+ * host) are moved to minimise lambda sum_s f_s + l f_loop + mu (sqrt(l) - 1)^2,
+ * f = xi^T Lambda xi with xi the rotation vector and translation of the
+ * edge's residual transform T_edge^-1 T_j^-1 T_i, mu = tau^2 |K_loop|, node 0
+ * fixed; l = (mu / (mu + f_loop))^2 at the optimum.  Odometry edge s (host,
+ * h_odo[s], n_nodes - 1 of them) must join nodes s and s + 1 (either
+ * direction); d_info_odo: device (n_nodes - 1) x 36 (lsr_edge_info).  Loop
+ * candidate c: h_loops[c] (host), d_info_loop + 36 c and d_count_loop[c]
+ * (device).  Gauss-Newton with l re-evaluated at every iterate.  d_res:
+ * device n_loops results; d_T_out: device n_loops x n_nodes x 16 optimised
+ * poses, or NULL.  2 <= n_nodes <= 4096, n_loops >= 0.
+ */
+int lsr_loop_solve(lsr_ctx *ctx, int32_t n_nodes, const double *h_T_init, const lsr_edge *h_odo,
+                   const double *d_info_odo, const lsr_edge *h_loops, int32_t n_loops, const double *d_info_loop,
+                   const int64_t *d_count_loop, const lsr_loop_params *prm, double *d_T_out,
+                   lsr_loop_result *d_res, void *stream);
+
+/*
+ * Both steps: the information of every odometry edge and loop candidate of
+ * a chain of n_frags fragments (frags[s] is node s), then lsr_loop_solve.
+ */
+int lsr_loop_verify(lsr_ctx *ctx, const lsr_cloud *frags, int32_t n_frags, const double *h_T_init,
+                    const lsr_edge *h_odo, const lsr_edge *h_loops, int32_t n_loops, const lsr_loop_params *prm,
+                    double *d_T_out, lsr_loop_result *d_res, void *stream);
 
 /* ---- autotuning of the batch driver's launch shapes ---- */
 

@@ -11,6 +11,7 @@ from ._lib import (  # noqa: F401
     Params, Result, LsrError, lib, default_params, Context, get_context,
     voxel_downsample, register_pair, register_batch, autotune, get_tune, set_tune, align_loss, align_loss_backward, set_timing, get_timing,
     stage_normals, stage_spfh, stage_fpfh, stage_match, stage_consistency, stage_gnc, stage_verify,
-    ransac_pair, stage_ransac, stage_gnc_noalloc,
+    ransac_pair, stage_ransac, stage_gnc_noalloc, surfel_correct, loop_params, edge_info, loop_solve, loop_verify,
+    se3_retract, se3_retract_grad,
 )
 from .autograd import AlignLoss  # noqa: F401

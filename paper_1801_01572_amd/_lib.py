@@ -69,6 +69,25 @@ class RansacTrace(C.Structure):
                 ("sum_d2", C.c_void_p), ("T", C.c_void_p)]
 
 
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32), ("z_min", C.c_double), ("z_max", C.c_double)]
+
+
+class Edge(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("T", C.c_double * 16)]
+
+
+class LoopParams(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("tau", C.c_double), ("l_min", C.c_double), ("tol", C.c_double),
+                ("eps", C.c_float), ("max_iter", C.c_int32)]
+
+
+class LoopResult(C.Structure):
+    _fields_ = [("l", C.c_double), ("f_loop", C.c_double), ("energy", C.c_double), ("mu", C.c_double),
+                ("n_corr", C.c_int64), ("status", C.c_int32), ("iters", C.c_int32)]
+
+
 class Cloud(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("nx", C.c_void_p), ("ny", C.c_void_p), ("nz", C.c_void_p), ("n", C.c_int64)]
@@ -107,6 +126,14 @@ def lib():
         L.lsr_ransac_pair.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), C.POINTER(Params), i64, vp, vp]
         L.lsr_stage_ransac.argtypes = [vp, C.POINTER(Cloud), vp, C.POINTER(Cloud), vp, vp, i64, C.POINTER(Params),
                                        vp, C.POINTER(RansacTrace), vp]
+        L.lsr_surfel_correct.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, i32, C.POINTER(Camera), vp, vp, vp, vp,
+                                         vp]
+        L.lsr_default_loop_params.argtypes = [C.POINTER(LoopParams)]
+        L.lsr_edge_info.argtypes = [vp, vp, i32, vp, i32, C.c_float, vp, vp, vp]
+        L.lsr_loop_solve.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, C.POINTER(LoopParams), vp, vp, vp]
+        L.lsr_loop_verify.argtypes = [vp, vp, i32, vp, vp, vp, i32, C.POINTER(LoopParams), vp, vp, vp]
+        L.lsr_se3_retract.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.lsr_se3_retract_grad.argtypes = [vp, i32, vp, vp, vp, vp]
         L.lsr_set_timing.argtypes = [vp, C.c_int]
         L.lsr_autotune.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32, C.POINTER(Params), i32,
                                    C.POINTER(Tune), vp]
@@ -117,7 +144,9 @@ def lib():
                   "lsr_register_batch_trace", "lsr_align_loss",
                   "lsr_align_loss_backward", "lsr_stage_normals", "lsr_stage_fpfh", "lsr_stage_spfh", "lsr_voxel_downsample", "lsr_stage_match",
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify", "lsr_autotune", "lsr_get_tune",
-                  "lsr_set_tune", "lsr_ransac_pair", "lsr_stage_ransac", "lsr_stage_gnc_noalloc"):
+                  "lsr_set_tune", "lsr_ransac_pair", "lsr_stage_ransac", "lsr_stage_gnc_noalloc",
+                  "lsr_surfel_correct", "lsr_edge_info", "lsr_loop_solve", "lsr_loop_verify", "lsr_se3_retract",
+                  "lsr_se3_retract_grad"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -302,6 +331,140 @@ def voxel_downsample(cloud: torch.Tensor, voxel: float, ctx: Context | None = No
     if m < 0:
         raise LsrError("voxel downsample: non-finite coordinate or voxel index out of range")
     return out[:, :m]
+
+
+def surfel_correct(S: torch.Tensor, t0: torch.Tensor, tu: torch.Tensor, T_old, T_new, t_kf, camera: dict,
+                   ctx: Context | None = None, sync: bool = True):
+    """Dense surface correction of a surfel map (see lsr_surfel_correct).
+
+    S: (6, n) float32 CUDA surfels; t0, tu: (n,) int32 CUDA windows; T_old,
+    T_new: (K, 4, 4) float64 keyframe poses and t_kf (K,) int32 time stamps
+    (host arrays); camera: fx fy cx cy width height z_min z_max.  Returns
+    (kept (6, m) view, new_index (n,), k_obs (n,), n_kept tensor); with sync
+    the kept view is trimmed to m, else it has n columns and n_kept is a
+    device tensor to read later."""
+    ctx = ctx or get_context(S.device.index)
+    n = S.shape[1]
+    c = _cloud(S)
+    To = np.ascontiguousarray(T_old, np.float64).reshape(-1, 16)
+    Tn = np.ascontiguousarray(T_new, np.float64).reshape(-1, 16)
+    tk = np.ascontiguousarray(t_kf, np.int32)
+    out = torch.empty((6, max(n, 1)), dtype=torch.float32, device=S.device)
+    new_index = torch.empty(max(n, 1), dtype=torch.int32, device=S.device)
+    k_obs = torch.empty(max(n, 1), dtype=torch.int32, device=S.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=S.device)
+    src = (C.c_void_p * 6)(c.x, c.y, c.z, c.nx, c.ny, c.nz)
+    dst = (C.c_void_p * 6)(*[out[k].data_ptr() for k in range(6)])
+    cam = Camera(**camera)
+    ctx.check(lib().lsr_surfel_correct(ctx.h, src, _ptr(t0.contiguous()), _ptr(tu.contiguous()), n,
+                                       To.ctypes.data_as(C.c_void_p), Tn.ctypes.data_as(C.c_void_p),
+                                       tk.ctypes.data_as(C.c_void_p), len(tk), C.byref(cam), dst, _ptr(new_index),
+                                       _ptr(k_obs), _ptr(cnt), _stream()))
+    if not sync:
+        return out, new_index[:n], k_obs[:n], cnt
+    m = int(cnt.cpu()[0])
+    return out[:, :m], new_index[:n], k_obs[:n], m
+
+
+def loop_params(**kw) -> LoopParams:
+    """lsr_loop_params with the paper's defaults (lambda 1000, tau 0.2 m,
+    l_min 0.25, eps 0.05 m); keyword 'lambda' sets lambda_."""
+    p = LoopParams()
+    lib().lsr_default_loop_params(C.byref(p))
+    for k, v in kw.items():
+        k = "lambda_" if k == "lambda" else k
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _edge_array(E):
+    arr = (Edge * max(len(E), 1))()
+    for k, (i, j, T) in enumerate(E):
+        arr[k].i, arr[k].j = int(i), int(j)
+        arr[k].T[:] = [float(v) for v in np.asarray(T, np.float64).reshape(16)]
+    return arr
+
+
+def _cloud_array(frags):
+    arr = (Cloud * len(frags))()
+    for k, f in enumerate(frags):
+        arr[k] = _cloud(f, normals=False)
+    return arr
+
+
+def _parse_loop(buf: torch.Tensor, n: int):
+    raw = buf.cpu().numpy().tobytes()
+    sz = C.sizeof(LoopResult)
+    out = []
+    for k in range(n):
+        r = LoopResult.from_buffer_copy(raw[k * sz:(k + 1) * sz])
+        out.append({name: getattr(r, name) for name, _ in LoopResult._fields_})
+    return out
+
+
+def edge_info(frags, edges, eps=0.05, ctx=None):
+    """Information matrices (m, 6, 6) float64 and correspondence counts (m,)
+    int64 (CUDA tensors) of edges (i, j, T) between fragments (CUDA (3|6, n))."""
+    ctx = ctx or get_context(frags[0].device.index)
+    m = len(edges)
+    info = torch.zeros((max(m, 1), 6, 6), dtype=torch.float64, device=frags[0].device)
+    cnt = torch.zeros(max(m, 1), dtype=torch.int64, device=frags[0].device)
+    ctx.check(lib().lsr_edge_info(ctx.h, _cloud_array(frags), len(frags), _edge_array(edges), m, C.c_float(eps),
+                                  _ptr(info), _ptr(cnt), _stream()))
+    return info[:m], cnt[:m]
+
+
+def loop_solve(T_init, odo, info_odo, loops, info_loop, count_loop, params=None, ctx=None, poses=True):
+    """Line-process pose graph per loop candidate (see lsr_loop_solve).
+    Returns (list of result dicts, optimised poses (C, n, 4, 4) CUDA tensor or None)."""
+    ctx = ctx or get_context(info_odo.device.index)
+    T_init = np.ascontiguousarray(T_init, np.float64).reshape(-1, 16)
+    n, c = T_init.shape[0], len(loops)
+    dev = info_odo.device
+    res = torch.zeros(max(c, 1) * C.sizeof(LoopResult), dtype=torch.uint8, device=dev)
+    T_out = torch.zeros((max(c, 1), n, 4, 4), dtype=torch.float64, device=dev) if poses else None
+    ctx.check(lib().lsr_loop_solve(ctx.h, n, T_init.ctypes.data_as(C.c_void_p), _edge_array(odo),
+                                   _ptr(info_odo.contiguous()), _edge_array(loops), c,
+                                   _ptr(info_loop.contiguous()), _ptr(count_loop.contiguous()),
+                                   C.byref(params or loop_params()), _ptr(T_out), _ptr(res), _stream()))
+    return _parse_loop(res, c), (T_out[:c] if poses else None)
+
+
+def loop_verify(frags, T_init, odo, loops, params=None, ctx=None, poses=True, sync=True):
+    """Edge information of the chain and its loop candidates, then the pose
+    graph per candidate (see lsr_loop_verify)."""
+    ctx = ctx or get_context(frags[0].device.index)
+    T_init = np.ascontiguousarray(T_init, np.float64).reshape(-1, 16)
+    n, c = T_init.shape[0], len(loops)
+    dev = frags[0].device
+    res = torch.zeros(max(c, 1) * C.sizeof(LoopResult), dtype=torch.uint8, device=dev)
+    T_out = torch.zeros((max(c, 1), n, 4, 4), dtype=torch.float64, device=dev) if poses else None
+    ctx.check(lib().lsr_loop_verify(ctx.h, _cloud_array(frags), len(frags), T_init.ctypes.data_as(C.c_void_p),
+                                    _edge_array(odo), _edge_array(loops), c, C.byref(params or loop_params()),
+                                    _ptr(T_out), _ptr(res), _stream()))
+    if not sync:
+        return res, T_out
+    return _parse_loop(res, c), (T_out[:c] if poses else None)
+
+
+def se3_retract(xi: torch.Tensor, T: torch.Tensor, ctx=None) -> torch.Tensor:
+    """[Rod(w) | v] T per pose (xi (n, 6) and T (n, 4, 4) float64 CUDA)."""
+    ctx = ctx or get_context(T.device.index)
+    xi, T = xi.contiguous(), T.contiguous()
+    out = torch.empty_like(T)
+    ctx.check(lib().lsr_se3_retract(ctx.h, T.shape[0], _ptr(xi), _ptr(T), _ptr(out), _stream()))
+    return out
+
+
+def se3_retract_grad(xi: torch.Tensor, g_left: torch.Tensor, ctx=None) -> torch.Tensor:
+    """dE/dxi of E(Exp(xi) T) from the left-perturbation gradient at Exp(xi) T."""
+    ctx = ctx or get_context(xi.device.index)
+    xi, g_left = xi.contiguous(), g_left.contiguous()
+    out = torch.empty_like(g_left)
+    ctx.check(lib().lsr_se3_retract_grad(ctx.h, xi.shape[0], _ptr(xi), _ptr(g_left), _ptr(out), _stream()))
+    return out
 
 
 def _xyz_ptrs(t):

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsr.so")
 SOURCES = ["api.hip", "grid.hip", "descriptors.hip", "match.hip", "match_bf16.hip", "consistency.hip",
-           "gnc.hip", "verify.hip", "align_loss.hip", "voxel.hip", "ransac.hip"]
+           "gnc.hip", "verify.hip", "align_loss.hip", "voxel.hip", "ransac.hip", "surfel.hip",
+           "posegraph.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics"]

@@ -7,6 +7,8 @@
 // their memory and never allocate; a batch plan additionally keeps the HIP
 // graph of its launch sequence and replays it.
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -22,11 +24,14 @@ namespace lsr {
 int trials_per_block();
 int64_t align_blocks(const int64_t *coff, int nprob, void *host_tab, int64_t *pblk);
 size_t align_block_bytes();
+size_t align_seg_bytes(int64_t m, int64_t nP, int64_t nQ);
 hipError_t launch_align(bool bwd, const float *const P[3], int64_t nP, const float *const Q[3], int64_t nQ,
-                        const int32_t *corr,
+                        const int32_t *corr, int64_t m,
                         const void *dev_tab, int64_t nblocks, const int64_t *dev_pblk, int nprob, const double *T,
                         const double *mu, const double *dE, double *partial, double *out, float *const dP[3],
-                        float *const dQ[3], hipStream_t s);
+                        float *const dQ[3], char *seg, hipStream_t s);
+hipError_t launch_retract(int n, const double *xi, const double *T, double *Tout, hipStream_t s);
+hipError_t launch_retract_grad(int n, const double *xi, const double *gl, double *gx, hipStream_t s);
 hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairState *ps, void *scratch, int shape,
                              hipStream_t s);
 int screen_shapes();
@@ -42,7 +47,8 @@ using namespace lsr;
 
 namespace {
 
-enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN, K_VOXEL, K_RANSAC, K_RANSAC_STAGE };
+enum PlanKind { K_PAIRS = 1, K_NORMALS, K_FPFH, K_MATCH, K_CONS, K_VERIFY, K_ALIGN, K_VOXEL, K_RANSAC, K_RANSAC_STAGE,
+                K_SURFEL, K_EDGE, K_LOOP };
 
 struct FragIn {
     const float *src[6];
@@ -68,6 +74,7 @@ struct Plan {
     int64_t *cnt64 = nullptr;      // small device scalars for stage outputs
     void *mscratch = nullptr;      // matcher scratch
     void *extra = nullptr;         // stage-specific scratch (RANSAC hypotheses)
+    bool busy = false;             // in use by the current call: never released to make room
     int64_t pk_rows = 0;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -178,7 +185,8 @@ bool capturing(hipStream_t s) {
 int add_plan(lsr_ctx *c, std::unique_ptr<Plan> p, Plan **out) {
     if (c->plans.size() >= MAX_PLANS) {
         HIPCHK(c, hipDeviceSynchronize());
-        c->plans.erase(c->plans.begin());
+        for (size_t k = 0; k < c->plans.size(); ++k)
+            if (!c->plans[k]->busy) { c->plans.erase(c->plans.begin() + (ptrdiff_t)k); break; }
     }
     c->plans.push_back(std::move(p));
     *out = c->plans.back().get();
@@ -196,10 +204,14 @@ int plan_malloc(lsr_ctx *c, Plan *P, size_t bytes) {
         for (auto &q : c->plans) used += q->dbytes;
         if (used + bytes > c->cap) {
             HIPCHK(c, hipDeviceSynchronize());
-            while (!c->plans.empty() && used + bytes > c->cap) {
-                used -= c->plans.front()->dbytes;
-                c->plans.erase(c->plans.begin());
+            for (size_t k = 0; k < c->plans.size() && used + bytes > c->cap;) {
+                if (c->plans[k]->busy) { ++k; continue; }
+                used -= c->plans[k]->dbytes;
+                c->plans.erase(c->plans.begin() + (ptrdiff_t)k);
             }
+            if (used + bytes > c->cap)
+                return fail(c, LSR_ENOMEM, "workspace of %zu bytes does not fit beside the %zu bytes in use (cap %zu)",
+                            bytes, used, c->cap);
         }
     }
     hipError_t e = hipMalloc((void **)&P->dmem, bytes);
@@ -1055,6 +1067,257 @@ int lsr_voxel_downsample(lsr_ctx *ctx, const lsr_cloud *c, float voxel, float *c
     return LSR_OK;
 }
 
+int lsr_surfel_correct(lsr_ctx *ctx, const float *const surfels[6], const int32_t *d_t0, const int32_t *d_tu,
+                       int64_t n, const double *h_T_old, const double *h_T_new, const int32_t *h_t_kf,
+                       int32_t n_kf, const lsr_camera *cam, float *const out[6], int32_t *d_new_index,
+                       int32_t *d_k_obs, int64_t *d_n_kept, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (n < 0 || n > INT32_MAX) return fail(ctx, LSR_EINVAL, "surfel count %lld out of range", (long long)n);
+    if (n_kf < 0 || n_kf > (1 << 20)) return fail(ctx, LSR_EINVAL, "keyframe count %d out of range", n_kf);
+    if (!cam || !d_n_kept || (n > 0 && (!surfels || !d_t0 || !d_tu || !out)) ||
+        (n_kf > 0 && (!h_T_old || !h_T_new || !h_t_kf)))
+        return fail(ctx, LSR_EINVAL, "NULL surfel-correction argument");
+    for (int a = 0; a < 6 && n > 0; ++a)
+        if (!surfels[a] || !out[a]) return fail(ctx, LSR_EINVAL, "NULL surfel array");
+    const double cp[6] = {cam->fx, cam->fy, cam->cx, cam->cy, cam->z_min, cam->z_max};
+    for (double v : cp)
+        if (!std::isfinite(v)) return fail(ctx, LSR_EINVAL, "non-finite camera parameter");
+    if (cam->width <= 0 || cam->height <= 0) return fail(ctx, LSR_EINVAL, "bad image size");
+    for (int32_t f = 0; f < n_kf; ++f) {
+        if (f > 0 && h_t_kf[f] < h_t_kf[f - 1])
+            return fail(ctx, LSR_EINVAL, "keyframe time stamps must not decrease (keyframe %d)", f);
+        for (int k = 0; k < 16; ++k)
+            if (!std::isfinite(h_T_old[16 * f + k]) || !std::isfinite(h_T_new[16 * f + k]))
+                return fail(ctx, LSR_EINVAL, "non-finite pose of keyframe %d", f);
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        HIPCHK(ctx, fill<int64_t>(d_n_kept, 0, 1, s));
+        return LSR_OK;
+    }
+    std::vector<char> key;
+    put(key, (int)K_SURFEL);
+    put(key, n);
+    put(key, n_kf);
+    for (int a = 0; a < 6; ++a) put(key, out[a]);
+    Plan *pl = find_plan(ctx, key);
+    int rc;
+    if (!pl) {
+        auto P = std::make_unique<Plan>();
+        P->key = key;
+        if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
+        if ((rc = plan_malloc(ctx, P.get(), surfel_ws_bytes(n, n_kf)))) return rc;
+        HIPCHK(ctx, hipHostMalloc((void **)&P->hmem, 64, hipHostMallocDefault));
+        std::memcpy(P->hmem, out, 6 * sizeof(float *));
+        SurfelWs w = surfel_carve(P->dmem, n, n_kf);
+        HIPCHK(ctx, hipMemcpyAsync(w.out_ptrs, P->hmem, 6 * sizeof(float *), hipMemcpyHostToDevice, s));
+        if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
+    }
+    SurfelWs w = surfel_carve(pl->dmem, n, n_kf);
+    if (n_kf > 0) {
+        // stream-ordered copies that return once done: the host arrays may change after the call
+        HIPCHK(ctx, hipMemcpyWithStream(w.T_old, h_T_old, sizeof(double) * 16 * n_kf, hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyWithStream(w.T_new, h_T_new, sizeof(double) * 16 * n_kf, hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyWithStream(w.t_kf, h_t_kf, sizeof(int32_t) * n_kf, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(ctx, launch_surfel_correct(surfels, d_t0, d_tu, n, w, n_kf, *cam, w.out_ptrs, d_new_index, d_k_obs,
+                                      d_n_kept, s));
+    return LSR_OK;
+}
+
+void lsr_default_loop_params(lsr_loop_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->lambda = 1000.0;
+    p->tau = 0.2;
+    p->l_min = 0.25;
+    p->tol = 1e-12;
+    p->eps = 0.05f;
+    p->max_iter = 100;
+}
+
+static int check_edges(lsr_ctx *ctx, const lsr_edge *e, int32_t m, int32_t n_frags, const char *what) {
+    if (m > 0 && !e) return fail(ctx, LSR_EINVAL, "%s: NULL edge array", what);
+    for (int32_t k = 0; k < m; ++k) {
+        if (e[k].i < 0 || e[k].j < 0 || e[k].i >= n_frags || e[k].j >= n_frags || e[k].i == e[k].j)
+            return fail(ctx, LSR_EINVAL, "%s %d joins fragments %d and %d (of %d)", what, k, e[k].i, e[k].j, n_frags);
+        for (int q = 0; q < 16; ++q)
+            if (!std::isfinite(e[k].T[q])) return fail(ctx, LSR_EINVAL, "%s %d: non-finite transform", what, k);
+    }
+    return LSR_OK;
+}
+
+// Edge information of `edges` over a plan whose pair e is (frags[i_e], frags[j_e]).
+static int edge_info_run(lsr_ctx *ctx, const lsr_cloud *frags, int32_t n_frags, const lsr_edge *edges,
+                         int32_t m, float eps, double *d_info, int64_t *d_count, hipStream_t s) {
+    int rc;
+    std::vector<FragIn> fr;
+    int64_t nblk = 0;
+    for (int32_t k = 0; k < m; ++k) {
+        const lsr_cloud *a = frags + edges[k].i, *b = frags + edges[k].j;
+        fr.push_back(frag_of(a, 0, a->n));
+        fr.push_back(frag_of(b, 0, b->n));
+        nblk += (a->n + 255) / 256 + (b->n + 255) / 256;
+    }
+    std::vector<char> key;
+    put(key, (int)K_EDGE);
+    put(key, m);
+    for (auto &f : fr) put(key, f);
+    const size_t a_bytes = sizeof(double) * 16 * (size_t)m, part_bytes = sizeof(double) * 10 * (size_t)(nblk + 1);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl && (rc = make_batch_plan(ctx, fr, true, nullptr, key, s, &pl, a_bytes + part_bytes + 512))) return rc;
+    double *dA = (double *)pl->extra;
+    double *partial = (double *)((char *)pl->extra + ((a_bytes + 255) & ~(size_t)255));
+    std::vector<double> A(16 * (size_t)m);
+    for (int32_t k = 0; k < m; ++k) std::memcpy(&A[16 * (size_t)k], edges[k].T, sizeof(double) * 16);
+    if (m > 0) HIPCHK(ctx, hipMemcpyWithStream(dA, A.data(), a_bytes, hipMemcpyHostToDevice, s));
+    tmark("edge_start", s);
+    HIPCHK(ctx, build_grids(pl->g, eps, s));
+    tmark("edge_grids", s);
+    HIPCHK(ctx, launch_edge_info(pl->g, dA, m, eps, partial, d_info, d_count, s));
+    tmark("edge_info", s);
+    return LSR_OK;
+}
+
+static int check_frags(lsr_ctx *ctx, const lsr_cloud *frags, int32_t n_frags) {
+    if (!frags || n_frags < 1) return fail(ctx, LSR_EINVAL, "no fragments");
+    int rc;
+    for (int32_t f = 0; f < n_frags; ++f)
+        if ((rc = check_cloud(ctx, frags + f, "fragment", false))) return rc;
+    return LSR_OK;
+}
+
+int lsr_edge_info(lsr_ctx *ctx, const lsr_cloud *frags, int32_t n_frags, const lsr_edge *h_edges,
+                  int32_t n_edges, float eps, double *d_info, int64_t *d_count, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_frags(ctx, frags, n_frags)) || (rc = check_edges(ctx, h_edges, n_edges, n_frags, "edge")))
+        return rc;
+    if (n_edges < 0 || !(eps > 0) || !(eps < 1e30f) || (n_edges > 0 && (!d_info || !d_count)))
+        return fail(ctx, LSR_EINVAL, "bad edge-information arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (n_edges == 0) return LSR_OK;
+    return edge_info_run(ctx, frags, n_frags, h_edges, n_edges, eps, d_info, d_count, (hipStream_t)stream);
+}
+
+static int check_loop_params(lsr_ctx *ctx, const lsr_loop_params *p) {
+    if (!p) return fail(ctx, LSR_EINVAL, "NULL loop parameters");
+    if (!(p->lambda > 0) || !std::isfinite(p->lambda) || !(p->tau > 0) || !std::isfinite(p->tau) ||
+        !(p->l_min >= 0) || !(p->l_min <= 1) || !(p->tol >= 0) || !std::isfinite(p->tol) || !(p->eps > 0) ||
+        !(p->eps < 1e30f) || p->max_iter < 0)
+        return fail(ctx, LSR_EINVAL, "bad loop parameters");
+    return LSR_OK;
+}
+
+// Plan of a pose-graph solve: device copies of the poses and edges, per-candidate scratch.
+static int loop_solve_run(lsr_ctx *ctx, int32_t n, const double *h_T_init, const lsr_edge *h_odo,
+                          const double *d_info_odo, const lsr_edge *h_loops, int32_t n_loops,
+                          const double *d_info_loop, const int64_t *d_count_loop, const lsr_loop_params *prm,
+                          double *d_T_out, lsr_loop_result *d_res, hipStream_t s) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t bT = al(sizeof(double) * 16 * (size_t)n), bo = al(sizeof(lsr_edge) * (size_t)(n - 1)),
+                 bl = al(sizeof(lsr_edge) * (size_t)std::max(n_loops, 1)),
+                 bs = al(loop_scratch_bytes(n, std::max(n_loops, 1)));
+    std::vector<char> key;
+    put(key, (int)K_LOOP);
+    put(key, n);
+    put(key, n_loops);
+    Plan *pl = find_plan(ctx, key);
+    int rc;
+    if (!pl) {
+        auto P = std::make_unique<Plan>();
+        P->key = key;
+        if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
+        if ((rc = plan_malloc(ctx, P.get(), bT + bo + bl + bs))) return rc;
+        if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
+    }
+    double *dT = (double *)pl->dmem;
+    lsr_edge *dodo = (lsr_edge *)(pl->dmem + bT);
+    lsr_edge *dloops = (lsr_edge *)(pl->dmem + bT + bo);
+    double *scratch = (double *)(pl->dmem + bT + bo + bl);
+    HIPCHK(ctx, hipMemcpyWithStream(dT, h_T_init, sizeof(double) * 16 * (size_t)n, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyWithStream(dodo, h_odo, sizeof(lsr_edge) * (size_t)(n - 1), hipMemcpyHostToDevice, s));
+    if (n_loops > 0)
+        HIPCHK(ctx, hipMemcpyWithStream(dloops, h_loops, sizeof(lsr_edge) * (size_t)n_loops, hipMemcpyHostToDevice,
+                                        s));
+    tmark("loop_start", s);
+    HIPCHK(ctx, launch_loop_solve(n, dT, dodo, d_info_odo, dloops, n_loops, d_info_loop, d_count_loop, *prm,
+                                  scratch, d_T_out, d_res, s));
+    tmark("loop_solve", s);
+    return LSR_OK;
+}
+
+static int check_chain(lsr_ctx *ctx, int32_t n, const double *h_T_init, const lsr_edge *h_odo, const lsr_edge *h_loops,
+                       int32_t n_loops) {
+    if (n < 2 || n > 4096) return fail(ctx, LSR_EINVAL, "chain of %d nodes (2 .. 4096)", n);
+    if (n_loops < 0) return fail(ctx, LSR_EINVAL, "negative loop count");
+    if (!h_T_init) return fail(ctx, LSR_EINVAL, "NULL initial poses");
+    for (int64_t k = 0; k < 16 * (int64_t)n; ++k)
+        if (!std::isfinite(h_T_init[k])) return fail(ctx, LSR_EINVAL, "non-finite initial pose");
+    int rc;
+    if ((rc = check_edges(ctx, h_odo, n - 1, n, "odometry edge")) ||
+        (rc = check_edges(ctx, h_loops, n_loops, n, "loop candidate")))
+        return rc;
+    for (int32_t k = 0; k < n - 1; ++k)
+        if (std::min(h_odo[k].i, h_odo[k].j) != k || std::max(h_odo[k].i, h_odo[k].j) != k + 1)
+            return fail(ctx, LSR_EINVAL, "odometry edge %d must join nodes %d and %d", k, k, k + 1);
+    return LSR_OK;
+}
+
+int lsr_loop_solve(lsr_ctx *ctx, int32_t n_nodes, const double *h_T_init, const lsr_edge *h_odo,
+                   const double *d_info_odo, const lsr_edge *h_loops, int32_t n_loops, const double *d_info_loop,
+                   const int64_t *d_count_loop, const lsr_loop_params *prm, double *d_T_out,
+                   lsr_loop_result *d_res, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_loop_params(ctx, prm)) || (rc = check_chain(ctx, n_nodes, h_T_init, h_odo, h_loops, n_loops)))
+        return rc;
+    if (!d_info_odo || (n_loops > 0 && (!d_info_loop || !d_count_loop || !d_res)))
+        return fail(ctx, LSR_EINVAL, "NULL loop-solve array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return loop_solve_run(ctx, n_nodes, h_T_init, h_odo, d_info_odo, h_loops, n_loops, d_info_loop, d_count_loop,
+                          prm, d_T_out, d_res, (hipStream_t)stream);
+}
+
+int lsr_loop_verify(lsr_ctx *ctx, const lsr_cloud *frags, int32_t n_frags, const double *h_T_init,
+                    const lsr_edge *h_odo, const lsr_edge *h_loops, int32_t n_loops, const lsr_loop_params *prm,
+                    double *d_T_out, lsr_loop_result *d_res, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    int rc;
+    if ((rc = check_loop_params(ctx, prm)) || (rc = check_frags(ctx, frags, n_frags)) ||
+        (rc = check_chain(ctx, n_frags, h_T_init, h_odo, h_loops, n_loops)))
+        return rc;
+    if (n_loops > 0 && !d_res) return fail(ctx, LSR_EINVAL, "NULL loop results");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t m = n_frags - 1 + n_loops;
+    std::vector<lsr_edge> all(h_odo, h_odo + (n_frags - 1));
+    all.insert(all.end(), h_loops, h_loops + n_loops);
+    // information and counts of every edge: a plan of its own keyed by the chain's size
+    std::vector<char> key;
+    put(key, (int)K_LOOP);
+    put(key, -1);
+    put(key, m);
+    Plan *pl = find_plan(ctx, key);
+    if (!pl) {
+        auto P = std::make_unique<Plan>();
+        P->key = key;
+        if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
+        if ((rc = plan_malloc(ctx, P.get(), (sizeof(double) * 36 + sizeof(int64_t)) * (size_t)m + 256))) return rc;
+        if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
+    }
+    double *info = (double *)pl->dmem;
+    int64_t *cnt = (int64_t *)(pl->dmem + sizeof(double) * 36 * (size_t)m);
+    pl->busy = true;             // the solve reads it after the next steps' allocations
+    rc = edge_info_run(ctx, frags, n_frags, all.data(), m, prm->eps, info, cnt, s);
+    if (!rc)
+        rc = loop_solve_run(ctx, n_frags, h_T_init, h_odo, info, h_loops, n_loops, info + 36 * (size_t)(n_frags - 1),
+                            cnt + (n_frags - 1), prm, d_T_out, d_res, s);
+    pl->busy = false;
+    return rc;
+}
+
 static int64_t ransac_hyp_count(int64_t n_hyp, int64_t nP) {
     return n_hyp > 0 ? n_hyp : std::min<int64_t>(4000000, 100 * nP);
 }
@@ -1146,9 +1409,13 @@ static int align_common(lsr_ctx *ctx, bool bwd, const float *const P_xyz[3], int
     if (coff[n_problems] > 0 && !d_corr) return fail(ctx, LSR_EINVAL, "NULL correspondences");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
+    if (nP >= INT32_MAX || nQ >= INT32_MAX || coff[n_problems] >= INT32_MAX)
+        return fail(ctx, LSR_EINVAL, "align-loss sizes beyond 2^31 - 1");
     std::vector<char> key;
     put(key, (int)K_ALIGN);
     put(key, n_problems);
+    put(key, bwd ? nP : (int64_t)-1);
+    put(key, bwd ? nQ : (int64_t)-1);
     key.insert(key.end(), (const char *)coff, (const char *)(coff + n_problems + 1));
     Plan *pl = find_plan(ctx, key);
     if (!pl) {
@@ -1162,6 +1429,7 @@ static int align_common(lsr_ctx *ctx, bool bwd, const float *const P_xyz[3], int
         size_t h_tab = H.add(tab.size()), h_pb = H.add(sizeof(int64_t) * pblk.size());
         Layout D;
         size_t o_tabs = D.add(H.total), o_part = D.add(sizeof(double) * 6 * (size_t)std::max<int64_t>(nb, 1));
+        size_t o_seg = D.add(bwd ? align_seg_bytes(coff[n_problems], nP, nQ) : 256);
         if (capturing(s)) return fail(ctx, LSR_ENOMEM, "allocation during capture");
         HIPCHK(ctx, hipHostMalloc((void **)&P->hmem, H.total, hipHostMallocDefault));
         int rc1 = plan_malloc(ctx, P.get(), D.total);
@@ -1171,13 +1439,14 @@ static int align_common(lsr_ctx *ctx, bool bwd, const float *const P_xyz[3], int
         P->atab = P->dmem + o_tabs + h_tab;
         P->apblk = (int64_t *)(P->dmem + o_tabs + h_pb);
         P->apart = (double *)(P->dmem + o_part);
+        P->extra = P->dmem + o_seg;
         P->anblk = nb;
         HIPCHK(ctx, hipMemcpyAsync(P->dmem + o_tabs, P->hmem, H.total, hipMemcpyHostToDevice, s));
         int rc;
         if ((rc = add_plan(ctx, std::move(P), &pl))) return rc;
     }
-    HIPCHK(ctx, launch_align(bwd, P_xyz, nP, Q_xyz, nQ, d_corr, pl->atab, pl->anblk, pl->apblk, n_problems, d_T, d_mu, d_dE,
-                             pl->apart, out, dP, dQ, s));
+    HIPCHK(ctx, launch_align(bwd, P_xyz, nP, Q_xyz, nQ, d_corr, coff[n_problems], pl->atab, pl->anblk, pl->apblk,
+                             n_problems, d_T, d_mu, d_dE, pl->apart, out, dP, dQ, (char *)pl->extra, s));
     return LSR_OK;
 }
 
@@ -1195,6 +1464,23 @@ int lsr_align_loss_backward(lsr_ctx *ctx, const float *const P_xyz[3], int64_t n
     if (!d_dxi) return ctx ? fail(ctx, LSR_EINVAL, "NULL d_dxi") : LSR_EINVAL;
     return align_common(ctx, true, P_xyz, nP, Q_xyz, nQ, d_corr, coff, n_problems, d_T, d_mu, d_dE, d_dxi, dP_xyz, dQ_xyz,
                         stream);
+}
+
+int lsr_se3_retract(lsr_ctx *ctx, int32_t n, const double *d_xi, const double *d_T, double *d_T_out, void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (n < 0 || (n > 0 && (!d_xi || !d_T || !d_T_out))) return fail(ctx, LSR_EINVAL, "bad retraction arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_retract(n, d_xi, d_T, d_T_out, (hipStream_t)stream));
+    return LSR_OK;
+}
+
+int lsr_se3_retract_grad(lsr_ctx *ctx, int32_t n, const double *d_xi, const double *d_g_left, double *d_g_xi,
+                         void *stream) {
+    if (!ctx) return LSR_EINVAL;
+    if (n < 0 || (n > 0 && (!d_xi || !d_g_left || !d_g_xi))) return fail(ctx, LSR_EINVAL, "bad retraction arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_retract_grad(n, d_xi, d_g_left, d_g_xi, (hipStream_t)stream));
+    return LSR_OK;
 }
 
 }  // extern "C"

@@ -191,6 +191,15 @@ struct TrialBlk {              // consistency trials handled by one block
     int64_t count;             // trials of this pair (all blocks)
 };
 
+struct SurfelWs {              // scratch of one surfel correction (surfel_carve)
+    float *tmp;                // 6 x n updates at the surfels' own indices
+    int32_t *keep, *pos;       // keep flags and their exclusive scan
+    int32_t *scan_tmp;
+    double *T_old, *T_new;     // keyframe table: n_kf x 16 each
+    int32_t *t_kf;
+    float **out_ptrs;          // the six output array pointers (device copy)
+};
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t build_grids(GridBufs &g, float r_cell, hipStream_t s);
@@ -228,6 +237,20 @@ hipError_t launch_align_loss(const float *const P[3], const float *const Q[3], c
                              const double *dE, double *partial, int64_t nblocks, const int64_t *blk_first,
                              const int32_t *blk_prob_first, int nprob, double *E_out, float *const dP[3],
                              float *const dQ[3], double *dxi, hipStream_t s);
+
+size_t surfel_ws_bytes(int64_t n, int32_t n_kf);
+SurfelWs surfel_carve(char *ws, int64_t n, int32_t n_kf);
+hipError_t launch_surfel_correct(const float *const src[6], const int32_t *t0, const int32_t *tu, int64_t n,
+                                 const SurfelWs &w, int32_t n_kf, const lsr_camera &cam, float *const *out_dev,
+                                 int32_t *new_index, int32_t *k_obs, int64_t *n_kept, hipStream_t s);
+
+hipError_t launch_edge_info(const GridBufs &g, const double *A, int n_edges, float eps, double *partial,
+                            double *info, int64_t *count, hipStream_t s);
+size_t loop_scratch_bytes(int n, int n_loops);
+hipError_t launch_loop_solve(int n, const double *T_init, const lsr_edge *odo, const double *L_odo,
+                             const lsr_edge *loops, int n_loops, const double *L_loop, const int64_t *cnt_loop,
+                             const lsr_loop_params &prm, double *scratch, double *T_out, lsr_loop_result *res,
+                             hipStream_t s);
 
 // Optional stage timing: when enabled, launchers record an event after each
 // named step on the launch stream (eager runs only, never under capture).

@@ -14,7 +14,8 @@ before the loop correction (old poses) carries a random-walk drift of about
 the keyframes pass the surfel's azimuth about the room centre at
 f_c = K azimuth / 2 pi, and the window spans f_c -+ U(0.08, 0.16) K keyframes
 (first and last update, in frames); surfels near azimuth 0 are seen again
-when the loop closes, outside their window.
+when the loop closes, outside their window.  Surfels are stored in order of
+their first update, as a fusion map appends a surfel when it is first seen.
 
 Only seeded sampling and pose composition here, none of the correction's
 arithmetic.
@@ -107,5 +108,6 @@ def make_surfel_map(n: int, n_kf: int, seed: int = SURFEL_SEED) -> SurfelMap:
     h = rng.uniform(0.08, 0.16, size=n) * n_kf
     t0 = np.maximum(np.round(10 * (fc - h)), -1).astype(np.int32)
     tu = np.round(10 * (fc + h)).astype(np.int32)
-    return SurfelMap(S=S.astype(np.float32), t0=t0, tu=tu, T_old=T_old, T_new=T_new, t_kf=t_kf,
-                     camera=dict(CAMERA))
+    order = np.argsort(t0, kind="stable")
+    return SurfelMap(S=np.ascontiguousarray(S[:, order], dtype=np.float32), t0=np.ascontiguousarray(t0[order]),
+                     tu=np.ascontiguousarray(tu[order]), T_old=T_old, T_new=T_new, t_kf=t_kf, camera=dict(CAMERA))

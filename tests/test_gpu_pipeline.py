@@ -215,6 +215,81 @@ def test_autograd_function_fd(L):
         assert abs(fd - xi.grad[0, k].item()) <= 1e-4 * (1 + abs(fd))
 
 
+def test_autograd_function_nonzero_xi(L, orc):
+    """E at the retracted pose [Rod(w) | v] T equals the oracle's energy at
+    that pose (retraction written here with scipy); dE/dxi equals central
+    differences of the forward; dP, dQ equal the oracle's gradients there."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(8)
+    n = 600
+    p = rng.uniform(-1, 1, (n, 3))
+    T0 = np.eye(4)
+    T0[:3, :3] = Rotation.from_rotvec([0.2, -0.5, 0.3]).as_matrix()
+    T0[:3, 3] = [0.3, -0.1, 0.2]
+    xi0 = np.array([0.25, -0.1, 0.4, 0.05, 0.3, -0.2])
+    Tx = np.eye(4)
+    Tx[:3, :3] = Rotation.from_rotvec(xi0[:3]).as_matrix()
+    Tx[:3, 3] = xi0[3:]
+    Tx = Tx @ T0
+    q = (Tx[:3, :3] @ p.T).T + Tx[:3, 3] + rng.normal(0, 0.05, (n, 3))
+    p32, q32 = p.astype(np.float32), q.astype(np.float32)
+    C = np.stack([np.arange(n), np.arange(n)], 1).astype(np.int32)
+    P = dev(p32.T).requires_grad_(True)
+    Q = dev(q32.T).requires_grad_(True)
+    mu = dev(np.array([0.01]))
+    xi = dev(xi0[None]).requires_grad_(True)
+    E = L.AlignLoss.apply(P, Q, dev(C), [0, n], dev(T0[None]), mu, xi)
+    Eo, dpo, dqo, _ = orc.align_loss(p32.astype(np.float64), q32.astype(np.float64), Tx, 0.01)
+    assert abs(E.item() - Eo) <= 1e-10 * (1 + abs(Eo))
+    E.sum().backward()
+    assert np.abs(P.grad.cpu().numpy().T - dpo).max() <= 1e-6 * (1 + np.abs(dpo).max())
+    assert np.abs(Q.grad.cpu().numpy().T - dqo).max() <= 1e-6 * (1 + np.abs(dqo).max())
+    h = 1e-6
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        Ep = L.AlignLoss.apply(P.detach(), Q.detach(), dev(C), [0, n], dev(T0[None]), mu, dev((xi0 + e)[None]))
+        Em = L.AlignLoss.apply(P.detach(), Q.detach(), dev(C), [0, n], dev(T0[None]), mu, dev((xi0 - e)[None]))
+        fd = (Ep.item() - Em.item()) / (2 * h)
+        assert abs(fd - xi.grad[0, k].item()) <= 1e-5 * (1 + abs(fd)), (k, fd, xi.grad[0, k].item())
+
+
+def test_adjoint_deterministic_with_shared_points(L, orc):
+    """Points shared by several correspondences (each P point three times,
+    Q points twice, across two problems): two backward runs give the same
+    bits, and the sums equal the oracle's per-correspondence gradients
+    accumulated in FP64."""
+    rng = np.random.default_rng(9)
+    nP, nQ = 2000, 3000
+    P = rng.uniform(-1, 1, (3, nP)).astype(np.float32)
+    Q = rng.uniform(-1, 1, (3, nQ)).astype(np.float32)
+    m = 6000
+    ci = np.tile(np.arange(nP), 3)[rng.permutation(m)]
+    cj = np.tile(rng.permutation(nQ), 2)[:m]
+    C = np.stack([ci, cj], 1).astype(np.int32)
+    coff = [0, 2500, m]
+    T = np.stack([np.eye(4), np.eye(4)])
+    T[1, :3, 3] = [0.1, 0.0, -0.2]
+    mu = np.array([0.05, 0.02])
+    dE = np.array([1.0, -0.5])
+    outs = []
+    for _ in range(2):
+        dP, dQ, dxi = L.align_loss_backward(dev(P), dev(Q), dev(C), coff, dev(T), dev(mu), dev(dE))
+        outs.append((dP.cpu().numpy(), dQ.cpu().numpy(), dxi.cpu().numpy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    wp = np.zeros((nP, 3))
+    wq = np.zeros((nQ, 3))
+    for k in range(2):
+        sl = slice(coff[k], coff[k + 1])
+        _, dp, dq, _ = orc.align_loss(P.T[C[sl, 0]].astype(np.float64), Q.T[C[sl, 1]].astype(np.float64), T[k],
+                                      mu[k])
+        np.add.at(wp, C[sl, 0], dE[k] * dp)
+        np.add.at(wq, C[sl, 1], dE[k] * dq)
+    assert np.abs(outs[0][0].T - wp).max() <= 1e-6 * (1 + np.abs(wp).max())
+    assert np.abs(outs[0][1].T - wq).max() <= 1e-6 * (1 + np.abs(wq).max())
+
+
 def test_autotune_variants_agree(L):
     """Every launch-shape variant computes the same bits; the autotuner picks one and times all."""
     import paper_1801_01572_amd._lib as lib

@@ -71,12 +71,13 @@ def test_binding_structs_match_the_header(tmp_path):
     from paper_1801_01572_amd import _lib
     pairs = [("lsr_cloud", _lib.Cloud), ("lsr_params", _lib.Params), ("lsr_result", _lib.Result),
              ("lsr_tune", _lib.Tune), ("lsr_trace", _lib.Trace), ("lsr_ransac_result", _lib.RansacResult),
-             ("lsr_ransac_trace", _lib.RansacTrace)]
+             ("lsr_ransac_trace", _lib.RansacTrace), ("lsr_camera", _lib.Camera),
+             ("lsr_edge", _lib.Edge), ("lsr_loop_params", _lib.LoopParams), ("lsr_loop_result", _lib.LoopResult)]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lsr.h"', "int main(void) {"]
     for cname, cls in pairs:
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
-        for fname, _ in cls._fields_:
-            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+        for fname, _ in cls._fields_:   # a trailing underscore marks a C name that is a Python keyword
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname.rstrip("_")}));')
     lines += ["  return 0;", "}"]
     src = tmp_path / "abi.c"
     src.write_text("\n".join(lines) + "\n")
