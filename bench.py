@@ -30,24 +30,125 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _rot_angle(A, B):
+    import numpy as np
+    return float(np.arccos(np.clip((np.trace(A.T @ B) - 1) / 2, -1, 1)))
+
+
+def bench_surfels(lsr, n, n_kf, steps, cpu_sample):
+    """Dense surface correction (Sec. VI, eq. 7) on a synthetic surfel map:
+    surfels/s over `steps` calls, the update kernel's HBM roofline from HIP
+    events, and the oracle on a bounded sample."""
+    import numpy as np
+    import torch
+
+    from synth.surfels import make_surfel_map
+    m = make_surfel_map(n, n_kf)
+    S, t0, tu = (torch.from_numpy(a).cuda() for a in (m.S, m.t0, m.tu))
+    for _ in range(2):
+        lsr.surfel_correct(S, t0, tu, m.T_old, m.T_new, m.t_kf, m.camera, sync=False)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
+        r = lsr.surfel_correct(S, t0, tu, m.T_old, m.T_new, m.t_kf, m.camera, sync=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    kept = int(r[3].cpu()[0])
+    lsr.set_timing(True)
+    lsr.get_timing()
+    lsr.surfel_correct(S, t0, tu, m.T_old, m.T_new, m.t_kf, m.camera, sync=False)
+    st = dict(lsr.get_timing())
+    lsr.set_timing(False)
+    upd = st.get("surfel_update", float("nan"))
+    bytes_upd = n * (6 * 4 + 2 * 4 + 6 * 4 + 4 + 4)   # surfel + window in; update, keep flag, |F| out
+    gbs = bytes_upd / (upd * 1e-3) / 1e9
+    out = {"workload": f"surfel map {n} surfels, {n_kf} keyframes (room recipe, 640x480 pinhole)",
+           "surfels_per_s": round(n * steps / (tb - ta), 1), "ms_per_call": round((tb - ta) * 1e3 / steps, 4),
+           "kept": kept, "stages_ms": {k: round(v, 4) for k, v in st.items()},
+           "roofline": {"bound": "hbm", "kernel": "k_surfel_update", "achieved": round(gbs, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                        "bytes_per_surfel": bytes_upd // n, "traffic": None}}
+    if cpu_sample > 0:
+        import oracle
+        k = min(cpu_sample, n)
+        tc = time.perf_counter()
+        oracle.surfel_correct(m.S[:, :k], m.t0[:k], m.tu[:k], m.T_old, m.T_new, m.t_kf, m.camera)
+        out["oracle_surfels_per_s"] = round(k / (time.perf_counter() - tc), 1)
+    log(f"surfel correction: {out}")
+    return out
+
+
+def bench_loops(lsr, n_frags, m, n_true, n_false, steps, cpu):
+    """Loop verification (Sec. V) of a fragment chain's loop candidates:
+    candidates/s over `steps` lsr_loop_verify calls (edge information of
+    every odometry edge and candidate, then the pose graph per candidate),
+    stage times from HIP events, and the oracle on the same chain."""
+    import numpy as np
+    import torch
+
+    from synth.chain import make_chain
+    ch = make_chain(n_frags, m, n_true=n_true, n_false=n_false)
+    frags = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in ch.frags]
+    prm = lsr.loop_params()
+    for _ in range(2):
+        lsr.loop_verify(frags, ch.T_init, ch.odo, ch.loops, prm, poses=False, sync=False)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
+        res, _ = lsr.loop_verify(frags, ch.T_init, ch.odo, ch.loops, prm, poses=False, sync=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    res = lsr._lib._parse_loop(res, len(ch.loops))
+    lsr.set_timing(True)
+    lsr.get_timing()
+    lsr.loop_verify(frags, ch.T_init, ch.odo, ch.loops, prm, poses=False, sync=False)
+    st = dict(lsr.get_timing())
+    lsr.set_timing(False)
+    dec = [r["status"] == lsr.ACCEPTED for r in res]
+    n_edges = n_frags - 1 + len(ch.loops)
+    pts = sum(f.shape[1] for f in ch.frags[:-1]) + sum(ch.frags[i].shape[1] for i, _, _ in ch.loops)
+    out = {"workload": f"fragment chain {n_frags} x {m} points, {len(ch.loops)} loop candidates "
+                       f"({int(ch.loop_true.sum())} true), {n_edges} edges",
+           "candidates_per_s": round(len(ch.loops) * steps / (tb - ta), 2),
+           "ms_per_call": round((tb - ta) * 1e3 / steps, 4),
+           "stages_ms": {k: round(v, 4) for k, v in st.items()},
+           "edge_points_per_s": round(pts / (st.get("edge_info", float("nan")) * 1e-3), 1),
+           "decisions_correct": int(sum(d == t for d, t in zip(dec, ch.loop_true))),
+           "iters": [r["iters"] for r in res]}
+    if cpu:
+        import oracle
+        tc = time.perf_counter()
+        info = [oracle.edge_info(ch.frags[i], ch.frags[j], A) for (i, j, A) in list(ch.odo) + list(ch.loops)]
+        Lo = np.array([x[0] for x in info[: n_frags - 1]])
+        for c, (i, j, A) in enumerate(ch.loops):
+            oracle.loop_solve(ch.T_init, ch.odo, Lo, (i, j, A), info[n_frags - 1 + c][0], info[n_frags - 1 + c][1])
+        out["oracle_candidates_per_s"] = round(len(ch.loops) / (time.perf_counter() - tc), 3)
+    log(f"loop verification: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pairs", type=int, default=256)
-    ap.add_argument("--distinct", type=int, default=64, help="distinct generated pairs, tiled to --pairs")
+    ap.add_argument("--distinct", type=int, default=0,
+                    help="distinct generated pairs, tiled to --pairs (default: every pair distinct)")
     ap.add_argument("--points", type=int, default=50000)
     ap.add_argument("--recipe", type=int, default=1,
                     help="scene recipe: 1 = indoor rooms at --points per fragment (the headline workload), "
                          "2 = ragged loop-closure pairs (5k-80k points, 20%% negatives)")
     ap.add_argument("--baseline-pairs", type=int, default=16)
-    ap.add_argument("--cpu-pairs", type=int, default=1)
+    ap.add_argument("--cpu-pairs", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shapes", default=None, help="force launch shapes 'screen,consistency' instead of autotuning")
+    ap.add_argument("--surfels", type=int, default=8_000_000, help="surfel-correction map size (0: skip)")
+    ap.add_argument("--keyframes", type=int, default=512)
+    ap.add_argument("--chain", type=int, default=64, help="loop-verification chain length (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -65,7 +166,7 @@ def main():
 
     lsr.lib()
     t0 = time.time()
-    distinct = max(1, min(args.distinct, args.pairs))
+    distinct = max(1, min(args.distinct or args.pairs, args.pairs))
     prs = synth.make_batch(args.recipe, distinct, n_points=args.points if args.recipe == 1 else None)
     log(f"generated {distinct} distinct pairs in {time.time() - t0:.1f}s")
     order = [k % distinct for k in range(args.pairs)]
@@ -122,12 +223,14 @@ def main():
     nPs = np.diff(offP).astype(np.float64)
     nQs = np.diff(offQ).astype(np.float64)
     screen_kernel = "k_screen_pr" if lsr.get_tune()["screen_shape"] == lsr._lib.PRUNED_SCREEN else "k_screen"
-    flops_full = float(np.sum(2.0 * 2 * 33 * nPs * nQs))   # both directions: every point vs the other fragment
-    # the pruned screen skips chunks: count the chunk visits it made (centroid passes included)
+    # algorithmic work: one 33-term distance contraction per (i, j), 2 flops a term; it serves both directions
+    flops_alg = float(np.sum(2.0 * 33 * nPs * nQs))
+    # issued matrix-core work: per direction and (query, row), two chained K=32 MFMAs (hi and lo candidate
+    # halves), over the chunk visits the pruned screen made (centroid passes included)
     nch_all = sum(r["n_screen_chunks"] for r in res)
     work = sum(r["n_screen_chunks_swept"] for r in res) / nch_all if nch_all else 1.0
-    flops = flops_full * work
-    achieved = flops / (scr * 1e-3) / 1e12
+    flops_issued = float(np.sum(2 * 2 * 2.0 * 32 * nPs * nQs)) * work
+    achieved = flops_alg / (scr * 1e-3) / 1e12
     traffic = None
     tr_path = os.path.join(ROOT, "profiles", "screen_traffic.json")
     src = open(os.path.join(ROOT, "paper_1801_01572_amd", "csrc", "match_bf16.hip"), "rb").read()
@@ -136,8 +239,8 @@ def main():
         if tr.get("source_sha1") == hashlib.sha1(src).hexdigest() and tr.get("pairs") == npairs \
                 and tr.get("points") == args.points and tr.get("recipe", 1) == args.recipe:
             traffic = tr.get("bytes_per_launch")
-    log(f"screen kernel {scr:.3f} ms/launch, {work:.3f} of the chunks swept -> {achieved:.1f} TFLOP/s executed, "
-        f"{flops_full / (scr * 1e-3) / 1e12:.1f} TFLOP/s exhaustive-equivalent")
+    log(f"screen kernel {scr:.3f} ms/launch: {achieved:.1f} TFLOP/s algorithmic (2*33*N_P*N_Q per pair), "
+        f"{flops_issued / (scr * 1e-3) / 1e12:.1f} TFLOP/s issued ({work:.3f} of the chunks swept)")
     log("stages (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in stage_ms.items()))
 
     if args.calib_copy_mib > 0:
@@ -171,24 +274,63 @@ def main():
 
     cpu = None
     pose_vs_oracle = None
+    tie_exempt = None
     if not args.no_cpu and args.cpu_pairs > 0:
         import oracle
         k = min(args.cpu_pairs, distinct)
         t5 = time.perf_counter()
         outs = [oracle.register_pair(prs[j].P, prs[j].Q) for j in range(k)]
         t6 = time.perf_counter()
-        d = oracle.result_dict(outs[0][0])
-        Rg, Ro = np.asarray(res[0]["T"])[:3, :3], d["T"][:3, :3]
-        ang = float(np.arccos(np.clip((np.trace(Rg.T @ Ro) - 1) / 2, -1, 1)))
-        pose_vs_oracle = {"pair": 0, "rot_err_rad": ang,
-                          "trans_err_m": float(np.linalg.norm(np.asarray(res[0]["T"])[:3, 3] - d["T"][:3, 3])),
-                          "same_status": res[0]["status"] == d["status"],
-                          "same_counts": (res[0]["n_recip"], res[0]["n_consistent"]) == (d["n_recip"],
-                                                                                           d["n_consistent"])}
+        pose_vs_oracle = []
+        for j in range(k):
+            d = oracle.result_dict(outs[j][0])
+            Tg, To = np.asarray(res[j]["T"]), d["T"]
+            pose_vs_oracle.append({
+                "pair": j, "rot_err_rad": _rot_angle(Tg[:3, :3], To[:3, :3]),
+                "trans_err_m": float(np.linalg.norm(Tg[:3, 3] - To[:3, 3])),
+                "same_status": res[j]["status"] == d["status"],
+                "recip": [res[j]["n_recip"], d["n_recip"]], "consistent": [res[j]["n_consistent"],
+                                                                           d["n_consistent"]]})
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
         cpu = {"value": k / (t6 - t5), "unit": "fragment pairs/s", "cores": threads, "kind": "oracle",
-               "sample": f"{k} of the benchmark's 50k/50k pairs, full pipeline, FP64, {threads} OpenMP threads"}
+               "sample": f"{k} of the benchmark's pairs, full pipeline, FP64, {threads} OpenMP threads"}
         log(f"cpu oracle: {cpu['value']:.4f} pairs/s")
+        for e in pose_vs_oracle:
+            log(f"  pair {e['pair']}: pose vs oracle {e['rot_err_rad']:.2e} rad {e['trans_err_m']:.2e} m, "
+                f"recip {e['recip']}, K {e['consistent']}, same status {e['same_status']}")
+        # share of P rows whose descriptor neighbour lies within the near-tie margin (pair 0, oracle's own)
+        pr0 = prs[0]
+        nP0, _, _ = oracle.normals(pr0.P, prm.r_normal)[:3]
+        nQ0, _, _ = oracle.normals(pr0.Q, prm.r_normal)[:3]
+        F0, v0 = oracle.fpfh(pr0.P[:3], nP0, prm.r_feature)[:2]
+        G0, w0 = oracle.fpfh(pr0.Q[:3], nQ0, prm.r_feature)[:2]
+        m0 = oracle.match(F0, v0, G0, w0)
+        tP, tQ = oracle.tie_flags(F0, G0, m0)
+        tie_exempt = {"pair": 0, "rows_P": round(float(tP[v0 == 1].mean()), 4),
+                      "rows_Q": round(float(tQ[w0 == 1].mean()), 4)}
+        log(f"tie-exempt share (pair 0): {tie_exempt}")
+
+    # recovery of the generating transform (rotation <= 0.5 deg and translation <= 1 cm)
+    errs = [(_rot_angle(np.asarray(r["T"])[:3, :3], prs[k].T_gt[:3, :3]),
+             float(np.linalg.norm(np.asarray(r["T"])[:3, 3] - prs[k].T_gt[:3, 3]))) for r, k in zip(res, order)]
+    rec = np.array([a <= np.deg2rad(0.5) and t <= 0.01 for a, t in errs])
+    accd = np.array([r["status"] == lsr.ACCEPTED for r in res])
+    neg = np.array([bool(prs[k].meta.get("negative", False)) for k in order])
+    recovery = {"recovered": round(float(rec[~neg].mean()) if (~neg).any() else 0.0, 4),
+                "accepted_and_recovered": round(float((rec & accd)[~neg].mean()) if (~neg).any() else 0.0, 4),
+                "false_accepts": round(float((accd & ~rec).mean()), 4),
+                "negatives_accepted": round(float(accd[neg].mean()), 4) if neg.any() else None,
+                "median_rot_err_deg": round(float(np.rad2deg(np.median([a for a, _ in errs]))), 3),
+                "rule": "rotation <= 0.5 deg and translation <= 1 cm from the generating transform"}
+    log(f"recovery: {recovery}")
+
+    surf = None
+    if args.surfels > 0:
+        surf = bench_surfels(lsr, args.surfels, args.keyframes, 10, 0 if args.no_cpu else 1_000_000)
+
+    loops = None
+    if args.chain > 0:
+        loops = bench_loops(lsr, args.chain, 20000, 8, 8, 10, not args.no_cpu)
 
     acc = float(np.mean([r["status"] == lsr.ACCEPTED for r in res]))
     fb = int(sum(r["n_fallback_rows"] for r in res))
@@ -208,25 +350,34 @@ def main():
         "config": {"workload": (f"indoor-room pairs, {args.points}/{args.points} pts per fragment, "
                                 if args.recipe == 1 else "ragged loop-closure pairs, 5k-80k pts per fragment, "
                                                          "20% negatives, ")
-                               + f"batch of {npairs} ({distinct} distinct, tiled), one graph replay per step",
+                               + f"batch of {npairs} ({distinct} distinct"
+                               + (", tiled" if distinct < npairs else "") + "), one graph replay per step",
                    "pairs": npairs, "points_per_fragment": args.points if args.recipe == 1 else "5k-80k",
                    "precision": "bf16 screen + fp32 re-rank", "parallelism": "single GPU"},
         "plain_fp32_pairs_per_s": None if base is None else round(base, 3),
         "speedup_vs_plain_fp32": None if base is None else round(value / base, 3),
         "roofline": {"bound": "mfma", "kernel": screen_kernel, "achieved": round(achieved, 2),
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-                     "traffic": traffic, "ms_per_launch": round(scr, 4), "flops_per_launch": flops,
-                     "chunks_swept_fraction": round(work, 4), "flops_exhaustive": flops_full,
-                     "exhaustive_equivalent_tflops": round(flops_full / (scr * 1e-3) / 1e12, 2)},
+                     "traffic": traffic, "ms_per_launch": round(scr, 4), "flops_per_launch": flops_alg,
+                     "flops_note": "algorithmic: sum over pairs of 2*33*N_P*N_Q (one contraction serves both "
+                                   "directions)",
+                     "issued_flops_per_launch": flops_issued,
+                     "issued_tflops": round(flops_issued / (scr * 1e-3) / 1e12, 2),
+                     "issued_frac": round(flops_issued / (scr * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+                     "chunks_swept_fraction": round(work, 4)},
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "autotune": tune,
         "pose_vs_oracle": pose_vs_oracle,
+        "tie_exempt": tie_exempt,
+        "recovery_vs_T_gt": recovery,
         "paper_context": {"ms_per_pair": 20.50, "hardware": "Intel i7-6850K + NVIDIA Titan X Pascal",
                           "workload": "augmented ICL-NUIM fragment pairs, 5 cm voxels, point count not stated; "
                                       "GPU RANSAC (Table 1 average)",
                           "ms_per_pair_here": round(1e3 / value, 4)},
         "accepted_fraction": round(acc, 4),
+        "surfel_correction": surf,
+        "loop_verification": loops,
         "bf16_fallback_rows": fb,
     }
     print(json.dumps(line), flush=True)
