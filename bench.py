@@ -62,12 +62,20 @@ def bench_surfels(lsr, n, n_kf, steps, cpu_sample):
     upd = st.get("surfel_update", float("nan"))
     bytes_upd = n * (6 * 4 + 2 * 4 + 6 * 4 + 4 + 4)   # surfel + window in; update, keep flag, |F| out
     gbs = bytes_upd / (upd * 1e-3) / 1e9
+    traffic = None
+    tp = os.path.join(ROOT, "profiles", "surfel_traffic.json")
+    if os.path.exists(tp):
+        tr = json.load(open(tp))
+        src = open(os.path.join(ROOT, "paper_1801_01572_amd", "csrc", "surfel.hip"), "rb").read()
+        if tr.get("source_sha1") == hashlib.sha1(src).hexdigest() and tr.get("surfels") == n \
+                and tr.get("keyframes") == n_kf:
+            traffic = tr.get("bytes_per_launch")
     out = {"workload": f"surfel map {n} surfels, {n_kf} keyframes (room recipe, 640x480 pinhole)",
            "surfels_per_s": round(n * steps / (tb - ta), 1), "ms_per_call": round((tb - ta) * 1e3 / steps, 4),
            "kept": kept, "stages_ms": {k: round(v, 4) for k, v in st.items()},
            "roofline": {"bound": "hbm", "kernel": "k_surfel_update", "achieved": round(gbs, 1),
                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                        "bytes_per_surfel": bytes_upd // n, "traffic": None}}
+                        "bytes_per_surfel": bytes_upd // n, "traffic": traffic}}
     if cpu_sample > 0:
         import oracle
         k = min(cpu_sample, n)
@@ -127,6 +135,110 @@ def bench_loops(lsr, n_frags, m, n_true, n_false, steps, cpu):
     return out
 
 
+def bench_roc(lsr, n_pairs, first_pair):
+    """Accept/reject on held-out loop-closure pairs (the ragged recipe, 20%
+    negatives, pairs first_pair .. first_pair + n_pairs - 1, disjoint from
+    the test batch): the inlier ratio and consistent count of every pair, and
+    the ROC of the inlier-ratio threshold at the default minimum count.  A
+    registration is good when the pair overlaps and the returned pose moves
+    P's points by at most 0.2 m RMS from where the generating transform puts
+    them (and, stricter, within 2 deg and 5 cm)."""
+    import numpy as np
+    import torch
+
+    import synth
+    prs = synth.make_batch(2, n_pairs, first_pair=first_pair)
+    P = np.concatenate([p.P for p in prs], 1)
+    Q = np.concatenate([p.Q for p in prs], 1)
+    offP = np.concatenate([[0], np.cumsum([p.P.shape[1] for p in prs])]).astype(np.int64)
+    offQ = np.concatenate([[0], np.cumsum([p.Q.shape[1] for p in prs])]).astype(np.int64)
+    prm = lsr.default_params(precision=lsr.BF16_SCREEN)
+    res = lsr.register_batch(torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda(), offP, offQ, prm)
+    ratio = np.array([r["inlier_ratio"] for r in res])
+    K = np.array([r["n_consistent"] for r in res])
+    deg = np.array([r["status"] == lsr.DEGENERATE for r in res])
+    neg = np.array([bool(p.meta.get("negative", False)) for p in prs])
+    rms = np.zeros(n_pairs)
+    strict = np.zeros(n_pairs, bool)
+    for k, (r, p) in enumerate(zip(res, prs)):
+        T, G = np.asarray(r["T"]), p.T_gt
+        x = p.P[:3].astype(np.float64)
+        rms[k] = np.sqrt(np.mean(np.sum(((T[:3, :3] - G[:3, :3]) @ x + (T[:3, 3] - G[:3, 3])[:, None]) ** 2, 0)))
+        ang = np.arccos(np.clip((np.trace(T[:3, :3].T @ G[:3, :3]) - 1) / 2, -1, 1))
+        strict[k] = ang <= np.deg2rad(2.0) and np.linalg.norm(T[:3, 3] - G[:3, 3]) <= 0.05
+    good = ~neg & (rms <= 0.2)
+    base = (K >= prm.min_consistent) & ~deg
+    grid = np.round(np.arange(0.0, 1.0001, 0.01), 2)
+    tpr = [float(((base & (ratio >= g)) & good).sum() / max(good.sum(), 1)) for g in grid]
+    fpr = [float(((base & (ratio >= g)) & ~good).sum() / max((~good).sum(), 1)) for g in grid]
+    auc = float(-np.trapezoid(tpr, fpr)) if hasattr(np, "trapezoid") else float(-np.trapz(tpr, fpr))
+    ok = [g for g, f in zip(grid, fpr) if f <= 0.05]
+    rho5 = float(ok[0]) if ok else None
+    out = {"workload": f"{n_pairs} held-out loop-closure pairs (ragged 5k-80k, 20% negatives), pairs "
+                       f"{first_pair}..{first_pair + n_pairs - 1}",
+           "good_rule": "overlapping pair, pose within 0.2 m RMS of the generating transform over P's points",
+           "pairs_good": int(good.sum()), "pairs_strict_2deg_5cm": int((strict & ~neg).sum()),
+           "negatives": int(neg.sum()), "auc": round(auc, 4),
+           "at_default": {"rho_min": float(prm.min_inlier_ratio),
+                          "tpr": round(tpr[int(round(prm.min_inlier_ratio * 100))], 4),
+                          "fpr": round(fpr[int(round(prm.min_inlier_ratio * 100))], 4)},
+           "rho_for_fpr_5pct": rho5,
+           "tpr_at_that": None if rho5 is None else round(tpr[int(round(rho5 * 100))], 4),
+           "roc": {"rho": [float(g) for g in grid[::5]], "tpr": [round(t, 4) for t in tpr[::5]],
+                   "fpr": [round(f, 4) for f in fpr[::5]]},
+           "ratio_good_median": float(np.median(ratio[good])) if good.any() else None,
+           "ratio_bad_median": float(np.median(ratio[~good])) if (~good).any() else None}
+    log(f"accept/reject ROC: {out}")
+    return out
+
+
+def bench_building(lsr):
+    """The building-scale pair (3 x 3 rooms, 500k/500k points, 40% overlap):
+    one register_pair with the bf16 screen, its stage times, the screen's
+    algorithmic rate, and the pose against the oracle's run cached in
+    tests/golden/c3_building_500k.json (written once by
+    tests/golden/make_c3_reference.py; the oracle's quadratic matching takes
+    tens of minutes on a host)."""
+    import numpy as np
+    import torch
+
+    import synth
+    path = os.path.join(ROOT, "tests", "golden", "c3_building_500k.json")
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    pr = synth.make_pair(3, 0)
+    P, Q = torch.from_numpy(pr.P).cuda(), torch.from_numpy(pr.Q).cuda()
+    prm = lsr.default_params(precision=lsr.BF16_SCREEN)
+    lsr.register_pair(P, Q, prm)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = lsr.register_pair(P, Q, prm)
+    tb = time.perf_counter()
+    lsr.set_timing(True)
+    lsr.get_timing()
+    lsr.register_pair(P, Q, prm)
+    st = {}
+    for name, ms in lsr.get_timing():
+        st[name] = st.get(name, 0.0) + ms
+    lsr.set_timing(False)
+    To = np.array(ref["T"]).reshape(4, 4)
+    T = np.asarray(r["T"])
+    flops = 2.0 * 33 * pr.P.shape[1] * pr.Q.shape[1]
+    out = {"workload": "building 3 x 3 rooms, 500000/500000 pts, 40% overlap, one register_pair (bf16 screen)",
+           "ms": round((tb - ta) * 1e3, 2), "stages_ms": {k: round(v, 3) for k, v in st.items()},
+           "screen_tflops_algorithmic": round(flops / (st.get("screen", float("nan")) * 1e-3) / 1e12, 1),
+           "screen_frac": round(flops / (st.get("screen", float("nan")) * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+           "pose_vs_oracle": {"rot_err_rad": _rot_angle(T[:3, :3], To[:3, :3]),
+                              "trans_err_m": float(np.linalg.norm(T[:3, 3] - To[:3, 3]))},
+           "status": [r["status"], ref["status"]], "recip": [r["n_recip"], ref["n_recip"]],
+           "consistent": [r["n_consistent"], ref["n_consistent"]],
+           "tie_exempt_rows": [round(ref["tie_exempt_rows_P"], 4), round(ref["tie_exempt_rows_Q"], 4)],
+           "fallback_rows": r["n_fallback_rows"], "oracle_seconds": ref["oracle_seconds"]}
+    log(f"building pair: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +261,8 @@ def main():
     ap.add_argument("--surfels", type=int, default=8_000_000, help="surfel-correction map size (0: skip)")
     ap.add_argument("--keyframes", type=int, default=512)
     ap.add_argument("--chain", type=int, default=64, help="loop-verification chain length (0: skip)")
+    ap.add_argument("--roc-pairs", type=int, default=256, help="held-out pairs for the accept/reject ROC (0: skip)")
+    ap.add_argument("--no-building", action="store_true", help="skip the 500k/500k building pair")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -237,7 +351,8 @@ def main():
     if os.path.exists(tr_path):
         tr = json.load(open(tr_path))
         if tr.get("source_sha1") == hashlib.sha1(src).hexdigest() and tr.get("pairs") == npairs \
-                and tr.get("points") == args.points and tr.get("recipe", 1) == args.recipe:
+                and tr.get("points") == args.points and tr.get("recipe", 1) == args.recipe \
+                and tr.get("distinct", npairs) == distinct:
             traffic = tr.get("bytes_per_launch")
     log(f"screen kernel {scr:.3f} ms/launch: {achieved:.1f} TFLOP/s algorithmic (2*33*N_P*N_Q per pair), "
         f"{flops_issued / (scr * 1e-3) / 1e12:.1f} TFLOP/s issued ({work:.3f} of the chunks swept)")
@@ -332,6 +447,12 @@ def main():
     if args.chain > 0:
         loops = bench_loops(lsr, args.chain, 20000, 8, 8, 10, not args.no_cpu)
 
+    building = None if args.no_building else bench_building(lsr)
+
+    roc = None
+    if args.roc_pairs > 0:
+        roc = bench_roc(lsr, args.roc_pairs, 1000)
+
     acc = float(np.mean([r["status"] == lsr.ACCEPTED for r in res]))
     fb = int(sum(r["n_fallback_rows"] for r in res))
     line = {
@@ -378,6 +499,8 @@ def main():
         "accepted_fraction": round(acc, 4),
         "surfel_correction": surf,
         "loop_verification": loops,
+        "accept_reject_roc": roc,
+        "building_500k": building,
         "bf16_fallback_rows": fb,
     }
     print(json.dumps(line), flush=True)

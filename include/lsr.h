@@ -436,6 +436,8 @@ typedef struct {
     int32_t n_screen_shapes, n_consistency_shapes;
     float screen_ms[LSR_MAX_VARIANTS];
     float consistency_ms[LSR_MAX_VARIANTS];
+    int32_t from_cache;      /* lsr_autotune: 1 when the choice came from the tune cache (timings zero) */
+    int32_t pad;
 } lsr_tune;
 
 /*
@@ -450,6 +452,15 @@ typedef struct {
 int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
                  const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, int32_t reps,
                  lsr_tune *out, void *stream);
+/* Tune cache: a JSON file of choices keyed by the device architecture and a
+ * size bucket of the batch (pairs, mean and largest fragment, each rounded
+ * up to a power of two).  With a cache set, lsr_autotune first looks the
+ * batch's key up and, when it is there, takes that choice without timing;
+ * otherwise it times the variants and records the choice in the file
+ * (rewritten whole, through a temporary file and a rename).  path NULL or
+ * empty: no cache (the default).  The path is copied. */
+int lsr_set_tune_cache(lsr_ctx *ctx, const char *path);
+
 /* Current choice (timings zero); set a saved choice (LSR_EINVAL if a
  * variant index is out of range; drops cached plans when it changes). */
 int lsr_get_tune(lsr_ctx *ctx, lsr_tune *out);

@@ -49,7 +49,8 @@ PRUNED_SCREEN = 5          # screen variant that skips the partner's chunks by t
 class Tune(C.Structure):
     _fields_ = [("screen_shape", C.c_int32), ("consistency_shape", C.c_int32),
                 ("n_screen_shapes", C.c_int32), ("n_consistency_shapes", C.c_int32),
-                ("screen_ms", C.c_float * MAX_VARIANTS), ("consistency_ms", C.c_float * MAX_VARIANTS)]
+                ("screen_ms", C.c_float * MAX_VARIANTS), ("consistency_ms", C.c_float * MAX_VARIANTS),
+                ("from_cache", C.c_int32), ("pad", C.c_int32)]
 
 
 class Trace(C.Structure):
@@ -138,6 +139,7 @@ def lib():
         L.lsr_autotune.argtypes = [vp, C.POINTER(Cloud), C.POINTER(Cloud), vp, vp, i32, C.POINTER(Params), i32,
                                    C.POINTER(Tune), vp]
         L.lsr_get_tune.argtypes = [vp, C.POINTER(Tune)]
+        L.lsr_set_tune_cache.argtypes = [vp, C.c_char_p]
         L.lsr_set_tune.argtypes = [vp, C.POINTER(Tune)]
         L.lsr_get_timing.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
         for f in ("lsr_set_timing", "lsr_get_timing", "lsr_create", "lsr_register_pair", "lsr_register_batch",
@@ -146,7 +148,7 @@ def lib():
                   "lsr_stage_consistency", "lsr_stage_gnc", "lsr_stage_verify", "lsr_autotune", "lsr_get_tune",
                   "lsr_set_tune", "lsr_ransac_pair", "lsr_stage_ransac", "lsr_stage_gnc_noalloc",
                   "lsr_surfel_correct", "lsr_edge_info", "lsr_loop_solve", "lsr_loop_verify", "lsr_se3_retract",
-                  "lsr_se3_retract_grad"):
+                  "lsr_se3_retract_grad", "lsr_set_tune_cache"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -283,13 +285,16 @@ def register_batch(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params:
 def _tune_dict(t: Tune) -> dict:
     return {"screen_shape": t.screen_shape, "consistency_shape": t.consistency_shape,
             "screen_ms": list(t.screen_ms[:t.n_screen_shapes]),
-            "consistency_ms": list(t.consistency_ms[:t.n_consistency_shapes])}
+            "consistency_ms": list(t.consistency_ms[:t.n_consistency_shapes]), "from_cache": bool(t.from_cache)}
 
 
 def autotune(P_all: torch.Tensor, Q_all: torch.Tensor, offP, offQ, params: Params | None = None, reps: int = 2,
-             ctx: Context | None = None) -> dict:
-    """Time every launch-shape variant on this batch and keep the fastest (lsr_autotune)."""
+             ctx: Context | None = None, cache: str | None = None) -> dict:
+    """Time every launch-shape variant on this batch and keep the fastest (lsr_autotune).
+    cache: a JSON tune-cache file (lsr_set_tune_cache) consulted and updated."""
     ctx = ctx or get_context(P_all.device.index)
+    if cache is not None:
+        ctx.check(lib().lsr_set_tune_cache(ctx.h, cache.encode() if cache else None))
     prm = params or default_params()
     offP = np.ascontiguousarray(offP, np.int64)
     offQ = np.ascontiguousarray(offQ, np.int64)

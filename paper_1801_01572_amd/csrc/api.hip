@@ -135,6 +135,7 @@ struct lsr_ctx {
     int tune_screen = 0;           // screen shape variant (autotuned)
     int tune_cons = 0;             // consistency block-width variant (autotuned)
     std::string err = "no error";
+    std::string tune_cache;        // JSON file of autotune choices, or empty
     std::vector<std::unique_ptr<Plan>> plans;   // most recently used last
 };
 
@@ -302,6 +303,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     size_t o_spfh = D.add(16 * SPR * n1), o_knb = D.add(4 * n1), o_F = D.add(4 * FD * n1), o_valid = D.add(4 * n1);
     size_t o_pk = D.add(2 * PK * (size_t)std::max<int64_t>(pk_rows, 1));
     size_t o_cpack = D.add(32 * n1), o_cwords = D.add(sizeof(uint2) * corr_words(ntot, nf));
+    size_t o_nnkey = D.add(8 * n1);
     size_t o_nn = D.add(4 * n1), o_dist = D.add(4 * n1), o_mut = D.add(n1), o_flag = D.add(4 * n1),
            o_kpos = D.add(4 * n1), o_kp = D.add(12 * n1), o_kq = D.add(12 * n1), o_ki = D.add(4 * n1);
     size_t o_ps = D.add(sizeof(PairState) * (size_t)std::max(npairs, 1));
@@ -344,6 +346,7 @@ int make_batch_plan(lsr_ctx *c, const std::vector<FragIn> &frags, bool paired, c
     P->d.valid = (int32_t *)(db + o_valid);
     P->d.pk = (uint16_t *)(db + o_pk);
     P->m.nn = (int32_t *)(db + o_nn);
+    P->m.nnkey = (unsigned long long *)(db + o_nnkey);
     P->m.dist = (float *)(db + o_dist);
     P->m.mutual = (uint8_t *)(db + o_mut);
     P->m.cpack = (float4 *)(db + o_cpack);
@@ -757,6 +760,75 @@ int lsr_set_tune(lsr_ctx *ctx, const lsr_tune *t) {
     return LSR_OK;
 }
 
+// ---- the tune cache: one JSON object per line inside an "entries" array
+namespace {
+
+std::string tune_key(lsr_ctx *ctx, const std::vector<FragIn> &fr, int32_t n_pairs) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+    }
+    auto p2 = [](int64_t v) { int64_t b = 1; while (b < v) b <<= 1; return b; };
+    int64_t tot = 0, mx = 0;
+    for (auto &f : fr) { tot += f.n; mx = std::max(mx, f.n); }
+    const int64_t mean = fr.empty() ? 0 : (tot + (int64_t)fr.size() - 1) / (int64_t)fr.size();
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|pairs=%lld|mean=%lld|max=%lld", arch.c_str(), (long long)p2(n_pairs),
+             (long long)p2(mean), (long long)p2(mx));
+    return buf;
+}
+
+struct TuneEntry {
+    std::string key;
+    int screen = -1, cons = -1;
+    std::string line;
+};
+
+std::vector<TuneEntry> read_tune_cache(const std::string &path) {
+    std::vector<TuneEntry> out;
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return out;
+    char buf[4096];
+    while (fgets(buf, sizeof buf, f)) {
+        std::string l(buf);
+        const size_t k = l.find("\"key\": \""), a = l.find("\"screen_shape\": "), b = l.find("\"consistency_shape\": ");
+        if (k == std::string::npos || a == std::string::npos || b == std::string::npos) continue;
+        const size_t ke = l.find('"', k + 8);
+        if (ke == std::string::npos) continue;
+        TuneEntry e;
+        e.key = l.substr(k + 8, ke - (k + 8));
+        e.screen = atoi(l.c_str() + a + 16);
+        e.cons = atoi(l.c_str() + b + 21);
+        while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == '\r')) l.pop_back();
+        e.line = l;
+        out.push_back(e);
+    }
+    fclose(f);
+    return out;
+}
+
+bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es) {
+    const std::string tmp = path + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fprintf(f, "{\"lsr_tune_cache\": 1, \"entries\": [\n");
+    for (size_t k = 0; k < es.size(); ++k) fprintf(f, "%s%s\n", es[k].line.c_str(), k + 1 < es.size() ? "," : "");
+    fprintf(f, "]}\n");
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+}  // namespace
+
+int lsr_set_tune_cache(lsr_ctx *ctx, const char *path) {
+    if (!ctx) return LSR_EINVAL;
+    ctx->tune_cache = path ? path : "";
+    return LSR_OK;
+}
+
 int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, const int64_t *offP,
                  const int64_t *offQ, int32_t n_pairs, const lsr_params *prm, int32_t reps, lsr_tune *out,
                  void *stream) {
@@ -771,14 +843,30 @@ int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, c
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     if (capturing(s)) return fail(ctx, LSR_EINVAL, "autotuning cannot run under stream capture");
-    lsr_params tp = *prm;
-    tp.precision = LSR_BF16_SCREEN;                 // the screen is one of the tuned kernels
-    const bool timing = g_timing.on;
-    g_timing.on = false;
     lsr_tune res;
     std::memset(&res, 0, sizeof res);
     res.n_screen_shapes = screen_shapes();
     res.n_consistency_shapes = consistency_shapes();
+    std::string tkey;
+    std::vector<TuneEntry> cache;
+    if (!ctx->tune_cache.empty()) {
+        tkey = tune_key(ctx, fr, n_pairs);
+        cache = read_tune_cache(ctx->tune_cache);
+        for (auto &e : cache)
+            if (e.key == tkey && e.screen >= 0 && e.screen < res.n_screen_shapes && e.cons >= 0 &&
+                e.cons < res.n_consistency_shapes) {
+                res.screen_shape = e.screen;
+                res.consistency_shape = e.cons;
+                res.from_cache = 1;
+                if ((rc = lsr_set_tune(ctx, &res))) return rc;
+                if (out) *out = res;
+                return LSR_OK;
+            }
+    }
+    lsr_params tp = *prm;
+    tp.precision = LSR_BF16_SCREEN;                 // the screen is one of the tuned kernels
+    const bool timing = g_timing.on;
+    g_timing.on = false;
     lsr_result *d_out = nullptr;
     Plan *pl = nullptr;
     std::vector<char> key;
@@ -808,6 +896,24 @@ int lsr_autotune(lsr_ctx *ctx, const lsr_cloud *P_all, const lsr_cloud *Q_all, c
     for (int v = 1; v < res.n_consistency_shapes; ++v)
         if (res.consistency_ms[v] < res.consistency_ms[res.consistency_shape]) res.consistency_shape = v;
     if ((rc = lsr_set_tune(ctx, &res))) return rc;
+    if (!tkey.empty()) {
+        TuneEntry e;
+        e.key = tkey;
+        std::string ms;
+        char buf[64];
+        for (int v = 0; v < res.n_screen_shapes; ++v) { snprintf(buf, sizeof buf, "%s%.3f", v ? ", " : "", res.screen_ms[v]); ms += buf; }
+        std::string mc;
+        for (int v = 0; v < res.n_consistency_shapes; ++v) { snprintf(buf, sizeof buf, "%s%.3f", v ? ", " : "", res.consistency_ms[v]); mc += buf; }
+        e.line = "{\"key\": \"" + tkey + "\", \"screen_shape\": " + std::to_string(res.screen_shape) +
+                 ", \"consistency_shape\": " + std::to_string(res.consistency_shape) + ", \"screen_ms\": [" + ms +
+                 "], \"consistency_ms\": [" + mc + "]}";
+        std::vector<TuneEntry> keep;
+        for (auto &c : cache)
+            if (c.key != tkey) keep.push_back(c);
+        keep.push_back(e);
+        if (!write_tune_cache(ctx->tune_cache, keep))
+            return fail(ctx, LSR_EINVAL, "cannot write the tune cache %s", ctx->tune_cache.c_str());
+    }
     if (out) *out = res;
     return LSR_OK;
 }

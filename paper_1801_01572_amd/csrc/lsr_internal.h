@@ -164,6 +164,7 @@ struct DescBufs {
 
 struct MatchBufs {
     int32_t *nn;               // original order: nearest neighbour (index in partner fragment)
+    unsigned long long *nnkey; // float32 scan split over candidate ranges: (distance bits, index) minima
     float *dist;
     uint8_t *mutual;           // original order
     float4 *cpack;             // reciprocal correspondences packed per pair: (px, py, pz, qx), (qy, qz, i, 0)

@@ -8,6 +8,8 @@
 // LSR_BF16_SCREEN (match_bf16.hip) screens on the matrix cores, re-ranks the
 // surviving candidates with d2_row and falls back to the scan for rows it
 // cannot certify, so both modes return identical bits.
+#include <algorithm>
+
 #include "match_common.h"
 
 namespace lsr {
@@ -17,14 +19,25 @@ constexpr int MR = 2;           // query rows per thread
 constexpr int MC = 64;          // candidates staged per LDS round
 constexpr int MS = 36;          // LDS row stride (floats), 33 rounded up for 16-byte reads
 
+// Block (x, y): 512 query rows of one fragment (2 per thread, held in
+// registers) against candidate range y of SPLIT ranges of the partner
+// (candidates staged in LDS 64 at a time, read by every thread at once).
+// A range's best per row is merged into key[row] = min((distance bits << 32)
+// | index) with a 64-bit atomic minimum: distances are non-negative, so the
+// bits order like the values, and equal distances keep the lowest index, as
+// a single scan in index order would.  One split (a batch of many pairs)
+// fills the chip with query blocks alone; a single pair needs several.
 __global__ void __launch_bounds__(MT) k_match_fp32(const Frag *frag, const Blk *blk, const float *F,
-                                                   const int32_t *valid, int32_t *nn, float *dist) {
+                                                   const int32_t *valid, int split, unsigned long long *key) {
     __shared__ __align__(16) float cand[MC * MS];
     __shared__ int32_t cval[MC];
     const Blk b = blk[blockIdx.x];
     const Frag &Fq = frag[b.frag];
     if (Fq.partner < 0) return;
     const Frag &Fc = frag[Fq.partner];
+    const int per = ((Fc.n + split - 1) / split + MC - 1) / MC * MC;
+    const int j_lo = (int)blockIdx.y * per, j_hi = min(Fc.n, j_lo + per);
+    if (j_lo >= j_hi) return;
     float q[MR][MS];
     bool qv[MR];
     float best[MR];
@@ -39,10 +52,10 @@ __global__ void __launch_bounds__(MT) k_match_fp32(const Frag *frag, const Blk *
         best[r] = INFINITY;
         bj[r] = -1;
     }
-    for (int c0 = 0; c0 < Fc.n; c0 += MC) {
+    for (int c0 = j_lo; c0 < j_hi; c0 += MC) {
         __syncthreads();
         const float *base = F + (Fc.off + c0) * FD;
-        int lim = min(MC, Fc.n - c0);
+        int lim = min(MC, j_hi - c0);
         for (int t = threadIdx.x; t < MC * MS; t += MT) {
             int jj = t / MS, c = t - jj * MS;
             cand[t] = (jj < lim && c < FD) ? base[jj * FD + c] : 0.f;
@@ -62,11 +75,22 @@ __global__ void __launch_bounds__(MT) k_match_fp32(const Frag *frag, const Blk *
 #pragma unroll
     for (int r = 0; r < MR; ++r) {
         int i = b.start + threadIdx.x + r * MT;
-        if (i < Fq.n) {
-            nn[Fq.off + i] = qv[r] ? bj[r] : -1;
-            dist[Fq.off + i] = qv[r] ? best[r] : INFINITY;
-        }
+        if (i < Fq.n && qv[r] && bj[r] >= 0)
+            atomicMin(&key[Fq.off + i], ((unsigned long long)__float_as_uint(best[r]) << 32) | (uint32_t)bj[r]);
     }
+}
+
+__global__ void __launch_bounds__(256) k_match_fp32_out(const Frag *frag, const Blk *blk, const int32_t *valid,
+                                                        const unsigned long long *key, int32_t *nn, float *dist) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &Fq = frag[b.frag];
+    const int i = b.start + threadIdx.x;
+    if (i >= Fq.n) return;
+    const int64_t gi = Fq.off + i;
+    const unsigned long long k = key[gi];
+    const bool found = Fq.partner >= 0 && valid[gi] && k != ~0ull;
+    nn[gi] = found ? (int32_t)(uint32_t)k : -1;
+    dist[gi] = found ? __uint_as_float((uint32_t)(k >> 32)) : INFINITY;
 }
 
 // One block per listed row: threads split the candidates, then the block
@@ -119,8 +143,16 @@ __global__ void __launch_bounds__(256) k_match_rows(const Frag *frag, const floa
 
 hipError_t launch_match_fp32(const GridBufs &g, const DescBufs &d, MatchBufs &m, hipStream_t s) {
     if (g.ntot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_match_fp32, dim3(g.nblk512), dim3(MT), 0, s, (const Frag *)g.frag, (const Blk *)g.blk512,
-                       (const float *)d.F, (const int32_t *)d.valid, m.nn, m.dist);
+    hipError_t e = fill<unsigned long long>(m.nnkey, ~0ull, g.ntot, s);
+    if (e != hipSuccess) return e;
+    // candidate ranges per query block: enough blocks for 8 per CU
+    const int split = std::max(1, std::min(64, 2048 / std::max(1, g.nblk512)));
+    if (g.nblk512 > 0)
+        hipLaunchKernelGGL(k_match_fp32, dim3(g.nblk512, split), dim3(MT), 0, s, (const Frag *)g.frag,
+                           (const Blk *)g.blk512, (const float *)d.F, (const int32_t *)d.valid, split, m.nnkey);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_match_fp32_out, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)d.valid, (const unsigned long long *)m.nnkey, m.nn, m.dist);
     return hipGetLastError();
 }
 

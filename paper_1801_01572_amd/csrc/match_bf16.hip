@@ -200,6 +200,8 @@ __global__ void __launch_bounds__(256) k_desc_mean(const Frag *frag, int nfrag, 
         float h[30];
         for (int k = 0; k < 3; ++k) helmert11(m + NB * k, h + 10 * k);
         for (int c = 0; c < 30; ++c) mean_out[32 * b + c] = h[c];
+        mean_out[32 * b + 30] = 0.f;         // largest projection error of the pair's P rows (k_pack)
+        mean_out[32 * b + 31] = 0.f;         // ... and of its Q rows
     }
 }
 
@@ -207,7 +209,7 @@ __global__ void __launch_bounds__(256) k_desc_mean(const Frag *frag, int nfrag, 
 // point t (rows read in order, whole 128-byte rows written), a thread in
 // [n, padded n) writes padding row t.  yq stays indexed by point.
 __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                              const float *mean, const int32_t *rinv, uint16_t *pk, float4 *yq) {
+                                              float *mean, const int32_t *rinv, uint16_t *pk, float4 *yq) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
     const int t = b.start + threadIdx.x;
@@ -217,7 +219,7 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
     const int r = t < Fr.n ? rinv[Fr.off + t] : t;
     int64_t row = Fr.pk_off + r;
     uint16_t hi[32], lo[32];
-    float n2 = 0.f, dd = 0.f;
+    float n2 = 0.f, dd = 0.f, delta = 0.f;
     double dy = 0.0;
     bool v = t < Fr.n && valid[Fr.off + i];
     if (v) {
@@ -242,6 +244,22 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
         float cc = -0.5f * n2;
         hi[30] = f2bf(cc);
         hi[31] = f2bf(cc - bf2f(hi[30]));
+        // projection error: |y - y*| with y* the FP64 Helmert projection of the same float
+        // descriptor minus the same centre (rounded up); the certificate widens by it
+        double e2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double sd = xb[NB * k];
+#pragma unroll
+            for (int q = 1; q < NB; ++q) {
+                const double hd = (sd - (double)q * (double)xb[NB * k + q]) / sqrt((double)(q * (q + 1)));
+                const double ed = (double)h[10 * k + q - 1] - (hd - (double)m[10 * k + q - 1]);
+                e2 += ed * ed;
+                sd += (double)xb[NB * k + q];
+            }
+        }
+        delta = (float)(sqrt(e2) * (1.0 + 1e-6)) + 1e-15f;
+        atomicMax((unsigned int *)(mean + 32 * (b.frag >> 1) + 30 + (b.frag & 1)), __float_as_uint(delta));
     } else {
 #pragma unroll
         for (int c = 0; c < 30; ++c) { hi[c] = 0; lo[c] = 0; }
@@ -261,7 +279,7 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
         w.w = o[6] | ((uint32_t)o[7] << 16);
         dst[q] = w;
     }
-    if (t < Fr.n) yq[Fr.pk_off + i] = make_float4(n2, (float)dy, sqrtf(dd) * 1.0001f, 0.f);
+    if (t < Fr.n) yq[Fr.pk_off + i] = make_float4(n2, (float)dy, sqrtf(dd) * 1.0001f, delta);
 }
 
 // ---------------------------------------------------------------- row order
@@ -1202,19 +1220,28 @@ __device__ __forceinline__ void load_row(const float *F, int64_t r, float *x) {
     for (int c = 0; c < FD; ++c) x[c] = p[c];
 }
 
-// Error bound of the screen for competitors of a row with |y_i|^2 = ny2 and
-// current best D (see the file header).
-__device__ __forceinline__ float slack(float best) { return best * 3e-6f + 1e-7f; }
-__device__ __forceinline__ float screen_err(float4 q, float best) {
+// Error bounds of the certificate (the rounding analysis is in the design
+// notes).  dl = delta_i + delta_max of the partner fragment, the largest
+// distance between a row's float projection y and the exact projection y* of
+// its float descriptor (minus the same centre).  slack(D) bounds
+// |D^ - D^y| for a competitor at distance about D: the float32
+// difference-form distance D^ is within 35 u D of the exact D over the 33
+// bins (u = 2^-24), the projected distance D^y within 2 sqrt(D) dl + dl^2
+// of D (plus block-sum terms below 1e-12).  screen_err bounds
+// |s - t - c_i| for competitors (D^ <= D* implies |y_j - y_i| <= Rp).
+__device__ __forceinline__ float slack(float best, float dl) {
+    return best * 3e-6f + 2.01f * sqrtf(best) * dl + 2.0f * dl * dl + 1e-10f;
+}
+__device__ __forceinline__ float screen_err(float4 q, float best, float dl) {
     const float yi = sqrtf(q.x);
-    const float Rp = sqrtf(best + slack(best)) * 1.0001f + 1e-6f;     // bound on |y_j - y_i| of competitors
-    const float R = yi * 1.0001f + Rp;                                 // bound on |y_j|
-    return q.z * Rp + 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;   // |d_i| Rp + 2^-15 (|y_i| R + R^2 / 2)
+    const float Rp = sqrtf(best + slack(best, dl)) * 1.0001f + dl + 1e-9f;   // bound on |y_j - y_i| of competitors
+    const float R = yi * 1.0001f + Rp;                                       // bound on |y_j|
+    return q.z * Rp + 3.0518e-5f * (yi * R + 0.5f * R * R) + 1e-9f;         // |d_i| Rp + 2^-15 (|y_i| R + R^2 / 2)
 }
 
 template <int T>
 __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
-                                                const float4 *yq, const int32_t *perm, const int32_t *c1,
+                                                const float4 *yq, const float *mean, const int32_t *perm, const int32_t *c1,
                                                 const float *v2, const float *v1, int32_t *nn,
                                                 float *dist, int32_t *fb_row, float *thr, int32_t *fb_cnt,
                                                 int32_t *full_row, int32_t *full_frag, int32_t *full_cnt,
@@ -1239,6 +1266,7 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
             float a2 = -INFINITY;
             const float4 qv = yq[Fq.pk_off + i];
             const float ny2 = qv.x;
+            const float dl = qv.w + mean[32 * (b.frag >> 1) + 30 + (Fq.partner & 1)];
             // T = 16: four lane groups, rows 4 g + e of their best tile;
             // T = 32: two lane halves, rows 8 (e / 4) + 4 g + e % 4
             constexpr int G = T == 16 ? 4 : 2, NE = T == 16 ? 4 : 16;
@@ -1261,7 +1289,7 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                 if (tl < 0) continue;
                 // A tile whose screened maximum t obeys t + c_i + E < (|y_i|^2 - D - slack) / 2
                 // holds only rows with distance above D + slack: it cannot hold the minimum.
-                if (bj >= 0 && gv[g] + qv.y + screen_err(qv, best) < 0.5f * (ny2 - best - slack(best))) continue;
+                if (bj >= 0 && gv[g] + qv.y + screen_err(qv, best, dl) < 0.5f * (ny2 - best - slack(best, dl))) continue;
                 for (int e = 0; e < NE; ++e) {
                     const int32_t r = T == 16 ? tl * 16 + 4 * g + e : tl * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
                     if (r >= Fc.n) continue;
@@ -1273,8 +1301,8 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                     if (d < best || (d == best && j < bj)) { best = d; bj = j; }
                 }
             }
-            float E = screen_err(qv, best);
-            bool cert = a2 == -INFINITY || (bj >= 0 && best + slack(best) < ny2 - 2.0f * (a2 + qv.y + E));
+            float E = screen_err(qv, best, dl);
+            bool cert = a2 == -INFINITY || (bj >= 0 && best + slack(best, dl) < ny2 - 2.0f * (a2 + qv.y + E));
             if (cert) {
                 nn[gi] = bj;
                 dist[gi] = best;
@@ -1282,7 +1310,7 @@ __global__ void __launch_bounds__(256) k_rerank(const Frag *frag, const Blk *blk
                 fb = true;
                 int k = atomicAdd(&fb_cnt[b.frag], 1);
                 fb_row[Fq.off + k] = i;
-                thr[Fq.off + k] = bj >= 0 ? 0.5f * (ny2 - best - slack(best)) - qv.y - E : -INFINITY;
+                thr[Fq.off + k] = bj >= 0 ? 0.5f * (ny2 - best - slack(best, dl)) - qv.y - E : -INFINITY;
                 if (k >= lst_cap(Fq) || bj < 0) {               // no list slot: rescan in float32
                     int r = atomicAdd(full_cnt, 1);
                     full_row[r] = i;
@@ -1464,8 +1492,7 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     hipLaunchKernelGGL(k_rinv, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const int32_t *)S.perm, S.rinv);
     hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const float *)S.mean, (const int32_t *)S.rinv,
-                       d.pk, S.yq);
+                       (const float *)d.F, (const int32_t *)d.valid, S.mean, (const int32_t *)S.rinv, d.pk, S.yq);
     if (SCREEN_SHAPES[shape].prune)
         hipLaunchKernelGGL(k_chunk_stats, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag,
                            (const Blk *)g.blk256, (const uint16_t *)d.pk, S.cpk, S.cst);
@@ -1474,12 +1501,14 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     tmark("screen", s);
     if (SCREEN_SHAPES[shape].t == 16)
         hipLaunchKernelGGL(k_rerank<16>, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.perm, (const int32_t *)S.c1,
+                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const float *)S.mean,
+                           (const int32_t *)S.perm, (const int32_t *)S.c1,
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps, g.nblk256);
     else
         hipLaunchKernelGGL(k_rerank<32>, dim3(xcd_grid(g.nblk256)), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const int32_t *)S.perm, (const int32_t *)S.c1,
+                           (const float *)d.F, (const int32_t *)d.valid, (const float4 *)S.yq, (const float *)S.mean,
+                           (const int32_t *)S.perm, (const int32_t *)S.c1,
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps, g.nblk256);
     tmark("rerank", s);

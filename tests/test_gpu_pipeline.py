@@ -290,6 +290,34 @@ def test_adjoint_deterministic_with_shared_points(L, orc):
     assert np.abs(outs[0][1].T - wq).max() <= 1e-6 * (1 + np.abs(wq).max())
 
 
+def test_autotune_cache(L, tmp_path):
+    """The tune cache: a first autotune times the variants and records the
+    choice under the device's architecture and the batch's size bucket; a
+    fresh context with the same cache takes that choice without timing; an
+    unreadable entry falls back to timing."""
+    import json
+    prs = [pair(4, k, 3000) for k in range(3)]
+    P = np.concatenate([p.P for p in prs], 1)
+    Q = np.concatenate([p.Q for p in prs], 1)
+    off = np.array([0, 3000, 6000, 9000], np.int64)
+    path = str(tmp_path / "tune.json")
+    c1 = L.Context(0)
+    t1 = L.autotune(dev(P), dev(Q), off, off, L.default_params(), reps=1, ctx=c1, cache=path)
+    assert not t1["from_cache"] and max(t1["screen_ms"]) > 0
+    data = json.load(open(path))
+    assert len(data["entries"]) == 1 and data["entries"][0]["key"].startswith("gfx950|pairs=4|")
+    assert data["entries"][0]["screen_shape"] == t1["screen_shape"]
+    c2 = L.Context(0)
+    t2 = L.autotune(dev(P), dev(Q), off, off, L.default_params(), reps=1, ctx=c2, cache=path)
+    assert t2["from_cache"] and (t2["screen_shape"], t2["consistency_shape"]) == \
+        (t1["screen_shape"], t1["consistency_shape"]) and max(t2["screen_ms"]) == 0
+    assert L.get_tune(c2)["screen_shape"] == t1["screen_shape"]
+    data["entries"][0]["screen_shape"] = 99                   # out of range: timed again, entry replaced
+    json.dump(data, open(path, "w"))
+    t3 = L.autotune(dev(P), dev(Q), off, off, L.default_params(), reps=1, ctx=L.Context(0), cache=path)
+    assert not t3["from_cache"] and len(json.load(open(path))["entries"]) == 1
+
+
 def test_autotune_variants_agree(L):
     """Every launch-shape variant computes the same bits; the autotuner picks one and times all."""
     import paper_1801_01572_amd._lib as lib

@@ -9,12 +9,15 @@
   sampled descriptors against the oracle, sampled matcher rows against brute
   force (the oracle's own matcher is quadratic and too slow at this size).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import synth
-from gpu_helpers import DESC_RTOL, WORK_KEYS, check_chain, desc_exempt, dev, trace_slice
+from gpu_helpers import DESC_RTOL, POSE_TOL, WORK_KEYS, check_chain, desc_exempt, dev, rot_err, trace_slice
 
 pytestmark = pytest.mark.gpu
 
@@ -179,6 +182,18 @@ def test_building_scale_500k(L, orc):
         d2 = np.partition(d, 1)[:2]
         if d2[1] - d2[0] > 1e-5:                    # clear of the float32 rounding of near ties
             assert m32[0][i] == j, (i, m32[0][i], j)
+    # the whole pipeline against the oracle's own run, cached once (its quadratic matching takes
+    # tens of minutes on a host; tests/golden/make_c3_reference.py)
+    ref_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_building_500k.json")
+    if os.path.exists(ref_path):
+        ref = json.load(open(ref_path))
+        To = np.array(ref["T"]).reshape(4, 4)
+        ang, tr = rot_err(np.asarray(b["T"]), To)
+        print(f"  vs the oracle's run: recip {b['n_recip']} / {ref['n_recip']}, K {b['n_consistent']} / "
+              f"{ref['n_consistent']}, status {b['status']} / {ref['status']}, pose {ang:.2e} rad {tr:.2e} m; "
+              f"tie-exempt rows {ref['tie_exempt_rows_P']:.3f} / {ref['tie_exempt_rows_Q']:.3f}", flush=True)
+        assert b["status"] == ref["status"]
+        assert ang <= POSE_TOL and tr <= POSE_TOL
 
 
 def test_align_loss_c4_scale(L, orc):
