@@ -760,6 +760,8 @@ int lsr_set_tune(lsr_ctx *ctx, const lsr_tune *t) {
     return LSR_OK;
 }
 
+}  // extern "C"
+
 // ---- the tune cache: one JSON object per line inside an "entries" array
 namespace {
 
@@ -822,6 +824,8 @@ bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es)
 }
 
 }  // namespace
+
+extern "C" {
 
 int lsr_set_tune_cache(lsr_ctx *ctx, const char *path) {
     if (!ctx) return LSR_EINVAL;

@@ -24,12 +24,20 @@
 // T <- [Rod(w) | v] T (that of T_j is minus that of T_i).  The normal
 // equations are block tridiagonal (the chain) plus the loop's coupling of
 // nodes a < b; node b is eliminated last: the two chains left without it
-// (1 .. b-1 and b+1 .. n-1) are solved by block LDL^T (6x6 Cholesky per
-// node) for the right-hand side and the six columns that couple them to b,
-// then b's 6x6 Schur complement gives its step and back-substitution the
-// rest: O(n) per iteration.  Accepted when l >= l_min at the returned poses.
-// One thread per candidate (small independent problems, FP64, state in
-// device scratch).
+// (1 .. b-1 and b+1 .. n-1) are solved by block LDL^T for the right-hand
+// side and the six columns that couple them to b, then b's 6x6 Schur
+// complement gives its step and back-substitution the rest: O(n) per
+// iteration.  Accepted when l >= l_min at the returned poses.
+//
+// One wave per candidate.  Edge blocks are formed one edge per lane and
+// summed into node blocks one node per lane (each node in edge order, so
+// the sums do not depend on scheduling).  Along a chain every 6x6 (and 6x7)
+// block operation is spread over the lanes, one element each, exchanging
+// operands through LDS; each Schur-complemented diagonal block is inverted
+// by Gauss-Jordan elimination without pivoting, whose pivots are those of
+// a Cholesky factorisation (a pivot <= 1e-12 tr(H) marks the system
+// singular).  The next node's blocks are loaded while the current one is
+// eliminated.  State lives in device scratch, FP64 throughout.
 #include <math.h>
 
 #include "lsr_internal.h"
@@ -275,107 +283,148 @@ __device__ void edge_block(const double *L, const double *J, const double *xi, d
     }
 }
 
-// Cholesky of a 6x6 SPD block in place (lower); false on a pivot <= thr
-__device__ bool chol6(double *M, double thr) {
-    for (int j = 0; j < 6; ++j) {
-        double d = M[6 * j + j];
-        for (int k = 0; k < j; ++k) d -= M[6 * j + k] * M[6 * j + k];
-        if (!(d > thr)) return false;
-        const double l = sqrt(d);
-        M[6 * j + j] = l;
-        for (int i = j + 1; i < 6; ++i) {
-            double s = M[6 * i + j];
-            for (int k = 0; k < j; ++k) s -= M[6 * i + k] * M[6 * j + k];
-            M[6 * i + j] = s / l;
-        }
-    }
-    return true;
-}
-// X (6 x nc, row-major, stride nc) <- M^-1 X with M = L L^T from chol6
-__device__ void cholsolve6(const double *L, double *X, int nc) {
-    for (int c = 0; c < nc; ++c) {
-        double y[6];
-        for (int i = 0; i < 6; ++i) {
-            double s = X[nc * i + c];
-            for (int k = 0; k < i; ++k) s -= L[6 * i + k] * y[k];
-            y[i] = s / L[6 * i + i];
-        }
-        for (int i = 5; i >= 0; --i) {
-            double s = y[i];
-            for (int k = i + 1; k < 6; ++k) s -= L[6 * k + i] * X[nc * k + c];
-            X[nc * i + c] = s / L[6 * i + i];
-        }
-    }
-}
-
-constexpr int NC = 7;       // right-hand sides of a chain solve: six coupling columns and the gradient
-
 // Per-candidate scratch (doubles) for n nodes.
+constexpr int NY = 42;      // a node's right-hand sides: 6 rows x (six coupling columns, -g)
 struct Ws {
     double *T;      // n x 16 poses
-    double *Dg;     // n x 36 diagonal blocks (node 0 unused), then their factors
-    double *Of;     // n x 36: Of[k] = H(k, k+1)
-    double *g;      // n x 6
-    double *Cb;     // n x 36: H(k, b) for the nodes coupled to b
-    double *Y;      // n x 6 x NC right-hand sides / solutions
-    double *x;      // n x 6 step
+    double *K;      // n x 36 edge blocks w J^T Lambda J (odometry edges 0 .. n-2, then the loop)
+    double *r;      // n x 6 edge gradients w J^T Lambda xi
+    double *D;      // n x 36 diagonal blocks H(k, k), then the inverses of their Schur complements
+    double *O;      // n x 36: O[k] = H(k, k + 1)
+    double *Y;      // n x 42 right-hand sides, then eliminated, then solved
 };
-__host__ __device__ inline size_t ws_doubles(int n) { return (size_t)n * (16 + 36 + 36 + 6 + 36 + 6 * NC + 6); }
+__host__ __device__ inline size_t ws_doubles(int n) { return (size_t)n * (16 + 36 + 6 + 36 + 36 + NY); }
 __device__ inline Ws carve(double *base, int n) {
     Ws w;
     w.T = base; base += 16 * n;
-    w.Dg = base; base += 36 * n;
-    w.Of = base; base += 36 * n;
-    w.g = base; base += 6 * n;
-    w.Cb = base; base += 36 * n;
-    w.Y = base; base += 6 * NC * n;
-    w.x = base;
+    w.K = base; base += 36 * n;
+    w.r = base; base += 6 * n;
+    w.D = base; base += 36 * n;
+    w.O = base; base += 36 * n;
+    w.Y = base;
     return w;
 }
 
-// Block LDL^T solve of the chain of nodes [lo, hi] (diagonal Dg, upper Of)
-// for the NC right-hand sides in Y; factors Dg in place.  False on a pivot
-// <= thr.
-__device__ bool chain_solve(Ws &w, int lo, int hi, double thr) {
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// butterfly reductions: every lane ends with the same value
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// LDS of one wave's solve: one slot per lane (lanes past a block's 36 or 42
+// elements write slots nobody reads, so no lane branches)
+struct Lds {
+    double a[64], b[64], inv[64], o[64], z[64];
+    double y[2][64], x[64], t[64], s[64];
+};
+
+// Inverse of the symmetric positive definite 6x6 block whose element
+// (l / 6, l % 6) lane l < 36 holds in v: Gauss-Jordan elimination in place,
+// no pivoting (the pivot of step p is the p-th diagonal entry of the Schur
+// complement, a Cholesky pivot).  The inverse lands in L.inv[0 .. 36) and
+// each lane's element in v.  False (on every lane) on a pivot <= thr.
+__device__ bool gj6(double &v, double thr, Lds &L) {
+    const int l = threadIdx.x, i = l < 36 ? l : 35, r = i / 6, c = i % 6;
+    L.a[l] = v;
+    wsync();
+    double *src = L.a, *nxt = L.b;
+    for (int p = 0; p < 6; ++p) {
+        const double piv = src[7 * p];
+        if (!(piv > thr)) return false;
+        const double ip = 1.0 / piv;
+        const double mrc = src[i], mrp = src[6 * r + p], mpc = src[6 * p + c];
+        const double up = mpc * ip, left = -mrp * ip, rest = mrc - mrp * mpc * ip;
+        const double nv = r == p ? (c == p ? ip : up) : (c == p ? left : rest);
+        double *dst = p == 5 ? L.inv : nxt;
+        dst[l] = nv;
+        wsync();
+        nxt = src;
+        src = dst;
+        v = nv;
+    }
+    return true;
+}
+
+// Block LDL^T solve of the chain of nodes [lo, hi] (diagonal blocks D, upper
+// blocks O) for the right-hand sides Y, lane-parallel within the wave:
+// forward elimination D_k -= O_{k-1}^T D_{k-1}^-1 O_{k-1}, Y_k -= O_{k-1}^T
+// D_{k-1}^-1 Y_{k-1}, then Y_k = D_k^-1 (Y_k - O_k Y_{k+1}) backwards.  D
+// ends holding the inverted Schur complements.  False on a pivot <= thr.
+__device__ bool chain_solve(const Ws &w, int lo, int hi, double thr, Lds &L) {
+    const int l = threadIdx.x;
+    const bool m36 = l < 36, m42 = l < NY;
+    const int i36 = m36 ? l : 35, i42 = m42 ? l : 41;
+    const int r6 = i36 / 6, c6 = i36 % 6, ry = i42 / 7, cy = i42 % 7;
+    double d = w.D[36 * lo + i36], y = w.Y[NY * lo + i42], o = 0;
+    int p = 0;
     for (int k = lo; k <= hi; ++k) {
-        double *Dk = w.Dg + 36 * k;
-        double *Yk = w.Y + 6 * NC * k;
+        double nd = 0, ny = 0, no = 0;
+        if (k < hi) {
+            nd = w.D[36 * (k + 1) + i36];
+            ny = w.Y[NY * (k + 1) + i42];
+            no = w.O[36 * k + i36];
+        }
         if (k > lo) {
-            // W = O^T D_{k-1}^-1 with O = Of[k-1]: D_k -= W O, Y_k -= W Y_{k-1}
-            const double *O = w.Of + 36 * (k - 1);
-            const double *Lp = w.Dg + 36 * (k - 1);
-            double Z[36];                       // Z = D_{k-1}^-1 O (6 x 6), so W = Z^T
-            for (int i = 0; i < 36; ++i) Z[i] = O[i];
-            cholsolve6(Lp, Z, 6);
-            const double *Yp = w.Y + 6 * NC * (k - 1);
-            for (int a = 0; a < 6; ++a) {
-                for (int b = 0; b < 6; ++b) {
-                    double s = 0;
-                    for (int m = 0; m < 6; ++m) s += Z[6 * m + a] * O[6 * m + b];
-                    Dk[6 * a + b] -= s;
-                }
-                for (int c = 0; c < NC; ++c) {
-                    double s = 0;
-                    for (int m = 0; m < 6; ++m) s += Z[6 * m + a] * Yp[NC * m + c];
-                    Yk[NC * a + c] -= s;
-                }
+            L.o[l] = o;
+            wsync();
+            double z = 0;                          // Z = D_{k-1}^-1 O_{k-1}
+            for (int q = 0; q < 6; ++q) z += L.inv[6 * r6 + q] * L.o[6 * q + c6];
+            L.z[l] = z;
+            wsync();
+            double sd = 0, sy = 0;
+            for (int q = 0; q < 6; ++q) {
+                sd += L.z[6 * q + r6] * L.o[6 * q + c6];
+                sy += L.z[6 * q + ry] * L.y[p][7 * q + cy];
+            }
+            d -= sd;
+            y -= sy;
+        }
+        if (m42) w.Y[NY * k + l] = y;
+        L.y[p ^ 1][l] = y;
+        if (!gj6(d, thr, L)) return false;
+        if (m36) w.D[36 * k + l] = d;
+        p ^= 1;
+        d = nd;
+        y = ny;
+        o = no;
+    }
+    __syncthreads();                               // the inverses, read by rows below
+    double yv = w.Y[NY * hi + i42], orow[6], drow[6];
+    for (int q = 0; q < 6; ++q) { orow[q] = 0; drow[q] = w.D[36 * hi + 6 * ry + q]; }
+    for (int k = hi; k >= lo; --k) {
+        double nyv = 0, norow[6], ndrow[6];
+        for (int q = 0; q < 6; ++q) norow[q] = ndrow[q] = 0;
+        if (k > lo) {
+            nyv = w.Y[NY * (k - 1) + i42];
+            for (int q = 0; q < 6; ++q) {
+                norow[q] = w.O[36 * (k - 1) + 6 * ry + q];
+                ndrow[q] = w.D[36 * (k - 1) + 6 * ry + q];
             }
         }
-        if (!chol6(Dk, thr)) return false;
-    }
-    for (int k = hi; k >= lo; --k) {
-        double *Yk = w.Y + 6 * NC * k;
         if (k < hi) {
-            const double *O = w.Of + 36 * k;
-            const double *Yn = w.Y + 6 * NC * (k + 1);
-            for (int a = 0; a < 6; ++a)
-                for (int c = 0; c < NC; ++c) {
-                    double s = 0;
-                    for (int m = 0; m < 6; ++m) s += O[6 * a + m] * Yn[NC * m + c];
-                    Yk[NC * a + c] -= s;
-                }
+            double s = 0;
+            for (int q = 0; q < 6; ++q) s += orow[q] * L.x[7 * q + cy];
+            yv -= s;
         }
-        cholsolve6(w.Dg + 36 * k, Yk, NC);
+        L.t[l] = yv;
+        wsync();
+        double x = 0;
+        for (int q = 0; q < 6; ++q) x += drow[q] * L.t[7 * q + cy];
+        if (m42) w.Y[NY * k + l] = x;
+        L.x[l] = x;
+        wsync();
+        yv = nyv;
+        for (int q = 0; q < 6; ++q) { orow[q] = norow[q]; drow[q] = ndrow[q]; }
     }
     return true;
 }
@@ -398,27 +447,39 @@ struct LoopArgs {
     lsr_loop_result *res;
 };
 
+// Energy at the poses T (every lane gets it): odometry edges one per lane.
 __device__ double energy(const LoopArgs &a, const double *T, const lsr_edge &L, const double *Ll, double mu,
                          double *f_loop) {
     double E = 0, xi[6];
-    for (int s = 0; s < a.n - 1; ++s) {
+    for (int s = threadIdx.x; s < a.n - 1; s += 64) {
         pg::residual(a.odo[s].T, T + 16 * a.odo[s].i, T + 16 * a.odo[s].j, xi, nullptr);
         E += a.lambda * pg::quad(a.L_odo + 36 * s, xi);
     }
+    E = pg::wave_sum(E);
     pg::residual(L.T, T + 16 * L.i, T + 16 * L.j, xi, nullptr);
     const double f = pg::quad(Ll, xi);
     *f_loop = f;
     return E + (mu > 0 ? mu * f / (mu + f) : 0.0);
 }
 
+// H(k, b) for a node k != b: minus the loop's block at its other end u (node
+// 0 being fixed has none), minus the odometry blocks of b's chain neighbours.
+__device__ __forceinline__ double coupling(const pg::Ws &w, int n, int k, int b, int u, int q, int c) {
+    double s = 0;
+    if (k == u && u >= 1) s -= w.K[36 * (n - 1) + 6 * q + c];
+    if (k == b - 1) s -= w.K[36 * (b - 1) + 6 * q + c];
+    if (k == b + 1) s -= w.K[36 * b + 6 * c + q];
+    return s;
+}
+
 __global__ void __launch_bounds__(64) k_loop_solve(LoopArgs a) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n_loops) return;
-    const int n = a.n;
-    pg::Ws w = pg::carve(a.scratch + (size_t)c * pg::ws_doubles(n), n);
+    __shared__ pg::Lds S;
+    const int c = blockIdx.x, l = threadIdx.x, n = a.n;
+    const pg::Ws w = pg::carve(a.scratch + (size_t)c * pg::ws_doubles(n), n);
     const lsr_edge L = a.loops[c];
     const double *Ll = a.L_loop + 36 * c;
-    for (int k = 0; k < 16 * n; ++k) w.T[k] = a.T_init[k];
+    for (int k = l; k < 16 * n; k += 64) w.T[k] = a.T_init[k];
+    __syncthreads();
     lsr_loop_result r;
     r.n_corr = a.cnt_loop[c];
     r.mu = a.tau2 * (double)r.n_corr;
@@ -429,100 +490,103 @@ __global__ void __launch_bounds__(64) k_loop_solve(LoopArgs a) {
         r.l = 0.0;
         r.status = LSR_REJECTED;
     } else {
-        const int b = max(L.i, L.j);
+        const int b = max(L.i, L.j), u = min(L.i, L.j);
+        const bool m36 = l < 36, m42 = l < pg::NY;
+        const int r6 = l / 6, c6 = l % 6, ry = m42 ? l / 7 : 0, cy = m42 ? l % 7 : 0;
         int it;
-        for (it = 0; it < a.max_iter && n > 1; ++it) {
-            for (int k = 0; k < 36 * n; ++k) { w.Dg[k] = 0; w.Of[k] = 0; w.Cb[k] = 0; }
-            for (int k = 0; k < 6 * n; ++k) w.g[k] = 0;
-            // every edge: K = w J^T L J, r = w J^T L xi into the blocks of its nodes
-            for (int e = 0; e < n; ++e) {
+        for (it = 0; it < a.max_iter; ++it) {
+            // edge blocks, one edge per lane
+            for (int e = l; e < n; e += 64) {
                 const lsr_edge &E = e < n - 1 ? a.odo[e] : L;
                 const double *Le = e < n - 1 ? a.L_odo + 36 * e : Ll;
-                double xi[6], J[36], K[36], rr[6];
+                double xi[6], J[36];
                 pg::residual(E.T, w.T + 16 * E.i, w.T + 16 * E.j, xi, J);
                 double wt = a.lambda;
                 if (e == n - 1) { const double q = r.mu / (r.mu + pg::quad(Le, xi)); wt = q * q; }
-                pg::edge_block(Le, J, xi, wt, K, rr);
-                const int i = E.i, j = E.j;
-                for (int q = 0; q < 6; ++q) { w.g[6 * i + q] += rr[q]; w.g[6 * j + q] -= rr[q]; }
-                for (int q = 0; q < 36; ++q) { w.Dg[36 * i + q] += K[q]; w.Dg[36 * j + q] += K[q]; }
-                // off-diagonal H(i, j) = -K: chain neighbours go to Of, the loop's pair (a, b) to Cb[a]
-                const int u = min(i, j), v = max(i, j);
-                if (u == 0) continue;                       // node 0 is fixed
-                if (v == b && e == n - 1) {
-                    for (int q = 0; q < 36; ++q) w.Cb[36 * u + q] -= K[q];
-                } else if (v == u + 1) {
-                    for (int q = 0; q < 36; ++q) w.Of[36 * u + q] -= K[q];
-                }
+                pg::edge_block(Le, J, xi, wt, w.K + 36 * e, w.r + 6 * e);
             }
-            double tr = 0;
-            for (int k = 1; k < n; ++k)
-                for (int q = 0; q < 6; ++q) tr += w.Dg[36 * k + 7 * q];
-            const double thr = 1e-12 * tr;
-            // node b last: H(k, b) for k != b are Of[b-1] (k = b-1), Of[b]^T (k = b+1) and Cb[lo] (loop)
-            if (b - 1 >= 1) for (int q = 0; q < 36; ++q) w.Cb[36 * (b - 1) + q] += w.Of[36 * (b - 1) + q];
-            if (b + 1 <= n - 1)
-                for (int r6 = 0; r6 < 6; ++r6)
-                    for (int c6 = 0; c6 < 6; ++c6) w.Cb[36 * (b + 1) + 6 * r6 + c6] += w.Of[36 * b + 6 * c6 + r6];
-            // right-hand sides of the two chains: six coupling columns and -g
-            for (int k = 1; k < n; ++k) {
-                if (k == b) continue;
-                double *Yk = w.Y + 6 * pg::NC * k;
+            __syncthreads();
+            // node blocks, one node per lane, its edges in order
+            double trp = 0;
+            for (int k = 1 + l; k < n; k += 64) {
+                double D[36], g[6];
+                for (int q = 0; q < 36; ++q) D[q] = 0;
+                for (int q = 0; q < 6; ++q) g[q] = 0;
+                const int es[3] = {k - 1, k <= n - 2 ? k : -1, (L.i == k || L.j == k) ? n - 1 : -1};
+                for (int t = 0; t < 3; ++t) {
+                    const int e = es[t];
+                    if (e < 0) continue;
+                    const lsr_edge &E = e < n - 1 ? a.odo[e] : L;
+                    const double *K = w.K + 36 * e, *rr = w.r + 6 * e;
+                    for (int q = 0; q < 36; ++q) D[q] += K[q];
+                    if (E.i == k) for (int q = 0; q < 6; ++q) g[q] += rr[q];
+                    else for (int q = 0; q < 6; ++q) g[q] -= rr[q];
+                }
+                for (int q = 0; q < 36; ++q) w.D[36 * k + q] = D[q];
+                for (int q = 0; q < 6; ++q) trp += D[7 * q];
+                if (k <= n - 2)
+                    for (int q = 0; q < 36; ++q) w.O[36 * k + q] = -w.K[36 * k + q];
                 for (int q = 0; q < 6; ++q) {
-                    for (int c6 = 0; c6 < 6; ++c6) Yk[pg::NC * q + c6] = w.Cb[36 * k + 6 * q + c6];
-                    Yk[pg::NC * q + 6] = -w.g[6 * k + q];
+                    for (int cc = 0; cc < 6; ++cc) w.Y[pg::NY * k + 7 * q + cc] = coupling(w, n, k, b, u, q, cc);
+                    w.Y[pg::NY * k + 7 * q + 6] = -g[q];
                 }
             }
+            const double thr = 1e-12 * pg::wave_sum(trp);
+            __syncthreads();
             bool ok = true;
-            if (b - 1 >= 1) ok = pg::chain_solve(w, 1, b - 1, thr);
-            if (ok && b + 1 <= n - 1) ok = pg::chain_solve(w, b + 1, n - 1, thr);
+            if (b - 1 >= 1) ok = pg::chain_solve(w, 1, b - 1, thr, S);
+            if (ok && b + 1 <= n - 1) ok = pg::chain_solve(w, b + 1, n - 1, thr, S);
             if (!ok) { status = LSR_DEGENERATE; break; }
-            // Schur complement on b: S = H_bb - sum_k H_kb^T Y_k, rhs -g_b - sum_k H_kb^T z_k
-            double S[36], sb[6];
-            for (int q = 0; q < 36; ++q) S[q] = w.Dg[36 * b + q];
-            for (int q = 0; q < 6; ++q) sb[q] = -w.g[6 * b + q];
-            for (int k = 1; k < n; ++k) {
-                if (k == b) continue;
-                const double *C = w.Cb + 36 * k;
-                const double *Yk = w.Y + 6 * pg::NC * k;
-                for (int r6 = 0; r6 < 6; ++r6) {
-                    for (int c6 = 0; c6 < 6; ++c6) {
-                        double s = 0;
-                        for (int m = 0; m < 6; ++m) s += C[6 * m + r6] * Yk[pg::NC * m + c6];
-                        S[6 * r6 + c6] -= s;
-                    }
-                    double s = 0;
-                    for (int m = 0; m < 6; ++m) s += C[6 * m + r6] * Yk[pg::NC * m + 6];
-                    sb[r6] -= s;
-                }
+            __syncthreads();
+            // b's Schur complement (lanes < 42: six columns and the right-hand side)
+            double sv = 0;
+            if (m42) sv = cy < 6 ? w.D[36 * b + 6 * ry + cy] : w.Y[pg::NY * b + 7 * ry + 6];
+            const int ks[3] = {u >= 1 && u != b - 1 ? u : -1, b - 1 >= 1 ? b - 1 : -1, b + 1 <= n - 1 ? b + 1 : -1};
+            for (int t = 0; t < 3; ++t) {
+                const int k = ks[t];
+                if (k < 0 || !m42) continue;
+                double s = 0;
+                for (int q = 0; q < 6; ++q) s += coupling(w, n, k, b, u, q, ry) * w.Y[pg::NY * k + 7 * q + cy];
+                sv -= s;
             }
-            if (!pg::chol6(S, thr)) { status = LSR_DEGENERATE; break; }
-            pg::cholsolve6(S, sb, 1);
+            S.s[l] = sv;
+            pg::wsync();
+            double v = m36 ? S.s[7 * r6 + c6] : 0.0;
+            if (!pg::gj6(v, thr, S)) { status = LSR_DEGENERATE; break; }
+            double xb[6];
+            for (int i = 0; i < 6; ++i) {
+                double s = 0;
+                for (int q = 0; q < 6; ++q) s += S.inv[6 * i + q] * S.s[7 * q + 6];
+                xb[i] = s;
+            }
+            // steps and retraction T_k <- [Rod(w) | v] T_k, one node per lane
             double dmax = 0;
-            for (int q = 0; q < 6; ++q) { w.x[6 * b + q] = sb[q]; dmax = fmax(dmax, fabs(sb[q])); }
-            for (int k = 1; k < n; ++k) {
-                if (k == b) continue;
-                const double *Yk = w.Y + 6 * pg::NC * k;
+            for (int k = 1 + l; k < n; k += 64) {
+                double x[6];
                 for (int q = 0; q < 6; ++q) {
-                    double s = Yk[pg::NC * q + 6];
-                    for (int m = 0; m < 6; ++m) s -= Yk[pg::NC * q + m] * sb[m];
-                    w.x[6 * k + q] = s;
-                    dmax = fmax(dmax, fabs(s));
+                    if (k == b) { x[q] = xb[q]; }
+                    else {
+                        double s = w.Y[pg::NY * k + 7 * q + 6];
+                        for (int m = 0; m < 6; ++m) s -= w.Y[pg::NY * k + 7 * q + m] * xb[m];
+                        x[q] = s;
+                    }
+                    dmax = fmax(dmax, fabs(x[q]));
                 }
-            }
-            for (int k = 1; k < n; ++k) {                    // T_k <- [Rod(w) | v] T_k
                 double R[3][3], E4[16];
-                pg::rod(w.x + 6 * k, R);
+                pg::rod(x, R);
                 for (int r3 = 0; r3 < 3; ++r3) {
                     for (int c3 = 0; c3 < 3; ++c3) E4[4 * r3 + c3] = R[r3][c3];
-                    E4[4 * r3 + 3] = w.x[6 * k + 3 + r3];
+                    E4[4 * r3 + 3] = x[3 + r3];
                 }
                 E4[12] = E4[13] = E4[14] = 0;
                 E4[15] = 1;
                 pg::mul4(E4, w.T + 16 * k, w.T + 16 * k);
             }
+            dmax = pg::wave_max(dmax);
+            __syncthreads();
             if (dmax < a.tol) { ++it; break; }
         }
+        __syncthreads();
         r.iters = it;
         r.energy = energy(a, w.T, L, Ll, r.mu, &r.f_loop);
         const double q = r.mu / (r.mu + r.f_loop);
@@ -530,9 +594,9 @@ __global__ void __launch_bounds__(64) k_loop_solve(LoopArgs a) {
         if (status != LSR_DEGENERATE) status = r.l >= a.l_min ? LSR_ACCEPTED : LSR_REJECTED;
         r.status = status;
     }
-    a.res[c] = r;
+    if (l == 0) a.res[c] = r;
     if (a.T_out)
-        for (int k = 0; k < 16 * n; ++k) a.T_out[(size_t)c * 16 * n + k] = w.T[k];
+        for (int k = l; k < 16 * n; k += 64) a.T_out[(size_t)c * 16 * n + k] = w.T[k];
 }
 
 size_t loop_scratch_bytes(int n, int n_loops) { return sizeof(double) * pg::ws_doubles(n) * (size_t)n_loops; }
@@ -559,7 +623,7 @@ hipError_t launch_loop_solve(int n, const double *T_init, const lsr_edge *odo, c
     a.scratch = scratch;
     a.T_out = T_out;
     a.res = res;
-    hipLaunchKernelGGL(k_loop_solve, dim3((n_loops + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_loop_solve, dim3(n_loops), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
