@@ -135,6 +135,54 @@ def bench_loops(lsr, n_frags, m, n_true, n_false, steps, cpu):
     return out
 
 
+def recovery_stats(lsr, res, prs):
+    """Registration outcome against the generating transforms: the share of
+    overlapping pairs whose pose is within 0.5 deg / 1 cm (strict) and within
+    0.2 m RMS over P's points (good), accepted shares, false accepts (accepted
+    but not good) and accepted negatives."""
+    import numpy as np
+    n = len(res)
+    neg = np.array([bool(p.meta.get("negative", False)) for p in prs])
+    acc = np.array([r["status"] == lsr.ACCEPTED for r in res])
+    strict = np.zeros(n, bool)
+    good = np.zeros(n, bool)
+    rot = np.zeros(n)
+    for k, (r, p) in enumerate(zip(res, prs)):
+        T, G = np.asarray(r["T"]), p.T_gt
+        x = p.P[:3].astype(np.float64)
+        rms = np.sqrt(np.mean(np.sum(((T[:3, :3] - G[:3, :3]) @ x + (T[:3, 3] - G[:3, 3])[:, None]) ** 2, 0)))
+        rot[k] = _rot_angle(T[:3, :3], G[:3, :3])
+        strict[k] = rot[k] <= np.deg2rad(0.5) and np.linalg.norm(T[:3, 3] - G[:3, 3]) <= 0.01
+        good[k] = rms <= 0.2
+    pos = ~neg
+    f = lambda m: round(float(m.mean()), 4) if m.size else None
+    return {"pairs": n, "negatives": int(neg.sum()),
+            "recovered_0.5deg_1cm": f(strict[pos]), "good_0.2m_rms": f(good[pos]),
+            "accepted": f(acc), "accepted_and_good": f((acc & good)[pos]),
+            "false_accepts": f(acc & ~(good & pos)), "negatives_accepted": f(acc[neg]) if neg.any() else None,
+            "median_rot_err_deg": round(float(np.rad2deg(np.median(rot[pos]))), 3) if pos.any() else None}
+
+
+def bench_recovery_c0(lsr, n_pairs):
+    """Recovery on the small single-pair recipe (5,000-point scenes of planes,
+    boxes and a sphere, 70% overlap, sigma 3 mm), n_pairs seeded pairs in one
+    batch with the default parameters."""
+    import numpy as np
+    import torch
+
+    import synth
+    prs = synth.make_batch(0, n_pairs)
+    P = np.concatenate([p.P for p in prs], 1)
+    Q = np.concatenate([p.Q for p in prs], 1)
+    offP = np.concatenate([[0], np.cumsum([p.P.shape[1] for p in prs])]).astype(np.int64)
+    offQ = np.concatenate([[0], np.cumsum([p.Q.shape[1] for p in prs])]).astype(np.int64)
+    prm = lsr.default_params(precision=lsr.BF16_SCREEN)
+    res = lsr.register_batch(torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda(), offP, offQ, prm)
+    out = {"workload": f"{n_pairs} pairs of the 5,000-point planes/boxes/sphere recipe", **recovery_stats(lsr, res, prs)}
+    log(f"recovery (small scenes): {out}")
+    return out
+
+
 def bench_roc(lsr, n_pairs, first_pair):
     """Accept/reject on held-out loop-closure pairs (the ragged recipe, 20%
     negatives, pairs first_pair .. first_pair + n_pairs - 1, disjoint from
@@ -187,7 +235,8 @@ def bench_roc(lsr, n_pairs, first_pair):
            "roc": {"rho": [float(g) for g in grid[::5]], "tpr": [round(t, 4) for t in tpr[::5]],
                    "fpr": [round(f, 4) for f in fpr[::5]]},
            "ratio_good_median": float(np.median(ratio[good])) if good.any() else None,
-           "ratio_bad_median": float(np.median(ratio[~good])) if (~good).any() else None}
+           "ratio_bad_median": float(np.median(ratio[~good])) if (~good).any() else None,
+           "recovery_at_default": recovery_stats(lsr, res, prs)}
     log(f"accept/reject ROC: {out}")
     return out
 
@@ -263,6 +312,8 @@ def main():
     ap.add_argument("--chain", type=int, default=64, help="loop-verification chain length (0: skip)")
     ap.add_argument("--roc-pairs", type=int, default=256, help="held-out pairs for the accept/reject ROC (0: skip)")
     ap.add_argument("--no-building", action="store_true", help="skip the 500k/500k building pair")
+    ap.add_argument("--small-pairs", type=int, default=64,
+                    help="pairs of the 5,000-point recipe for the recovery line (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -425,18 +476,8 @@ def main():
                       "rows_Q": round(float(tQ[w0 == 1].mean()), 4)}
         log(f"tie-exempt share (pair 0): {tie_exempt}")
 
-    # recovery of the generating transform (rotation <= 0.5 deg and translation <= 1 cm)
-    errs = [(_rot_angle(np.asarray(r["T"])[:3, :3], prs[k].T_gt[:3, :3]),
-             float(np.linalg.norm(np.asarray(r["T"])[:3, 3] - prs[k].T_gt[:3, 3]))) for r, k in zip(res, order)]
-    rec = np.array([a <= np.deg2rad(0.5) and t <= 0.01 for a, t in errs])
-    accd = np.array([r["status"] == lsr.ACCEPTED for r in res])
-    neg = np.array([bool(prs[k].meta.get("negative", False)) for k in order])
-    recovery = {"recovered": round(float(rec[~neg].mean()) if (~neg).any() else 0.0, 4),
-                "accepted_and_recovered": round(float((rec & accd)[~neg].mean()) if (~neg).any() else 0.0, 4),
-                "false_accepts": round(float((accd & ~rec).mean()), 4),
-                "negatives_accepted": round(float(accd[neg].mean()), 4) if neg.any() else None,
-                "median_rot_err_deg": round(float(np.rad2deg(np.median([a for a, _ in errs]))), 3),
-                "rule": "rotation <= 0.5 deg and translation <= 1 cm from the generating transform"}
+    # recovery of the generating transforms
+    recovery = recovery_stats(lsr, res, [prs[k] for k in order])
     log(f"recovery: {recovery}")
 
     surf = None
@@ -452,6 +493,7 @@ def main():
     roc = None
     if args.roc_pairs > 0:
         roc = bench_roc(lsr, args.roc_pairs, 1000)
+    small = bench_recovery_c0(lsr, args.small_pairs) if args.small_pairs > 0 else None
 
     acc = float(np.mean([r["status"] == lsr.ACCEPTED for r in res]))
     fb = int(sum(r["n_fallback_rows"] for r in res))
@@ -492,6 +534,7 @@ def main():
         "pose_vs_oracle": pose_vs_oracle,
         "tie_exempt": tie_exempt,
         "recovery_vs_T_gt": recovery,
+        "recovery_small_scenes": small,
         "paper_context": {"ms_per_pair": 20.50, "hardware": "Intel i7-6850K + NVIDIA Titan X Pascal",
                           "workload": "augmented ICL-NUIM fragment pairs, 5 cm voxels, point count not stated; "
                                       "GPU RANSAC (Table 1 average)",

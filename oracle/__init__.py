@@ -256,7 +256,7 @@ def ransac_hypotheses(P, Q, nnQ, n_hyp, tau=0.9, seed=0x1801015720):
 
 
 def ransac(P, nrmP, Q, nrmQ, nnQ, n_hyp, tau=0.9, seed=0x1801015720, delta=0.015, normal_check=1,
-           normal_cos=0.8660254, min_ratio=0.15):
+           normal_cos=0.8660254, min_ratio=0.25):
     """RANSAC consensus (Algorithm 1) on the one-directional cache nnQ:
     (status, T 4x4, info dict)."""
     P = _f32(P); Q = _f32(Q)

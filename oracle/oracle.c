@@ -1059,7 +1059,7 @@ double orc_align_loss(const double *p, const double *q, int64_t m, const double 
 void orc_default_params(orc_params *p) {
     p->r_normal = 0.025f; p->r_feature = 0.05f; p->max_corr = 0.015f; p->tau = 0.9f;
     p->n_trials = 0; p->gnc_div = 1.4; p->gnc_every = 4; p->gnc_max_iter = 256; p->polish_iter = 32;
-    p->min_inlier_ratio = 0.15f; p->min_consistent = 10; p->normal_check = 0; p->normal_cos = 0.8660254f;
+    p->min_inlier_ratio = 0.25f; p->min_consistent = 10; p->normal_check = 0; p->normal_cos = 0.8660254f;
     p->seed = 0x1801015720ULL;
 }
 

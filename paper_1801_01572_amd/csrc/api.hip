@@ -532,7 +532,7 @@ void lsr_default_params(lsr_params *p) {
     p->gnc_every = 4;
     p->gnc_max_iter = 256;
     p->polish_iter = 32;
-    p->min_inlier_ratio = 0.15f;
+    p->min_inlier_ratio = 0.25f;
     p->min_consistent = 10;
     p->normal_check = 0;
     p->normal_cos = 0.8660254f;
