@@ -284,9 +284,15 @@ def bench_building(lsr):
            "oracle": None}
     if ref is not None:
         To = np.array(ref["T"]).reshape(4, 4)
+        # the oracle's acceptance applied to its recorded ratio and count with this run's thresholds
+        st = ref["status"]
+        if st != lsr.DEGENERATE:
+            ok = ref["n_consistent"] >= prm.min_consistent and \
+                ref["inlier_ratio"] >= float(np.float32(prm.min_inlier_ratio))
+            st = lsr.ACCEPTED if ok else lsr.REJECTED
         out["oracle"] = {"rot_err_rad": _rot_angle(T[:3, :3], To[:3, :3]),
                          "trans_err_m": float(np.linalg.norm(T[:3, 3] - To[:3, 3])),
-                         "status": ref["status"], "recip": ref["n_recip"], "consistent": ref["n_consistent"],
+                         "status": st, "recip": ref["n_recip"], "consistent": ref["n_consistent"],
                          "tie_exempt_rows": [round(ref["tie_exempt_rows_P"], 4), round(ref["tie_exempt_rows_Q"], 4)],
                          "oracle_seconds": ref["oracle_seconds"], "threads": ref.get("threads")}
     log(f"building pair: {out}")

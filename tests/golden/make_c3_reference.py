@@ -46,6 +46,7 @@ def main():
            "n_valid_P": int(d["n_valid_P"]), "n_valid_Q": int(d["n_valid_Q"]),
            "inlier_ratio": float(d["inlier_ratio"]),
            "tie_exempt_rows_P": float(tP[vF == 1].mean()), "tie_exempt_rows_Q": float(tQ[vG == 1].mean()),
+           "min_inlier_ratio": float(prm.min_inlier_ratio), "min_consistent": int(prm.min_consistent),
            "T_gt": pr.T_gt.reshape(16).tolist(), "oracle_seconds": round(time.time() - t0, 1),
            "threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()}
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_building_500k.json")

@@ -163,3 +163,33 @@ def test_loop_verify_at_scale(L, orc):
         r, To = orc.loop_solve(ch.T_init, ch.odo, Lo[:63], ch.loops[c], Lo[63 + c], co[63 + c])
         assert abs(res[c]["l"] - r["l"]) <= 1e-9 and res[c]["status"] == r["status"]
         assert np.abs(T[c] - To).max() <= 1e-9
+
+
+def test_loop_solve_long_chain(L, orc):
+    """A 150-node chain: edges and nodes beyond the wave's 64 lanes (each lane
+    takes several), and a chain on one side of the loop's later node longer
+    than 64; the solve against the oracle's dense one on the GPU's own edge
+    information."""
+    ch = make_chain(150, 2000, n_true=2, n_false=2)
+    frags = [dev(f) for f in ch.frags]
+    n = len(ch.frags)
+    print(f"loop solve: {n} fragments x 2000 points, {len(ch.loops)} candidates "
+          f"{[(i, j) for i, j, _ in ch.loops]}", flush=True)
+    prm = L.loop_params()
+    res, T = L.loop_verify(frags, ch.T_init, ch.odo, ch.loops, prm)
+    info, cnt = L.edge_info(frags, list(ch.odo) + list(ch.loops), prm.eps)
+    Lo = info.cpu().numpy()
+    co = cnt.cpu().numpy()
+    T = T.cpu().numpy()
+    assert max(max(i, j) for i, j, _ in ch.loops) - 1 > 64
+    for c in range(len(ch.loops)):
+        r, To = orc.loop_solve(ch.T_init, ch.odo, Lo[:n - 1], ch.loops[c], Lo[n - 1 + c], co[n - 1 + c])
+        g = res[c]
+        print(f"  candidate {c}: gpu l {g['l']:.6f} status {g['status']} iters {g['iters']}; "
+              f"oracle l {r['l']:.6f} status {r['status']} iters {r['iters']}", flush=True)
+        assert g["n_corr"] == co[n - 1 + c]
+        assert abs(g["l"] - r["l"]) <= 1e-9
+        assert g["status"] == r["status"]
+        assert abs(g["iters"] - r["iters"]) <= 1
+        assert np.abs(T[c] - To).max() <= 1e-9
+        assert abs(g["energy"] - r["energy"]) <= 1e-9 * (1 + abs(r["energy"]))
