@@ -163,23 +163,26 @@ def recovery_stats(lsr, res, prs):
             "median_rot_err_deg": round(float(np.rad2deg(np.median(rot[pos]))), 3) if pos.any() else None}
 
 
-def bench_recovery_c0(lsr, n_pairs):
-    """Recovery on the small single-pair recipe (5,000-point scenes of planes,
-    boxes and a sphere, 70% overlap, sigma 3 mm), n_pairs seeded pairs in one
-    batch with the default parameters."""
+RECOVERY_RECIPES = {0: "5,000-point planes/boxes/sphere scenes (70% overlap, sigma 3 mm)",
+                    5: "20,000-point rooms holding 25 objects of varied curvature (sigma 1 mm)"}
+
+
+def bench_recovery(lsr, recipe, n_pairs):
+    """Recovery of the generating transforms on n_pairs seeded pairs of a
+    recipe, registered in one batch with the default parameters."""
     import numpy as np
     import torch
 
     import synth
-    prs = synth.make_batch(0, n_pairs)
+    prs = synth.make_batch(recipe, n_pairs)
     P = np.concatenate([p.P for p in prs], 1)
     Q = np.concatenate([p.Q for p in prs], 1)
     offP = np.concatenate([[0], np.cumsum([p.P.shape[1] for p in prs])]).astype(np.int64)
     offQ = np.concatenate([[0], np.cumsum([p.Q.shape[1] for p in prs])]).astype(np.int64)
     prm = lsr.default_params(precision=lsr.BF16_SCREEN)
     res = lsr.register_batch(torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda(), offP, offQ, prm)
-    out = {"workload": f"{n_pairs} pairs of the 5,000-point planes/boxes/sphere recipe", **recovery_stats(lsr, res, prs)}
-    log(f"recovery (small scenes): {out}")
+    out = {"workload": f"{n_pairs} pairs of the {RECOVERY_RECIPES[recipe]}", **recovery_stats(lsr, res, prs)}
+    log(f"recovery (recipe {recipe}): {out}")
     return out
 
 
@@ -324,7 +327,7 @@ def main():
     ap.add_argument("--roc-pairs", type=int, default=256, help="held-out pairs for the accept/reject ROC (0: skip)")
     ap.add_argument("--no-building", action="store_true", help="skip the 500k/500k building pair")
     ap.add_argument("--small-pairs", type=int, default=64,
-                    help="pairs of the 5,000-point recipe for the recovery line (0: skip)")
+                    help="pairs of the small-scene and the rich-room recipes for the recovery lines (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -504,7 +507,8 @@ def main():
     roc = None
     if args.roc_pairs > 0:
         roc = bench_roc(lsr, args.roc_pairs, 1000)
-    small = bench_recovery_c0(lsr, args.small_pairs) if args.small_pairs > 0 else None
+    small = bench_recovery(lsr, 0, args.small_pairs) if args.small_pairs > 0 else None
+    rich = bench_recovery(lsr, 5, args.small_pairs) if args.small_pairs > 0 else None
 
     acc = float(np.mean([r["status"] == lsr.ACCEPTED for r in res]))
     fb = int(sum(r["n_fallback_rows"] for r in res))
@@ -546,6 +550,7 @@ def main():
         "tie_exempt": tie_exempt,
         "recovery_vs_T_gt": recovery,
         "recovery_small_scenes": small,
+        "recovery_rich_rooms": rich,
         "paper_context": {"ms_per_pair": 20.50, "hardware": "Intel i7-6850K + NVIDIA Titan X Pascal",
                           "workload": "augmented ICL-NUIM fragment pairs, 5 cm voxels, point count not stated; "
                                       "GPU RANSAC (Table 1 average)",
