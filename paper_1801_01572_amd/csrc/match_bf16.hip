@@ -81,6 +81,10 @@ struct ScreenScratch {
     int32_t *lst;         // list slots x LCAP
     int32_t *lst_cnt;     // list slots
     int32_t *full_row, *full_frag, *full_cnt;
+    int32_t *lmark, *lpos;// ntot: uncertified rows marked at their packed rows, and the marks' exclusive scan
+    int32_t *fb_row2;     // ntot: the uncertified rows of each fragment in packed-row order
+    float *thr2;          // ntot: their thresholds
+    int32_t *stmp;        // scan scratch
     // descriptor-space row order (see "Row order" below)
     float *pca;           // (nfrag/2 + 1) x 96: three principal directions (30 each) and their key scales
     uint64_t *key0, *key1;// ntot: (fragment, Morton key) sort keys
@@ -126,6 +130,11 @@ static ScreenScratch carve(void *base, const GridBufs &g, size_t *bytes) {
     s.full_row = (int32_t *)take(sizeof(int32_t) * n1);
     s.full_frag = (int32_t *)take(sizeof(int32_t) * n1);
     s.full_cnt = (int32_t *)take(256);
+    s.lmark = (int32_t *)take(sizeof(int32_t) * n1);
+    s.lpos = (int32_t *)take(sizeof(int32_t) * n1);
+    s.fb_row2 = (int32_t *)take(sizeof(int32_t) * n1);
+    s.thr2 = (float *)take(sizeof(float) * n1);
+    s.stmp = (int32_t *)take(sizeof(int32_t) * scan_tmp_elems((int64_t)n1));
     s.pca = (float *)take(sizeof(float) * 96 * (size_t)(g.nfrag / 2 + 1));
     s.key0 = (uint64_t *)take(sizeof(uint64_t) * n1);
     s.key1 = (uint64_t *)take(sizeof(uint64_t) * n1);
@@ -1054,6 +1063,248 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     }
 }
 
+// Collect pass over the pruned layout.  The queries are a fragment's
+// uncertified rows in packed-row order (slots [start, start + 256) of its
+// list, so a block's rows are neighbours in descriptor space); a row with no
+// reference distance (threshold -inf) is already on the float32 rescan list
+// and takes no part.  A row needs partner chunk k unless the chunk's bound on
+// every computed score of its rows (the pruned screen's bound) stays below
+// the row's threshold: a skipped chunk holds no row that the exhaustive
+// collect pass would append, so the lists receive the same candidates.  The
+// block screens its queries against every centroid, then sweeps the chunks
+// some wavefront needs (a wavefront outside a chunk's mask stages it but
+// skips its MFMAs); every candidate of a swept tile whose score reaches the
+// row's threshold goes to the row's list.  Fragments past PR_NCH_MAX chunks
+// are swept whole.
+template <int SW, int SQB, int CH>
+__global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)))
+k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, const uint16_t *cpk, const float4 *cst,
+             const int32_t *rinv, const int32_t *fb_row, const int32_t *fb_cnt, const float *thr, int32_t *lst,
+             int32_t *lst_cnt) {
+    static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS, "pruned screen shape");
+    constexpr int CROWS = CH * 16;
+    constexpr int U4 = CROWS * PK / 8;
+    static_assert(SW <= 4 && PR_NCH_MAX <= 4096 && SW * PR_NCH_MAX <= U4 * 16, "chunk entries: 12-bit index, wave mask");
+    constexpr float MRG = 2.44140625e-4f;                       // 2^-12
+    __shared__ __align__(16) uint4 ldsA[U4];
+    __shared__ __align__(16) uint4 ldsB[U4];                    // between sweeps: need flags
+    __shared__ uint16_t seq[PR_NCH_MAX];
+    __shared__ int nseq;
+    const int bi = xcd_block(nblk);
+    if (bi >= nblk) return;
+    const Blk b = blk[bi];
+    const Frag &Fq = frag[b.frag];
+    if (Fq.partner < 0) return;
+    const int nq = min(fb_cnt[b.frag], lst_cap(Fq));
+    if (b.start >= nq) return;
+    const Frag &Fc = frag[Fq.partner];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int swz = lds_swz(col);
+    const int nch = (Fc.n + CROWS - 1) / CROWS;
+    const bool prune = nch <= PR_NCH_MAX;
+
+    // query operands [y_hi, 1, 1], n_i = |yh_i|^2 over the 30 coordinates, thresholds
+    bf16x8 Bh[SQB];
+    float nq2[SQB], th[SQB];
+    bool live[SQB];
+    const int qw = b.start + wv * SQB * 16;
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) {
+        const int slot = qw + 16 * k + col;
+        uint4 wh = make_uint4(0, 0, 0, 0);
+        float t = -INFINITY;
+        if (slot < nq) {
+            const int q = rinv[Fq.off + fb_row[Fq.off + slot]];
+            wh = *(const uint4 *)(pk + (Fq.pk_off + q) * PK + 8 * grp);
+            t = thr[Fq.off + slot];
+        }
+        const uint32_t w32[4] = {wh.x, wh.y, wh.z, wh.w};
+        float p2 = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = __uint_as_float((e & 1) ? (w32[e >> 1] & 0xFFFF0000u) : (w32[e >> 1] << 16));
+            if (grp < 3 || e < 6) p2 = fmaf(x, x, p2);
+        }
+        p2 += __shfl_xor(p2, 16, 64);
+        p2 += __shfl_xor(p2, 32, 64);
+        nq2[k] = p2;
+        live[k] = t > -INFINITY;                              // also false past the list
+        th[k] = live[k] ? t : INFINITY;                       // a row outside collects nothing
+        if (grp == 3) wh.w = 0x3f803f80u;                     // slots 30, 31 = 1.0
+        Bh[k] = __builtin_bit_cast(bf16x8, wh);
+    }
+
+    constexpr int PER = U4 / (SW * 64);
+    const uint4 *src = (const uint4 *)(pk + Fc.pk_off * PK);
+    const int64_t cb = cent_base(Fc, Fq.partner);
+    const uint4 *csrc = (const uint4 *)(cpk + cb * PK);
+    auto stage = [&](uint4 *dst, const uint4 *from) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int base = u * SW * 64 + wv * 64;
+            __builtin_amdgcn_global_load_lds((const void *)(from + lds_slot(base + lane)),
+                                             (__attribute__((address_space(3))) void *)(dst + base), 16, 0, 0);
+        }
+    };
+    auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    f32x4 prev[SQB];
+    int prev_tile = -1;
+    auto epilogue = [&](const f32x4 *accs, int tile) {
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) {
+            const f32x4 acc = accs[k];
+            const bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
+            if (hit) {                                        // rare: near-ties of uncertified rows
+                const int64_t slot = lst_base(Fq, b.frag) + qw + 16 * k + col;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (acc[e] >= th[k]) {
+                        const int pos = atomicAdd(&lst_cnt[slot], 1);
+                        if (pos < LCAP) lst[slot * LCAP + pos] = tile * 16 + 4 * grp + e;
+                    }
+            }
+        }
+    };
+    auto cid = [&](int c) { return prune ? (int)(seq[c] & 0xFFF) : c; };
+    auto swept_by_me = [&](int c) { return !prune || ((seq[c] >> (12 + wv)) & 1); };
+    auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) {
+        if (c + 1 < len) stage(D, src + (int64_t)cid(c + 1) * U4);
+        if (!swept_by_me(c)) {                                    // wave-uniform
+            wait_copies();
+            __syncthreads();
+            return;
+        }
+        const int tbase = cid(c) * CH;
+        uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
+#pragma unroll 2
+        for (int t = 0; t < CH; ++t) {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, nh);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, nl);
+            if (t + 1 < CH) {
+                const uint4 *rowp = L + ((t + 1) * 16 + col) * 8;
+                nh = rowp[grp ^ swz];
+                nl = rowp[(4 + grp) ^ swz];
+            }
+            f32x4 accs[SQB];
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
+            if (prev_tile >= 0) epilogue(prev, prev_tile);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
+            prev_tile = tbase + t;
+        }
+        wait_copies();
+        __syncthreads();
+    };
+    auto sweep = [&](int len) {
+        if (len <= 0) return;
+        stage(ldsA, src + (int64_t)cid(0) * U4);
+        wait_copies();
+        __syncthreads();
+        for (int c = 0; c < len; c += 2) {
+            chunk(ldsA, ldsB, c, len);
+            if (c + 1 < len) chunk(ldsB, ldsA, c + 1, len);
+        }
+        if (prev_tile >= 0) epilogue(prev, prev_tile);
+        prev_tile = -1;
+    };
+    if (!prune) {
+        sweep(nch);
+        return;
+    }
+    // need[w][k] = 1: some query of wavefront w needs chunk k
+    uint8_t *need = (uint8_t *)ldsB;
+    uint8_t *mine = need + wv * PR_NCH_MAX;
+    for (int k = threadIdx.x; k < SW * PR_NCH_MAX; k += SW * 64) need[k] = 0;
+    __syncthreads();
+    const int ncc = (nch + CROWS - 1) / CROWS;
+    for (int cc = 0; cc < ncc; ++cc) {
+        stage(ldsA, csrc + (int64_t)cc * U4);
+        wait_copies();
+        __syncthreads();
+        for (int t = 0; t < CH; ++t) {
+            const uint4 *rowp = ldsA + (t * 16 + col) * 8;
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
+            f32x4 accs[SQB];
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
+            const int kc0 = cc * CROWS + t * 16 + 4 * grp;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kc = kc0 + e;
+                bool nd_any = false;
+                if (kc < nch) {
+                    const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
+#pragma unroll
+                    for (int k = 0; k < SQB; ++k) {
+                        if (!live[k] || st.x < 0.f) continue;        // no query or empty chunk
+                        const float g2 = nq2[k] - 2.0f * accs[k][e] - MRG * (nq2[k] + st.w);
+                        const float Lb = fmaxf(sqrtf(fmaxf(g2, 0.f)) - st.x, 0.f);
+                        const float U = 0.5f * nq2[k] * (1.0f + 1.0e-6f) - 0.5f * Lb * Lb * (1.0f - 1.0e-6f) + st.y +
+                                        MRG * (nq2[k] + st.z);
+                        nd_any |= U >= th[k];
+                    }
+                }
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(nd_any);
+                if (col == 0 && ((bal >> (16 * grp)) & 0xFFFFull)) mine[kc] = 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (wv == 0) {
+        int cnt = 0;
+        for (int base = 0; base < nch; base += 64) {
+            const int k = base + lane;
+            uint32_t wm = 0;
+            if (k < nch)
+                for (int w = 0; w < SW; ++w) wm |= (need[w * PR_NCH_MAX + k] == 1 ? 1u : 0u) << w;
+            const bool f = wm != 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(f);
+            if (f) seq[cnt + (int)lanes_below_w(m)] = (uint16_t)(k | (wm << 12));
+            cnt += __popcll(m);
+        }
+        if (lane == 0) nseq = cnt;
+    }
+    __syncthreads();
+    sweep(nseq);
+}
+
+// Uncertified rows of a fragment in packed-row order: mark their packed rows
+// (mark starts zeroed), a scan gives each its slot.  A fragment whose list
+// overflowed keeps the arrival order (its rows past the capacity are already
+// on the float32 rescan list).  The list re-rank's result does not depend on
+// the order.
+__global__ void __launch_bounds__(256) k_fb_mark(const Frag *frag, const Blk *blk, const int32_t *fb_row,
+                                                 const int32_t *fb_cnt, const int32_t *rinv, int32_t *mark) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    const int k = b.start + threadIdx.x;
+    const int cnt = fb_cnt[b.frag];
+    if (F.partner < 0 || k >= F.n || k >= cnt || cnt > lst_cap(F)) return;
+    mark[F.off + rinv[F.off + fb_row[F.off + k]]] = 1;
+}
+
+__global__ void __launch_bounds__(256) k_fb_order(const Frag *frag, const Blk *blk, const int32_t *fb_row,
+                                                  const float *thr, const int32_t *fb_cnt, const int32_t *rinv,
+                                                  const int32_t *lpos, int32_t *fb_row2, float *thr2) {
+    const Blk b = blk[blockIdx.x];
+    const Frag &F = frag[b.frag];
+    const int k = b.start + threadIdx.x;
+    const int cnt = fb_cnt[b.frag];
+    if (F.partner < 0 || k >= F.n || k >= cnt) return;
+    const int32_t i = fb_row[F.off + k];
+    const int dst = cnt <= lst_cap(F) ? lpos[F.off + rinv[F.off + i]] - lpos[F.off] : k;
+    fb_row2[F.off + dst] = i;
+    thr2[F.off + dst] = thr[F.off + k];
+}
+
 // 32x32 tiles: 32x32x16 MFMAs (two per K = 32).  Lane (col, h) holds query col
 // and, of every 32-row tile, candidate rows 8 i + 4 h + j (i, j < 4): one lane
 // half sees 16 of the tile's rows, so the epilogue costs 12 VALU operations
@@ -1414,10 +1665,15 @@ static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScr
                           hipStream_t s) {
     const int32_t *perm = S.perm, *rinv = S.rinv;
     if constexpr (T == 16) {
-        if (COLLECT)
+        if constexpr (COLLECT && PRUNE != 0)
+            hipLaunchKernelGGL((k_screen_prc<SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
+                               (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, (const uint16_t *)S.cpk,
+                               (const float4 *)S.cst, rinv, (const int32_t *)S.fb_row2, (const int32_t *)S.fb_cnt,
+                               (const float *)S.thr2, S.lst, S.lst_cnt);
+        else if constexpr (COLLECT)
             hipLaunchKernelGGL((k_screen<true, SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
                                (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, nullptr, nullptr,
-                               nullptr, (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr,
+                               nullptr, (const int32_t *)S.fb_row2, (const int32_t *)S.fb_cnt, (const float *)S.thr2,
                                S.lst, S.lst_cnt, nullptr);
         else if constexpr (PRUNE != 0)
             hipLaunchKernelGGL((k_screen_pr<SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s, (const Frag *)g.frag,
@@ -1431,7 +1687,7 @@ static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScr
         if (COLLECT)
             hipLaunchKernelGGL((k_screen32<true, SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s,
                                (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, nullptr, nullptr,
-                               nullptr, (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const float *)S.thr,
+                               nullptr, (const int32_t *)S.fb_row2, (const int32_t *)S.fb_cnt, (const float *)S.thr2,
                                S.lst, S.lst_cnt, nullptr);
         else
             hipLaunchKernelGGL((k_screen32<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
@@ -1512,10 +1768,18 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
                            (const float *)S.v2, (const float *)S.v1, m.nn, m.dist, S.fb_row, S.thr, S.fb_cnt, S.full_row, S.full_frag,
                            S.full_cnt, ps, g.nblk256);
     tmark("rerank", s);
+    // the uncertified rows of each fragment in packed-row order
+    if ((e = fill<int32_t>(S.lmark, 0, g.ntot, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fb_mark, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)S.fb_row, (const int32_t *)S.fb_cnt, (const int32_t *)S.rinv, S.lmark);
+    if ((e = exclusive_scan_i32(S.lmark, S.lpos, g.ntot, S.stmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fb_order, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
+                       (const int32_t *)S.fb_row, (const float *)S.thr, (const int32_t *)S.fb_cnt,
+                       (const int32_t *)S.rinv, (const int32_t *)S.lpos, S.fb_row2, S.thr2);
     if ((e = launch_screen(true, shape, g, d.pk, S, ps, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rerank_list, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const float *)d.F, (const int32_t *)d.valid, (const int32_t *)S.fb_row,
-                       (const int32_t *)S.fb_cnt, (const float *)S.thr, (const int32_t *)S.lst,
+                       (const float *)d.F, (const int32_t *)d.valid, (const int32_t *)S.fb_row2,
+                       (const int32_t *)S.fb_cnt, (const float *)S.thr2, (const int32_t *)S.lst,
                        (const int32_t *)S.lst_cnt, (const int32_t *)S.perm, m.nn, m.dist, S.full_row, S.full_frag,
                        S.full_cnt);
     tmark("collect", s);
