@@ -216,21 +216,21 @@ __global__ void __launch_bounds__(256) k_desc_mean(const Frag *frag, int nfrag, 
 
 // Point i of a fragment goes to packed row rinv[off + i]; thread t < n takes
 // point t (rows read in order, whole 128-byte rows written), a thread in
-// [n, padded n) writes padding row t.  yq stays indexed by point.
+// [n, padded n) writes padding row t.  yq stays indexed by point.  The bf16
+// halves are packed two to a word as they are made, and the pair's largest
+// projection error takes one atomic per wavefront.
 __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
                                               float *mean, const int32_t *rinv, uint16_t *pk, float4 *yq) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
     const int t = b.start + threadIdx.x;
-    int npad = (Fr.n + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS;
-    if (t >= npad) return;
+    const int npad = (Fr.n + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS;
+    const bool active = t < npad;
     const int i = t;
-    const int r = t < Fr.n ? rinv[Fr.off + t] : t;
-    int64_t row = Fr.pk_off + r;
-    uint16_t hi[32], lo[32];
+    uint32_t hw[16], lw[16];                                  // bf16 pairs: hi slots 0-31, lo slots 0-31
     float n2 = 0.f, dd = 0.f, delta = 0.f;
     double dy = 0.0;
-    bool v = t < Fr.n && valid[Fr.off + i];
+    const bool v = t < Fr.n && valid[Fr.off + i];
     if (v) {
         const float *x = F + (Fr.off + i) * FD;
         const float *m = mean + 32 * (b.frag >> 1);
@@ -244,15 +244,17 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
         for (int c = 0; c < 30; ++c) {
             h[c] -= m[c];
             n2 = fmaf(h[c], h[c], n2);
-            hi[c] = f2bf(h[c]);
-            const float d = h[c] - bf2f(hi[c]);              // exact
-            lo[c] = f2bf(d);
+            const uint16_t hc = f2bf(h[c]);
+            const float d = h[c] - bf2f(hc);                 // exact
+            const uint16_t lc = f2bf(d);
             dd = fmaf(d, d, dd);
             dy += (double)d * (double)h[c];
+            if (c & 1) { hw[c >> 1] |= (uint32_t)hc << 16; lw[c >> 1] |= (uint32_t)lc << 16; }
+            else { hw[c >> 1] = hc; lw[c >> 1] = lc; }
         }
-        float cc = -0.5f * n2;
-        hi[30] = f2bf(cc);
-        hi[31] = f2bf(cc - bf2f(hi[30]));
+        const float cc = -0.5f * n2;
+        const uint16_t c0 = f2bf(cc);
+        hw[15] = c0 | ((uint32_t)f2bf(cc - bf2f(c0)) << 16);
         // projection error: |y - y*| with y* the FP64 Helmert projection of the same float
         // descriptor minus the same centre (rounded up); the certificate widens by it
         double e2 = 0.0;
@@ -268,26 +270,24 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
             }
         }
         delta = (float)(sqrt(e2) * (1.0 + 1e-6)) + 1e-15f;
-        atomicMax((unsigned int *)(mean + 32 * (b.frag >> 1) + 30 + (b.frag & 1)), __float_as_uint(delta));
     } else {
 #pragma unroll
-        for (int c = 0; c < 30; ++c) { hi[c] = 0; lo[c] = 0; }
-        hi[30] = f2bf(-1.0e30f);
-        hi[31] = 0;
+        for (int w = 0; w < 15; ++w) { hw[w] = 0; lw[w] = 0; }
+        hw[15] = f2bf(-1.0e30f);
     }
-    lo[30] = 0;
-    lo[31] = 0;
-    uint4 *dst = (uint4 *)(pk + row * PK);
+    lw[15] = 0;
+    // the pair's largest projection error (non-negative floats order as their bits)
+    float dm = delta;
+    for (int o = 32; o > 0; o >>= 1) dm = fmaxf(dm, __shfl_xor(dm, o, 64));
+    if ((threadIdx.x & 63) == 0 && dm > 0.f)
+        atomicMax((unsigned int *)(mean + 32 * (b.frag >> 1) + 30 + (b.frag & 1)), __float_as_uint(dm));
+    if (!active) return;
+    const int r = t < Fr.n ? rinv[Fr.off + t] : t;
+    uint4 *dst = (uint4 *)(pk + (Fr.pk_off + r) * PK);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const uint16_t *o = q < 4 ? hi + 8 * q : lo + 8 * (q - 4);
-        uint4 w;
-        w.x = o[0] | ((uint32_t)o[1] << 16);
-        w.y = o[2] | ((uint32_t)o[3] << 16);
-        w.z = o[4] | ((uint32_t)o[5] << 16);
-        w.w = o[6] | ((uint32_t)o[7] << 16);
-        dst[q] = w;
-    }
+    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(hw[4 * q], hw[4 * q + 1], hw[4 * q + 2], hw[4 * q + 3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[4 + q] = make_uint4(lw[4 * q], lw[4 * q + 1], lw[4 * q + 2], lw[4 * q + 3]);
     if (t < Fr.n) yq[Fr.pk_off + i] = make_float4(n2, (float)dy, sqrtf(dd) * 1.0001f, delta);
 }
 
@@ -447,14 +447,14 @@ __global__ void __launch_bounds__(256) k_rinv(const Frag *frag, const Blk *blk, 
 // max |y~_j|^2 + max h_j, and |mu~|^2.  A chunk without valid rows gets
 // radius -1 and a centroid that no query can approach.  The last chunk's
 // wavefront also writes the padding centroid rows.
-__global__ void __launch_bounds__(256) k_chunk_stats(const Frag *frag, const Blk *blk, const uint16_t *pk,
+__global__ void __launch_bounds__(128) k_chunk_stats(const Frag *frag, const Blk *blk, const uint16_t *pk,
                                                      uint16_t *cpk, float4 *cst) {
     const Blk b = blk[blockIdx.x];
     const Frag &Fr = frag[b.frag];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nch = (Fr.n + PAD_ROWS - 1) / PAD_ROWS;
-    const int k = b.start / PAD_ROWS + wv;                 // 256-point block: chunks start/128 + {0, 1}
-    if (wv >= 2 || k >= nch) return;
+    const int k = b.start / PAD_ROWS + wv;                 // 256-point block, two wavefronts: chunks start/128 + {0, 1}
+    if (k >= nch) return;
     const int64_t cb = cent_base(Fr, b.frag);
     // one row (lane + 64 u of the chunk): y~ = hi + lo, h = -(c_hi + c_lo), valid
     auto load = [&](int u, float *y, float &h) {
@@ -1750,7 +1750,7 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     hipLaunchKernelGGL(k_pack, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const float *)d.F, (const int32_t *)d.valid, S.mean, (const int32_t *)S.rinv, d.pk, S.yq);
     if (SCREEN_SHAPES[shape].prune)
-        hipLaunchKernelGGL(k_chunk_stats, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag,
+        hipLaunchKernelGGL(k_chunk_stats, dim3(g.nblk256), dim3(128), 0, s, (const Frag *)g.frag,
                            (const Blk *)g.blk256, (const uint16_t *)d.pk, S.cpk, S.cst);
     tmark("pack", s);
     if ((e = launch_screen(false, shape, g, d.pk, S, ps, s)) != hipSuccess) return e;
