@@ -754,9 +754,11 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 // g_ik^2 = n_i - 2 tc_ik - m_ik, and m_ik, acc_ik margins of 2^-12 of the
 // magnitudes involved (float32 accumulation of 64 products errs by ~2^-18 of
 // them).  A block
-//  1. screens its 256 queries against every centroid, and sweeps the PR_K
-//     chunks whose centroids come nearest to any live query;
-//  2. screens the centroids again: a query needs chunk k unless the bound
+//  1. sweeps PR_K seed chunks: the partner chunks around the block's median
+//     descriptor-space key (both fragments' keys come from the pair's
+//     principal directions, so these rows are near the block's queries; any
+//     seed set is correct, since step 2 bounds every chunk);
+//  2. screens its queries against every centroid: a query needs chunk k unless the bound
 //     stays below its best screened score so far minus a margin (four times
 //     the certificate's error estimate), and the bound of a chunk a query does
 //     not need is folded into its second-best tile maximum, so the certificate
@@ -769,16 +771,16 @@ constexpr int PR_NCH_MAX = 4096;      // chunks one block can track (fragments u
 template <int SW, int SQB, int CH>
 __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3))) k_screen_pr(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk,
                                                        const uint16_t *cpk, const float4 *cst, const int32_t *perm,
-                                                       int32_t *c1_out, float *v2_out, float *v1_out, PairState *ps) {
+                                                       int32_t *c1_out, float *v2_out, float *v1_out, PairState *ps,
+                                                       const uint64_t *skey) {
     static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS, "pruned screen shape");
     constexpr int CROWS = CH * 16;
     constexpr int U4 = CROWS * PK / 8;
     static_assert(SW <= 4 && PR_NCH_MAX <= 4096 && SW * PR_NCH_MAX <= U4 * 16, "chunk entries: 12-bit index, wave mask");
     constexpr float MRG = 2.44140625e-4f;                       // 2^-12
     __shared__ __align__(16) uint4 ldsA[U4];
-    __shared__ __align__(16) uint4 ldsB[U4];                    // between sweeps: chunk keys, then need flags
+    __shared__ __align__(16) uint4 ldsB[U4];                    // between sweeps: need flags
     __shared__ uint16_t seq[PR_NCH_MAX];                        // chunks of the current sweep
-    __shared__ float redv[SW];
     __shared__ int redi[SW];
     __shared__ int nseq, nwsw;
     // XCD-aware order: consecutive blocks hold neighbouring queries in descriptor
@@ -936,47 +938,24 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     if (!prune) {
         sweep(nch);
     } else {
-        // 1. block-minimum distance bound per chunk, then the PR_K nearest chunks
-        float *keys = (float *)ldsB;
-        for (int k = threadIdx.x; k < nch; k += SW * 64) keys[k] = INFINITY;
+        // 1. seeds: the PR_K partner chunks around the block's median descriptor-space key
+        //    (both fragments' keys come from the pair's principal directions)
+        const uint64_t KM = (1ull << 25) - 1ull;
+        const uint64_t km = skey[Fq.off + min(b.start + 128, Fq.n - 1)] & KM;
+        int first = nch;                                   // first chunk whose first row's key is >= km
+        for (int c = threadIdx.x; c < nch; c += SW * 64)
+            if ((skey[Fc.off + (int64_t)c * CROWS] & KM) >= km) first = min(first, c);
+        for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+        if (lane == 0) redi[wv] = first;
         __syncthreads();
-        cent_pass([&](const f32x4 *accs, int kc0) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kc = kc0 + e;
-                const float mc2 = kc < nch ? cst[cb + kc].w : 0.f;
-                float m = INFINITY;
-#pragma unroll
-                for (int k = 0; k < SQB; ++k)
-                    if (live[k]) m = fminf(m, nq2[k] - 2.0f * accs[k][e] - MRG * (nq2[k] + mc2));
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) m = fminf(m, __shfl_xor(m, o, 64));
-                if (col == 0 && kc < nch && m < INFINITY) atomicMin((int *)&keys[kc], __float_as_int(fmaxf(m, 0.f)));
-            }
-        });
         const int k1 = min(PR_K, nch);
-        for (int r = 0; r < k1; ++r) {
-            float bv = INFINITY;
-            int bk = 0x7fffffff;
-            for (int k = threadIdx.x; k < nch; k += SW * 64) {
-                const float v = keys[k];
-                if (v < bv || (v == bv && k < bk)) { bv = v; bk = k; }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                const float ov = __shfl_xor(bv, o, 64);
-                const int ok = __shfl_xor(bk, o, 64);
-                if (ov < bv || (ov == bv && ok < bk)) { bv = ov; bk = ok; }
-            }
-            if (lane == 0) { redv[wv] = bv; redi[wv] = bk; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                for (int w = 1; w < SW; ++w)
-                    if (redv[w] < bv || (redv[w] == bv && redi[w] < bk)) { bv = redv[w]; bk = redi[w]; }
-                seq[r] = (uint16_t)(bk | (((1u << SW) - 1u) << 12));  // every wavefront sweeps it
-                keys[bk] = __uint_as_float(0x7fffffffu);               // NaN: never the minimum again
-            }
-            __syncthreads();
+        if (threadIdx.x == 0) {
+            int f = redi[0];
+            for (int w = 1; w < SW; ++w) f = min(f, redi[w]);
+            int c0 = max(0, min(f - PR_K / 2, nch - k1));
+            for (int r = 0; r < k1; ++r) seq[r] = (uint16_t)((c0 + r) | (((1u << SW) - 1u) << 12));
         }
+        __syncthreads();
         sweep(k1);
         // 2. which chunks do the queries still need?
         float thn[SQB];
@@ -1678,7 +1657,7 @@ static void screen_launch(const GridBufs &g, const uint16_t *pk, const ScreenScr
         else if constexpr (PRUNE != 0)
             hipLaunchKernelGGL((k_screen_pr<SW, SQB, CH>), dim3(xcd_grid(g.nblk256)), dim3(SW * 64), 0, s, (const Frag *)g.frag,
                                (const Blk *)g.blk256, g.nblk256, pk, (const uint16_t *)S.cpk, (const float4 *)S.cst,
-                               perm, S.c1, S.v2, S.v1, ps);
+                               perm, S.c1, S.v2, S.v1, ps, (const uint64_t *)S.key1);
         else
             hipLaunchKernelGGL((k_screen<false, SW, SQB, CH>), dim3(g.nblk256), dim3(SW * 64), 0, s,
                                (const Frag *)g.frag, (const Blk *)g.blk256, g.nblk256, pk, perm, rinv, S.c1, S.v2, S.v1,
