@@ -968,10 +968,16 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
             const float dl = 7.8125e-3f * sqrtf(nq2[k] * D) + MRG * (nq2[k] + D) + 1.0e-7f;
             thn[k] = bq - dl;                                       // -inf when no row was screened
         }
+        float ga[SQB], ub[SQB];                                     // the bound's per-query terms
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) {
+            ga[k] = nq2[k] - MRG * nq2[k];
+            ub[k] = 0.5f * nq2[k] * (1.0f + 1.0e-6f) + MRG * nq2[k];
+        }
         // need[w][k]: 0 wave w skips chunk k, 1 it sweeps it, 2 already swept
         uint8_t *need = (uint8_t *)ldsB;
         uint8_t *mine = need + wv * PR_NCH_MAX;
-        for (int k = threadIdx.x; k < SW * PR_NCH_MAX; k += SW * 64) need[k] = 0;
+        for (int k = threadIdx.x; k < SW * nch; k += SW * 64) need[(k / nch) * PR_NCH_MAX + k % nch] = 0;
         __syncthreads();
         if (threadIdx.x < k1)
             for (int w = 0; w < SW; ++w) need[w * PR_NCH_MAX + (seq[threadIdx.x] & 0xFFF)] = 2;
@@ -984,13 +990,16 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
                 if (kc < nch) {
                     const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
                     const bool done = mine[kc] == 2;
+                    const float cw = MRG * st.w, cy = st.y + MRG * st.z;
 #pragma unroll
                     for (int k = 0; k < SQB; ++k) {
                         if (!live[k] || st.x < 0.f) continue;        // dead query or empty chunk
-                        const float g2 = nq2[k] - 2.0f * accs[k][e] - MRG * (nq2[k] + st.w);
+                        // g2 = n - 2 tc - MRG (n + |mu|^2), U = n (1 + 1e-6) / 2 - (1 - 1e-6) L^2 / 2 + delta
+                        // + MRG (n + st.z), the query's terms hoisted (a few ulps of rearrangement, far inside
+                        // the 1e-6 factors and the 2^-12 margins)
+                        const float g2 = fmaf(-2.0f, accs[k][e], ga[k] - cw);
                         const float L = fmaxf(sqrtf(fmaxf(g2, 0.f)) - st.x, 0.f);
-                        const float U = 0.5f * nq2[k] * (1.0f + 1.0e-6f) - 0.5f * L * L * (1.0f - 1.0e-6f) + st.y +
-                                        MRG * (nq2[k] + st.z);
+                        const float U = fmaf(-0.5f * (1.0f - 1.0e-6f), L * L, ub[k] + cy);
                         const bool nd = U >= thn[k];
                         nd_any |= nd && !done;
                         if (!nd && !done) sf[k] = fmaxf(sf[k], U);
@@ -1195,10 +1204,16 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
         sweep(nch);
         return;
     }
+    float ga[SQB], ub[SQB];                                         // the bound's per-query terms
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) {
+        ga[k] = nq2[k] - MRG * nq2[k];
+        ub[k] = 0.5f * nq2[k] * (1.0f + 1.0e-6f) + MRG * nq2[k];
+    }
     // need[w][k] = 1: some query of wavefront w needs chunk k
     uint8_t *need = (uint8_t *)ldsB;
     uint8_t *mine = need + wv * PR_NCH_MAX;
-    for (int k = threadIdx.x; k < SW * PR_NCH_MAX; k += SW * 64) need[k] = 0;
+    for (int k = threadIdx.x; k < SW * nch; k += SW * 64) need[(k / nch) * PR_NCH_MAX + k % nch] = 0;
     __syncthreads();
     const int ncc = (nch + CROWS - 1) / CROWS;
     for (int cc = 0; cc < ncc; ++cc) {
@@ -1221,13 +1236,13 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
                 bool nd_any = false;
                 if (kc < nch) {
                     const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
+                    const float cw = MRG * st.w, cy = st.y + MRG * st.z;
 #pragma unroll
                     for (int k = 0; k < SQB; ++k) {
                         if (!live[k] || st.x < 0.f) continue;        // no query or empty chunk
-                        const float g2 = nq2[k] - 2.0f * accs[k][e] - MRG * (nq2[k] + st.w);
+                        const float g2 = fmaf(-2.0f, accs[k][e], ga[k] - cw);   // the pruned screen's bound
                         const float Lb = fmaxf(sqrtf(fmaxf(g2, 0.f)) - st.x, 0.f);
-                        const float U = 0.5f * nq2[k] * (1.0f + 1.0e-6f) - 0.5f * Lb * Lb * (1.0f - 1.0e-6f) + st.y +
-                                        MRG * (nq2[k] + st.z);
+                        const float U = fmaf(-0.5f * (1.0f - 1.0e-6f), Lb * Lb, ub[k] + cy);
                         nd_any |= U >= th[k];
                     }
                 }
