@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
                                                        const uint16_t *cpk, const float4 *cst, const int32_t *perm,
                                                        int32_t *c1_out, float *v2_out, float *v1_out, PairState *ps,
                                                        const uint64_t *skey) {
-    static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS, "pruned screen shape");
+    static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS && CH % 2 == 0, "pruned screen shape: tiles in pairs");
     constexpr int CROWS = CH * 16;
     constexpr int U4 = CROWS * PK / 8;
     static_assert(SW <= 4 && PR_NCH_MAX <= 4096 && SW * PR_NCH_MAX <= U4 * 16, "chunk entries: 12-bit index, wave mask");
@@ -844,9 +844,14 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     };
     auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 ninf = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    // the previous tile's scores, folded in while the next tile's MFMAs run;
+    // -inf scores (before the first tile) change nothing
     f32x4 prev[SQB];
-    int prev_tile = -1;
-    auto epilogue = [&](const f32x4 *accs, int tile) {
+    int prev_tile = 0;
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) prev[k] = ninf;
+    auto epilogue = [&](const f32x4 *accs, int tile) __attribute__((always_inline)) {
         bool up[SQB];
         bool any = false;
 #pragma unroll
@@ -866,38 +871,46 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     auto cid = [&](int c) { return prune ? (int)(seq[c] & 0xFFF) : c; };
     auto swept_by_me = [&](int c) { return !prune || ((seq[c] >> (12 + wv)) & 1); };
     // one chunk of a sweep: start copying the next chunk into D, sweep the tiles of L
-    auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) {
+    auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) __attribute__((always_inline)) {
         if (c + 1 < len) stage(D, src + (int64_t)cid(c + 1) * U4);
         if (!swept_by_me(c)) {                                    // wave-uniform
             wait_copies();
             __syncthreads();
             return;
         }
-        const int tbase = cid(c) * CH;
-        uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
-#pragma unroll 2
-        for (int t = 0; t < CH; ++t) {
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, nh);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, nl);
-            if (t + 1 < CH) {
-                const uint4 *rowp = L + ((t + 1) * 16 + col) * 8;
-                nh = rowp[grp ^ swz];
-                nl = rowp[(4 + grp) ^ swz];
-            }
+        const int tbase = __builtin_amdgcn_readfirstlane(cid(c)) * CH;   // wave-uniform
+        // one tile: its MFMAs, then the previous tile's epilogue while they run
+        auto tile = [&](const uint4 &h, const uint4 &l, int t) __attribute__((always_inline)) {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, h);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, l);
             f32x4 accs[SQB];
 #pragma unroll
             for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
-            if (prev_tile >= 0) epilogue(prev, prev_tile);
+            epilogue(prev, prev_tile);
 #pragma unroll
             for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
             prev_tile = tbase + t;
+        };
+        // tiles in pairs with two operand register sets: the next tile's
+        // operands are read from LDS while the current tile's MFMAs run
+        const uint4 *rw = L + col * 8;
+        uint4 h0 = rw[grp ^ swz], l0 = rw[(4 + grp) ^ swz];
+#pragma unroll 1
+        for (int t = 0; t < CH; t += 2) {
+            const uint4 h1 = rw[(t + 1) * 128 + (grp ^ swz)], l1 = rw[(t + 1) * 128 + ((4 + grp) ^ swz)];
+            tile(h0, l0, t);
+            if (t + 2 < CH) {
+                h0 = rw[(t + 2) * 128 + (grp ^ swz)];
+                l0 = rw[(t + 2) * 128 + ((4 + grp) ^ swz)];
+            }
+            tile(h1, l1, t + 1);
         }
         wait_copies();
         __syncthreads();
     };
-    auto sweep = [&](int len) {
+    auto sweep = [&](int len) __attribute__((always_inline)) {
         if (len <= 0) return;
         stage(ldsA, src + (int64_t)cid(0) * U4);
         wait_copies();
@@ -906,8 +919,9 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
             chunk(ldsA, ldsB, c, len);
             if (c + 1 < len) chunk(ldsB, ldsA, c + 1, len);
         }
-        if (prev_tile >= 0) epilogue(prev, prev_tile);
-        prev_tile = -1;
+        epilogue(prev, prev_tile);
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) prev[k] = ninf;
     };
     // screened scores of the block's queries against every centroid row, one
     // staged chunk of 128 centroids at a time (single buffered: ldsB holds the
@@ -1069,7 +1083,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
 k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, const uint16_t *cpk, const float4 *cst,
              const int32_t *rinv, const int32_t *fb_row, const int32_t *fb_cnt, const float *thr, int32_t *lst,
              int32_t *lst_cnt) {
-    static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS, "pruned screen shape");
+    static_assert(SW * SQB * 16 == 256 && CH * 16 == PAD_ROWS && CH % 2 == 0, "pruned screen shape: tiles in pairs");
     constexpr int CROWS = CH * 16;
     constexpr int U4 = CROWS * PK / 8;
     static_assert(SW <= 4 && PR_NCH_MAX <= 4096 && SW * PR_NCH_MAX <= U4 * 16, "chunk entries: 12-bit index, wave mask");
@@ -1137,14 +1151,19 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
     };
     auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 ninf = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    // the previous tile's scores, tested while the next tile's MFMAs run; -inf
+    // scores (before the first tile) reach no threshold
     f32x4 prev[SQB];
-    int prev_tile = -1;
-    auto epilogue = [&](const f32x4 *accs, int tile) {
+    int prev_tile = 0;
+#pragma unroll
+    for (int k = 0; k < SQB; ++k) prev[k] = ninf;
+    auto epilogue = [&](const f32x4 *accs, int tile) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < SQB; ++k) {
             const f32x4 acc = accs[k];
-            const bool hit = acc[0] >= th[k] || acc[1] >= th[k] || acc[2] >= th[k] || acc[3] >= th[k];
-            if (hit) {                                        // rare: near-ties of uncertified rows
+            const float tm = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
+            if (tm >= th[k]) {                                // rare: near-ties of uncertified rows
                 const int64_t slot = lst_base(Fq, b.frag) + qw + 16 * k + col;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
@@ -1157,38 +1176,44 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
     };
     auto cid = [&](int c) { return prune ? (int)(seq[c] & 0xFFF) : c; };
     auto swept_by_me = [&](int c) { return !prune || ((seq[c] >> (12 + wv)) & 1); };
-    auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) {
+    auto chunk = [&](const uint4 *L, uint4 *D, int c, int len) __attribute__((always_inline)) {
         if (c + 1 < len) stage(D, src + (int64_t)cid(c + 1) * U4);
         if (!swept_by_me(c)) {                                    // wave-uniform
             wait_copies();
             __syncthreads();
             return;
         }
-        const int tbase = cid(c) * CH;
-        uint4 nh = L[col * 8 + (grp ^ swz)], nl = L[col * 8 + ((4 + grp) ^ swz)];
-#pragma unroll 2
-        for (int t = 0; t < CH; ++t) {
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, nh);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, nl);
-            if (t + 1 < CH) {
-                const uint4 *rowp = L + ((t + 1) * 16 + col) * 8;
-                nh = rowp[grp ^ swz];
-                nl = rowp[(4 + grp) ^ swz];
-            }
+        const int tbase = __builtin_amdgcn_readfirstlane(cid(c)) * CH;   // wave-uniform
+        auto tile = [&](const uint4 &h, const uint4 &l, int t) __attribute__((always_inline)) {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, h);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, l);
             f32x4 accs[SQB];
 #pragma unroll
             for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
-            if (prev_tile >= 0) epilogue(prev, prev_tile);
+            epilogue(prev, prev_tile);
 #pragma unroll
             for (int k = 0; k < SQB; ++k) prev[k] = accs[k];
             prev_tile = tbase + t;
+        };
+        // tiles in pairs, two operand register sets (as in the pruned screen)
+        const uint4 *rw = L + col * 8;
+        uint4 h0 = rw[grp ^ swz], l0 = rw[(4 + grp) ^ swz];
+#pragma unroll 1
+        for (int t = 0; t < CH; t += 2) {
+            const uint4 h1 = rw[(t + 1) * 128 + (grp ^ swz)], l1 = rw[(t + 1) * 128 + ((4 + grp) ^ swz)];
+            tile(h0, l0, t);
+            if (t + 2 < CH) {
+                h0 = rw[(t + 2) * 128 + (grp ^ swz)];
+                l0 = rw[(t + 2) * 128 + ((4 + grp) ^ swz)];
+            }
+            tile(h1, l1, t + 1);
         }
         wait_copies();
         __syncthreads();
     };
-    auto sweep = [&](int len) {
+    auto sweep = [&](int len) __attribute__((always_inline)) {
         if (len <= 0) return;
         stage(ldsA, src + (int64_t)cid(0) * U4);
         wait_copies();
@@ -1197,8 +1222,9 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
             chunk(ldsA, ldsB, c, len);
             if (c + 1 < len) chunk(ldsB, ldsA, c + 1, len);
         }
-        if (prev_tile >= 0) epilogue(prev, prev_tile);
-        prev_tile = -1;
+        epilogue(prev, prev_tile);
+#pragma unroll
+        for (int k = 0; k < SQB; ++k) prev[k] = ninf;
     };
     if (!prune) {
         sweep(nch);
