@@ -753,7 +753,9 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 // with g_ik <= |yh_i - mu~_k| taken from the screened centroid score tc_ik as
 // g_ik^2 = n_i - 2 tc_ik - m_ik, and m_ik, acc_ik margins of 2^-12 of the
 // magnitudes involved (float32 accumulation of 64 products errs by ~2^-18 of
-// them).  A block
+// them).  g_ik is taken from the hardware square root scaled by SQ_LO, which
+// keeps it below the exact root (the instruction errs by about one ulp, the
+// scale removes sixteen), so the bound only loosens.  A block
 //  1. sweeps PR_K seed chunks: the partner chunks around the block's median
 //     descriptor-space key (both fragments' keys come from the pair's
 //     principal directions, so these rows are near the block's queries; any
@@ -766,6 +768,7 @@ __global__ void __launch_bounds__(SW * 64) k_screen(const Frag *frag, const Blk 
 //  3. sweeps the chunks some live query needs.
 // Rows with a 2^24 key (invalid descriptors) sort last in each fragment.
 constexpr int PR_K = 8;
+constexpr float SQ_LO = 1.0f - 1.9073486328125e-6f;    // 1 - 2^-19
 constexpr int PR_NCH_MAX = 4096;      // chunks one block can track (fragments up to 524288 rows); beyond: no pruning
 
 template <int SW, int SQB, int CH>
@@ -926,10 +929,16 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     // screened scores of the block's queries against every centroid row, one
     // staged chunk of 128 centroids at a time (single buffered: ldsB holds the
     // per-chunk state); fn(accs, first centroid of the lane's four)
+    // the chunk bounds of the staged centroids go to seq's storage (free
+    // during this pass); fn(accs, first centroid of the lane's four, their bounds)
+    float4 *sst = (float4 *)seq;
+    static_assert(sizeof(seq) >= CROWS * sizeof(float4), "centroid bounds staging");
     auto cent_pass = [&](auto &&fn) {
         const int ncc = (nch + CROWS - 1) / CROWS;
         for (int cc = 0; cc < ncc; ++cc) {
             stage(ldsA, csrc + (int64_t)cc * U4);
+            // slots past nch are padding of the fragment's centroid region: read, never used
+            if (threadIdx.x < CROWS) sst[threadIdx.x] = cst[cb + (int64_t)cc * CROWS + threadIdx.x];
             wait_copies();
             __syncthreads();
             for (int t = 0; t < CH; ++t) {
@@ -941,7 +950,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
                 for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Bh[k], zero, 0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < SQB; ++k) accs[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Bh[k], accs[k], 0, 0, 0);
-                fn(accs, cc * CROWS + t * 16 + 4 * grp);
+                fn(accs, cc * CROWS + t * 16 + 4 * grp, sst + t * 16 + 4 * grp);
             }
             __syncthreads();
         }
@@ -996,28 +1005,27 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
         if (threadIdx.x < k1)
             for (int w = 0; w < SW; ++w) need[w * PR_NCH_MAX + (seq[threadIdx.x] & 0xFFF)] = 2;
         __syncthreads();
-        cent_pass([&](const f32x4 *accs, int kc0) {
+        cent_pass([&](const f32x4 *accs, int kc0, const float4 *stl) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int kc = kc0 + e;
+                const float4 st = stl[e];                            // rho, delta, max |y|^2 + max h, |mu|^2
+                // a real, non-empty chunk not swept as a seed
+                const bool open = kc < nch && st.x >= 0.f && mine[kc] != 2;
+                const float cw = MRG * st.w, cy = st.y + MRG * st.z;
                 bool nd_any = false;
-                if (kc < nch) {
-                    const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
-                    const bool done = mine[kc] == 2;
-                    const float cw = MRG * st.w, cy = st.y + MRG * st.z;
 #pragma unroll
-                    for (int k = 0; k < SQB; ++k) {
-                        if (!live[k] || st.x < 0.f) continue;        // dead query or empty chunk
-                        // g2 = n - 2 tc - MRG (n + |mu|^2), U = n (1 + 1e-6) / 2 - (1 - 1e-6) L^2 / 2 + delta
-                        // + MRG (n + st.z), the query's terms hoisted (a few ulps of rearrangement, far inside
-                        // the 1e-6 factors and the 2^-12 margins)
-                        const float g2 = fmaf(-2.0f, accs[k][e], ga[k] - cw);
-                        const float L = fmaxf(sqrtf(fmaxf(g2, 0.f)) - st.x, 0.f);
-                        const float U = fmaf(-0.5f * (1.0f - 1.0e-6f), L * L, ub[k] + cy);
-                        const bool nd = U >= thn[k];
-                        nd_any |= nd && !done;
-                        if (!nd && !done) sf[k] = fmaxf(sf[k], U);
-                    }
+                for (int k = 0; k < SQB; ++k) {
+                    // g2 = n - 2 tc - MRG (n + |mu|^2), U = n (1 + 1e-6) / 2 - (1 - 1e-6) L^2 / 2 + delta
+                    // + MRG (n + st.z), the query's terms hoisted (a few ulps of rearrangement, far inside
+                    // the 1e-6 factors and the 2^-12 margins)
+                    const float g2 = fmaf(-2.0f, accs[k][e], ga[k] - cw);
+                    const float L = fmaxf(fmaf(__builtin_amdgcn_sqrtf(fmaxf(g2, 0.f)), SQ_LO, -st.x), 0.f);
+                    const float U = fmaf(-0.5f * (1.0f - 1.0e-6f), L * L, ub[k] + cy);
+                    const bool use = open && live[k];                // dead queries take no part
+                    const bool nd = U >= thn[k];
+                    nd_any |= use && nd;
+                    sf[k] = use && !nd ? fmaxf(sf[k], U) : sf[k];
                 }
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(nd_any);
                 if (col == 0 && ((bal >> (16 * grp)) & 0xFFFFull)) mine[kc] = 1;
@@ -1241,9 +1249,12 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
     uint8_t *mine = need + wv * PR_NCH_MAX;
     for (int k = threadIdx.x; k < SW * nch; k += SW * 64) need[(k / nch) * PR_NCH_MAX + k % nch] = 0;
     __syncthreads();
+    float4 *sst = (float4 *)seq;                                    // the staged centroids' bounds
+    static_assert(sizeof(seq) >= CROWS * sizeof(float4), "centroid bounds staging");
     const int ncc = (nch + CROWS - 1) / CROWS;
     for (int cc = 0; cc < ncc; ++cc) {
         stage(ldsA, csrc + (int64_t)cc * U4);
+        if (threadIdx.x < CROWS) sst[threadIdx.x] = cst[cb + (int64_t)cc * CROWS + threadIdx.x];
         wait_copies();
         __syncthreads();
         for (int t = 0; t < CH; ++t) {
@@ -1259,18 +1270,16 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int kc = kc0 + e;
+                const float4 st = sst[t * 16 + 4 * grp + e];         // rho, delta, max |y|^2 + max h, |mu|^2
+                const bool open = kc < nch && st.x >= 0.f;           // a real, non-empty chunk
+                const float cw = MRG * st.w, cy = st.y + MRG * st.z;
                 bool nd_any = false;
-                if (kc < nch) {
-                    const float4 st = cst[cb + kc];                  // rho, delta, max |y|^2 + max h, |mu|^2
-                    const float cw = MRG * st.w, cy = st.y + MRG * st.z;
 #pragma unroll
-                    for (int k = 0; k < SQB; ++k) {
-                        if (!live[k] || st.x < 0.f) continue;        // no query or empty chunk
-                        const float g2 = fmaf(-2.0f, accs[k][e], ga[k] - cw);   // the pruned screen's bound
-                        const float Lb = fmaxf(sqrtf(fmaxf(g2, 0.f)) - st.x, 0.f);
-                        const float U = fmaf(-0.5f * (1.0f - 1.0e-6f), Lb * Lb, ub[k] + cy);
-                        nd_any |= U >= th[k];
-                    }
+                for (int k = 0; k < SQB; ++k) {
+                    const float g2 = fmaf(-2.0f, accs[k][e], ga[k] - cw);   // the pruned screen's bound
+                    const float Lb = fmaxf(fmaf(__builtin_amdgcn_sqrtf(fmaxf(g2, 0.f)), SQ_LO, -st.x), 0.f);
+                    const float U = fmaf(-0.5f * (1.0f - 1.0e-6f), Lb * Lb, ub[k] + cy);
+                    nd_any |= open && live[k] && U >= th[k];          // no query: takes no part
                 }
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(nd_any);
                 if (col == 0 && ((bal >> (16 * grp)) & 0xFFFFull)) mine[kc] = 1;
