@@ -854,21 +854,26 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
     int prev_tile = 0;
 #pragma unroll
     for (int k = 0; k < SQB; ++k) prev[k] = ninf;
+    // a tile whose maxima stay at or below every second-best changes nothing
+    // (med3(v1, t, v2) = v2 for t <= v2 <= v1), so the update runs only when
+    // some lane's maximum passes its second-best
     auto epilogue = [&](const f32x4 *accs, int tile) __attribute__((always_inline)) {
-        bool up[SQB];
+        float tm[SQB];
         bool any = false;
 #pragma unroll
         for (int k = 0; k < SQB; ++k) {
             const f32x4 acc = accs[k];
-            const float tm = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
-            v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm, v2[k]);
-            up[k] = tm > v1[k];
-            any |= up[k];
-            v1[k] = __builtin_fmaxf(v1[k], tm);
+            tm[k] = __builtin_fmaxf(__builtin_fmaxf(acc[0], acc[1]), __builtin_fmaxf(acc[2], acc[3]));
+            any |= tm[k] > v2[k];
         }
         if (__builtin_amdgcn_ballot_w64(any)) {
 #pragma unroll
-            for (int k = 0; k < SQB; ++k) c1[k] = up[k] ? tile : c1[k];
+            for (int k = 0; k < SQB; ++k) {
+                const bool up = tm[k] > v1[k];
+                v2[k] = __builtin_amdgcn_fmed3f(v1[k], tm[k], v2[k]);
+                v1[k] = __builtin_fmaxf(v1[k], tm[k]);
+                c1[k] = up ? tile : c1[k];
+            }
         }
     };
     auto cid = [&](int c) { return prune ? (int)(seq[c] & 0xFFF) : c; };
