@@ -946,7 +946,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)
             if (threadIdx.x < CROWS) sst[threadIdx.x] = cst[cb + (int64_t)cc * CROWS + threadIdx.x];
             wait_copies();
             __syncthreads();
-            for (int t = 0; t < CH; ++t) {
+            for (int t = 0; t < CH && cc * CROWS + t * 16 < nch; ++t) {   // tiles holding centroids
                 const uint4 *rowp = ldsA + (t * 16 + col) * 8;
                 const bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
                 const bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
@@ -1262,7 +1262,7 @@ k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, con
         if (threadIdx.x < CROWS) sst[threadIdx.x] = cst[cb + (int64_t)cc * CROWS + threadIdx.x];
         wait_copies();
         __syncthreads();
-        for (int t = 0; t < CH; ++t) {
+        for (int t = 0; t < CH && cc * CROWS + t * 16 < nch; ++t) {   // tiles holding centroids
             const uint4 *rowp = ldsA + (t * 16 + col) * 8;
             const bf16x8 ah = __builtin_bit_cast(bf16x8, rowp[grp ^ swz]);
             const bf16x8 al = __builtin_bit_cast(bf16x8, rowp[(4 + grp) ^ swz]);
