@@ -467,8 +467,9 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 // covers 4 candidates of a run: lane (i, k) = (l % 16, l / 16) forms w for
 // point i and candidate j = c0 + k (0 unless j is within r_f of p_i, the
 // same FP64 test as the per-point stencil) and loads the counts of j for bins
-// i, i + 16, i + 32; three 16x16x4 f32 MFMAs add W (16 x 4) times C (4 x 48)
-// into the group's sums.  A group spanning several rows takes one pass per
+// 2i and 2i + 1 (one word of the row) and the row's last 16 bytes (bin 32, its
+// zero pad, the scale); three 16x16x4 f32 MFMAs add W (16 x 4) times C (4 x 48)
+// into the group's sums, the even bins in the first, the odd in the second.  A group spanning several rows takes one pass per
 // row, each with W masked to that row's points.  Only the float32 summation
 // order differs from a per-point loop.  Five wavefronts per SIMD (90 VGPRs,
 // no spill; four at the unconstrained 104) hide more of the candidate-row
@@ -525,18 +526,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
                     // Branch-free steps, four per iteration so that their loads are
                     // in flight together: a lane past the run's end reads the run's
                     // last candidate (always in bounds) and adds zero.
-                    struct Cand { float4 q; float sc; uint32_t u0, u1, u2; bool in; };
+                    struct Cand { float4 q; uint32_t w; uint4 t; bool in; };
                     auto fetch = [&](int32_t c0) {
                         const int32_t j = c0 + kk;
                         const int64_t jj = min(j, re - 1);
-                        const uint16_t *cj = (const uint16_t *)(spfh + jj * SPR);
                         Cand r;
                         r.in = j < re;
                         r.q = g.p[jj];
-                        r.sc = ((const float *)(spfh + jj * SPR))[4 * SPR - 1];
-                        r.u0 = cj[pi];
-                        r.u1 = cj[pi + 16];
-                        r.u2 = cj[pi == 0 ? 32 : 33];
+                        r.w = ((const uint32_t *)(spfh + jj * SPR))[pi];     // bins 2 pi, 2 pi + 1
+                        r.t = spfh[jj * SPR + SPR - 1];                       // bin 32 | pad, pad, pad, scale
                         return r;
                     };
                     auto step = [&](const Cand &cd) {
@@ -546,11 +544,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
                         // neighbour decision above needs FP64.  A distance below the
                         // smallest normal float (coincident-looking points) is clamped
                         // there, keeping the weight finite; it dominates the sum either way.
-                        const float wv = __builtin_amdgcn_rsqf(fmaxf((float)(hit ? d2 : 1.0), 1.17549435e-38f)) * cd.sc;
+                        const float wv =
+                            __builtin_amdgcn_rsqf(fmaxf((float)(hit ? d2 : 1.0), 1.17549435e-38f)) * __uint_as_float(cd.t.w);
                         const float w = hit ? wv : 0.f;
                         // counts need no mask: a lane past the run's end has w = 0, and
-                        // slot 33 (read by pi != 0 for bin pi + 32) is the rows' zero pad
-                        const float b0 = (float)cd.u0, b1 = (float)cd.u1, b2 = (float)cd.u2;
+                        // slot 33 (taken by pi != 0 for column pi of the third product) is the rows' zero pad
+                        const float b0 = (float)(cd.w & 0xffffu), b1 = (float)(cd.w >> 16);
+                        const float b2 = (float)(pi == 0 ? (cd.t.x & 0xffffu) : (cd.t.x >> 16));
                         acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0, acc0, 0, 0, 0);
                         acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1, acc1, 0, 0, 0);
                         acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b2, acc2, 0, 0, 0);
@@ -565,11 +565,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
                 }
             }
         }
-        // lane (i, k) holds the sums of points 4 k + r, bins i + 16 m (r < 4, m < 3)
+        // lane (i, k) holds the sums of points 4 k + r (r < 4), bins 2 i, 2 i + 1 and i + 32
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            red[wv][4 * kk + r][pi] = acc0[r];
-            red[wv][4 * kk + r][pi + 16] = acc1[r];
+            red[wv][4 * kk + r][2 * pi] = acc0[r];
+            red[wv][4 * kk + r][2 * pi + 1] = acc1[r];
             red[wv][4 * kk + r][pi + 32] = acc2[r];
         }
         wave_sync_lds();
