@@ -226,6 +226,8 @@ int plan_malloc(lsr_ctx *c, Plan *P, size_t bytes) {
     return LSR_OK;
 }
 
+// cells of a fragment's grid; at least n: the grid build keeps each point's arrival rank in its
+// cell in the ncells-long cursor array
 int64_t cells_for(int64_t n) { return 4 * n + 4096; }
 
 // Lay out and allocate a fragment-batch plan.  frags[f] are the inputs;

@@ -182,22 +182,8 @@ hipError_t launch_normals_inject(const GridBufs &g, const double *nrm_orig, Desc
 
 // ---------------------------------------------------------------- SPFH
 
-// 1/sqrt(x) and 1/x in double: hardware estimate plus two Newton steps
-// (relative error ~1e-16, far inside the bin-decision margins).
-__device__ __forceinline__ double rsqrt_nr(double x) {
-    double r = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * r, r, 1.0);
-    r = fma(0.5 * r, e, r);
-    e = fma(-x * r, r, 1.0);
-    return fma(0.5 * r, e, r);
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
+// rsqrt_nr, rcp_nr (lsr_internal.h): relative error ~1e-16, far inside the
+// bin-decision margins.
 
 // theta's bin edges theta_k = -pi + 2 pi k / 11 as values of the pseudo-angle
 // pa(x, y) = 1 - x / (|x| + |y|) for y >= +0 and x / (|x| + |y|) - 1 for y < 0

@@ -145,7 +145,9 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
                 }
         }
         double tr = H[0][0] + H[1][1] + H[2][2] + H[3][3] + H[4][4] + H[5][5];
-        // one FP64 division per column (the reciprocal of L[j][j]), products elsewhere
+        // one reciprocal square root per column (1 / L[j][j], hardware estimate and
+        // two Newton steps: this block runs on one thread per iteration, so its
+        // latency is the solve's), products elsewhere
         double L[6][6], il[6];
         bool okc = true;
 #pragma unroll
@@ -154,8 +156,7 @@ __device__ void gn_step(const CorrSrc &src, int64_t m, double mu, GncShared &sh)
 #pragma unroll
             for (int u = 0; u < j; ++u) d -= L[j][u] * L[j][u];
             okc = okc && d > 1e-12 * tr;
-            L[j][j] = sqrt(okc ? d : 1.0);
-            il[j] = 1.0 / L[j][j];
+            il[j] = rsqrt_nr(okc ? d : 1.0);
 #pragma unroll
             for (int i = j + 1; i < 6; ++i) {
                 double s = H[i][j];

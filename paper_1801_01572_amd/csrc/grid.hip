@@ -160,7 +160,11 @@ __global__ void k_grid_setup(Frag *frag, int nfrag, float r_cell) {
     F.gz = (int)(floor(ext[2] / (double)fc) + 1);
 }
 
-__global__ void __launch_bounds__(256) k_count(const Frag *frag, const Blk *blk, int32_t *cell_of_pt, int32_t *ccount) {
+// Cell of each point and its arrival rank in the cell (the count's atomic
+// return value; any order of arrival, since the rank fix below orders each
+// cell by original index).
+__global__ void __launch_bounds__(256) k_count(const Frag *frag, const Blk *blk, int32_t *cell_of_pt, int32_t *ccount,
+                                               int32_t *arrival) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     int i = b.start + threadIdx.x;
@@ -170,18 +174,17 @@ __global__ void __launch_bounds__(256) k_count(const Frag *frag, const Blk *blk,
     cx = min(max(cx, 0), F.gx - 1); cy = min(max(cy, 0), F.gy - 1); cz = min(max(cz, 0), F.gz - 1);
     int32_t gc = (int32_t)(F.cell_off + ((int64_t)cz * F.gy + cy) * F.gx + cx);
     cell_of_pt[F.off + i] = gc;
-    atomicAdd(&ccount[gc], 1);
+    arrival[F.off + i] = atomicAdd(&ccount[gc], 1);
 }
 
 __global__ void __launch_bounds__(256) k_scatter(const Frag *frag, const Blk *blk, const int32_t *cell_of_pt,
-                                                 int32_t *cursor, int32_t *tmp) {
+                                                 const int32_t *cstart, const int32_t *arrival, int32_t *tmp) {
     const Blk b = blk[blockIdx.x];
     const Frag &F = frag[b.frag];
     int i = b.start + threadIdx.x;
     if (i >= F.n) return;
     int64_t g = F.off + i;
-    int32_t slot = atomicAdd(&cursor[cell_of_pt[g]], 1);
-    tmp[slot] = (int32_t)g;
+    tmp[cstart[cell_of_pt[g]] + arrival[g]] = (int32_t)g;
 }
 
 __global__ void __launch_bounds__(256) k_rankfix(const Frag *frag, const Blk *blk, const int32_t *cell_of_pt,
@@ -217,12 +220,12 @@ hipError_t build_grids(GridBufs &g, float r_cell, hipStream_t s) {
     hipLaunchKernelGGL(k_bbox_init, dim3((g.nfrag + 63) / 64), dim3(64), 0, s, g.frag, g.nfrag);
     hipLaunchKernelGGL(k_bbox, dim3(g.nblk256), dim3(256), 0, s, g.frag, (const Blk *)g.blk256);
     hipLaunchKernelGGL(k_grid_setup, dim3((g.nfrag + 63) / 64), dim3(64), 0, s, g.frag, g.nfrag, r_cell);
+    // arrival ranks in cursor[0, ntot) (ncells >= ntot), the scan's scratch from cursor + ncells
     hipLaunchKernelGGL(k_count, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       g.cell_of_pt, g.ccount);
+                       g.cell_of_pt, g.ccount, g.cursor);
     if ((e = exclusive_scan_i32(g.ccount, g.cstart, g.ncells, g.cursor + g.ncells, s)) != hipSuccess) return e;
-    if ((e = copy<int32_t>(g.cursor, g.cstart, g.ncells, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
-                       (const int32_t *)g.cell_of_pt, g.cursor, g.tmp);
+                       (const int32_t *)g.cell_of_pt, (const int32_t *)g.cstart, (const int32_t *)g.cursor, g.tmp);
     hipLaunchKernelGGL(k_rankfix, dim3(g.nblk256), dim3(256), 0, s, (const Frag *)g.frag, (const Blk *)g.blk256,
                        (const int32_t *)g.cell_of_pt, (const int32_t *)g.cstart, (const int32_t *)g.ccount,
                        (const int32_t *)g.tmp, g.sp, g.snx, g.sny, g.snz, g.sorig);

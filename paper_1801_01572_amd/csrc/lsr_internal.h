@@ -75,6 +75,24 @@ __device__ __forceinline__ double pdist2(double xi, double yi, double zi, double
 // use the upper 32 bits of the output.
 constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
 
+// 1/sqrt(x) and 1/x in double: the hardware estimate plus two Newton steps
+// (relative error ~1e-16), a few instructions against the correctly rounded
+// library sequences.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    e = fma(-x * r, r, 1.0);
+    return fma(0.5 * r, e, r);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ uint32_t splitmix64_hi(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -141,7 +159,7 @@ struct GridBufs {              // built per batch by build_grids()
     int32_t *cell_of_pt;       // internal index -> linear cell (within fragment table)
     int32_t *cstart;           // ncells + 1: global sorted position of each cell
     int32_t *ccount;           // ncells
-    int32_t *cursor;           // ncells, scatter cursor
+    int32_t *cursor;           // ncells (>= ntot) + scan scratch: each point's arrival rank in its cell
     int32_t *tmp;              // ntot, unstable scatter
     float4 *sp;                // sorted coordinates (x, y, z, 0): one 16-byte load per candidate
     float *snx, *sny, *snz;    // sorted input normals
