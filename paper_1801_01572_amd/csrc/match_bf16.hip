@@ -370,7 +370,13 @@ __global__ void __launch_bounds__(256) k_pca(const Frag *frag, int nfrag, const 
             for (int o = 32; o > 0; o >>= 1) n2 += __shfl_xor(n2, o, 64);
             if (!(n2 > 0.f)) break;
             lam = sqrtf(n2);
-            v = w / lam;
+            const float vn = w / lam;
+            // stop once the direction moves by less than 1e-4 (the keys only
+            // order rows; any direction is correct)
+            float dv = (vn - v) * (vn - v);
+            for (int o = 32; o > 0; o >>= 1) dv += __shfl_xor(dv, o, 64);
+            v = vn;
+            if (dv < 1e-8f) break;
         }
         // deflate: cv -= lam v v^T
         for (int k = 0; k < 30; ++k) {
@@ -492,15 +498,20 @@ __global__ void __launch_bounds__(128) k_chunk_stats(const Frag *frag, const Blk
         for (int c = 0; c < 30; ++c) y[c] = bf2f(row[c]) + bf2f(row[32 + c]);
         return chi > -1.0e29f;
     };
+    // the lane's two rows, loaded once for both passes
+    float yr[2][30], hr[2];
+    bool vr[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) vr[u] = load(u, yr[u], hr[u]);
     float s[30];
 #pragma unroll
     for (int c = 0; c < 30; ++c) s[c] = 0.f;
     int nv = 0;
-    for (int u = 0; u < 2; ++u) {
-        float y[30], h;
-        if (!load(u, y, h)) continue;
 #pragma unroll
-        for (int c = 0; c < 30; ++c) s[c] += y[c];
+    for (int u = 0; u < 2; ++u) {
+        if (!vr[u]) continue;
+#pragma unroll
+        for (int c = 0; c < 30; ++c) s[c] += yr[u][c];
         ++nv;
     }
     for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o, 64);
@@ -518,9 +529,11 @@ __global__ void __launch_bounds__(128) k_chunk_stats(const Frag *frag, const Blk
     }
     float rho = 0.f, ym = 0.f, hm = 0.f;
     double del = -1.0e300;
+#pragma unroll
     for (int u = 0; u < 2; ++u) {
-        float y[30], h;
-        if (!load(u, y, h)) continue;
+        if (!vr[u]) continue;
+        const float *y = yr[u];
+        const float h = hr[u];
         float d2 = 0.f, n2f = 0.f;
         double n2 = 0.0;
 #pragma unroll
