@@ -808,7 +808,8 @@ constexpr float SQ_LO = 1.0f - 1.9073486328125e-6f;    // 1 - 2^-19
 // chunks one block can track (fragments up to 522,240 rows; beyond: no pruning).
 // 4080, not 4096: the chunk list then leaves the pruned screen's shared memory
 // at 40,952 bytes, so four blocks fit a CU (four wavefronts per SIMD, 128
-// VGPRs, a few spills outside the sweeps): 59.5 -> 57.1 ms on the benchmark
+// VGPRs, a few spills outside the sweeps): 59.5 -> 57.1 ms on the benchmark,
+// and the collect pass likewise 6.9 -> 5.9 ms
 constexpr int PR_NCH_MAX = 4080;
 
 template <int SW, int SQB, int CH>
@@ -1132,7 +1133,7 @@ __global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(4)
 // row's threshold goes to the row's list.  Fragments past PR_NCH_MAX chunks
 // are swept whole.
 template <int SW, int SQB, int CH>
-__global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(SW * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_screen_prc(const Frag *frag, const Blk *blk, int nblk, const uint16_t *pk, const uint16_t *cpk, const float4 *cst,
              const int32_t *rinv, const int32_t *fb_row, const int32_t *fb_cnt, const float *thr, int32_t *lst,
              int32_t *lst_cnt) {
