@@ -457,11 +457,11 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 // zero pad, the scale); three 16x16x4 f32 MFMAs add W (16 x 4) times C (4 x 48)
 // into the group's sums, the even bins in the first, the odd in the second.  A group spanning several rows takes one pass per
 // row, each with W masked to that row's points.  Only the float32 summation
-// order differs from a per-point loop.  Six wavefronts per SIMD (80 VGPRs, no
-// spill; four at the unconstrained 104) hide more of the candidate-row
-// gathers: 18.4 -> 17.4 ms at five, 17.1 -> 16.5 ms at six, on 256 pairs of
-// 50k-point fragments.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_fpfh(const Frag *frag, const Blk *blk, int nblk, GridView g,
+// order differs from a per-point loop.  Seven wavefronts per SIMD (72 VGPRs,
+// 24 bytes of spills; four at the unconstrained 104) hide more of the
+// candidate-row gathers: 18.4 -> 17.4 ms at five, 17.1 -> 16.5 ms at six,
+// 16.2 ms at seven, on 256 pairs of 50k-point fragments.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_fpfh(const Frag *frag, const Blk *blk, int nblk, GridView g,
                                               const int32_t *sorig, const uint4 *spfh, const int32_t *knb, double r2,
                                               float *Fout, int32_t *valid, PairState *ps) {
     __shared__ float red[4][16][49];                  // per wavefront: 16 points x 48 bins (+1 pad)
